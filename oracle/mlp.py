@@ -1,0 +1,81 @@
+"""FP64 multilayer perceptron (NumPy): the checker of the GPU surrogate's forward pass,
+backward pass and Adam update.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Network: 10 inputs -> 4 hidden layers of width 64 with GELU -> 1 output.  GELU is the exact
+form x * Phi(x) with Phi the standard normal CDF.  Weights W[l] have shape [fan_in, fan_out];
+a layer computes Y = X @ W + b.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy.special import erfc
+
+SIZES = (10, 64, 64, 64, 64, 1)
+
+
+def gelu(x):
+    # Phi(x) = erfc(-x / sqrt 2) / 2, free of cancellation for negative x
+    return 0.5 * x * erfc(-x / math.sqrt(2.0))
+
+
+def gelu_grad(x):
+    return 0.5 * erfc(-x / math.sqrt(2.0)) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+
+
+def init_params(seed=0, sizes=SIZES):
+    rng = np.random.default_rng(seed)
+    Ws, bs = [], []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        Ws.append(rng.normal(0.0, math.sqrt(2.0 / a), size=(a, b)))
+        bs.append(np.zeros(b))
+    return Ws, bs
+
+
+def forward(Ws, bs, X):
+    """Returns (output [n, 1], pre-activations list, activations list)."""
+    acts = [np.asarray(X, np.float64)]
+    pres = []
+    h = acts[0]
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        z = h @ W + b
+        pres.append(z)
+        h = gelu(z) if l < len(Ws) - 1 else z
+        acts.append(h)
+    return h, pres, acts
+
+
+def mse_loss(Ws, bs, X, Y):
+    out, _, _ = forward(Ws, bs, X)
+    r = out[:, 0] - np.asarray(Y, np.float64)
+    return float(np.mean(r * r))
+
+
+def backward(Ws, bs, X, Y):
+    """Gradients of mean squared error over the batch: (dW list, db list, loss)."""
+    out, pres, acts = forward(Ws, bs, X)
+    n = out.shape[0]
+    r = out[:, 0] - np.asarray(Y, np.float64)
+    loss = float(np.mean(r * r))
+    g = (2.0 / n) * r[:, None]
+    dWs = [None] * len(Ws)
+    dbs = [None] * len(Ws)
+    for l in range(len(Ws) - 1, -1, -1):
+        dWs[l] = acts[l].T @ g
+        dbs[l] = g.sum(0)
+        if l > 0:
+            g = (g @ Ws[l].T) * gelu_grad(pres[l - 1])
+    return dWs, dbs, loss
+
+
+def adam_step(p, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba) with bias correction; returns (p, m, v)."""
+    m = b1 * m + (1.0 - b1) * grad
+    v = b2 * v + (1.0 - b2) * grad * grad
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

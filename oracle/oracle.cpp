@@ -1,0 +1,823 @@
+// FP64 reference implementation ("oracle") of the backward generalized-ray path tracer.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or calls this
+// file; only the test-suite, the smoke check and the CPU baseline leg of the benchmark do.
+// It shares no source with the HIP path: its own counter RNG, its own BVH, its own
+// intersection routine, its own scattering kernels, all in double precision, written for
+// clarity rather than speed.
+//
+// Paper: "A Generalized Ray Formulation for Wave-Optics Rendering" (arXiv 2303.15762).
+// Each function names the section / equation it follows.  Readings of passages the paper
+// leaves open are listed in the design notes and repeated next to the code that takes them.
+//
+// Parity status: every component below is pinned by the CPU test-suite except where a
+// function header says "parity unpinned".
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------------------------------
+// Counter-based RNG: Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11).  Round function: two 32x32->64 multiplies of counter
+// words 0 and 2 by the published multipliers; the high halves are xored with the other counter
+// words and the key; the key is bumped by the published Weyl constants between rounds.
+// ------------------------------------------------------------------------------------------
+struct U4 { uint32_t v[4]; };
+
+U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+    const uint64_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = M0 * (uint64_t)x0;
+        uint64_t p1 = M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ x1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ x3 ^ k1;
+        uint32_t n3 = lo0;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    return U4{{x0, x1, x2, x3}};
+}
+
+// 24-bit uniform in [0, 1): exactly representable in float and double.
+inline double unif(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+// Standard normal pair by the Box-Muller transform of two uniforms.
+inline void box_muller(double u1, double u2, double& z1, double& z2) {
+    double r = std::sqrt(-2.0 * std::log(1.0 - u1));
+    double ph = 2.0 * kPi * u2;
+    z1 = r * std::cos(ph);
+    z2 = r * std::sin(ph);
+}
+
+// Random-stream layout.  Counter = (path id low, path id high, interaction index, stream).
+enum { STREAM_SOURCE = 0, STREAM_NEE = 1, STREAM_SCATTER = 2 };
+
+U4 draw(uint64_t pid, uint32_t depth, uint32_t stream, uint64_t seed) {
+    return philox((uint32_t)pid, (uint32_t)(pid >> 32), depth, stream, (uint32_t)seed,
+                  (uint32_t)(seed >> 32));
+}
+
+// ------------------------------------------------------------------------------------------
+// Small vector helpers.
+// ------------------------------------------------------------------------------------------
+struct V3 { double x, y, z; };
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 unit(V3 a) { return (1.0 / norm(a)) * a; }
+inline V3 ld3(const double* p) { return {p[0], p[1], p[2]}; }
+
+// Self-intersection offset (metres): a fixed relative tolerance of the ray origin's size.
+inline double t_eps(V3 o) {
+    double m = std::max(std::fabs(o.x), std::max(std::fabs(o.y), std::fabs(o.z)));
+    return 1e-7 * (1.0 + m);
+}
+
+}  // namespace
+
+// ==========================================================================================
+// C structures of the oracle's interface (its own; the product library defines its own).
+// ==========================================================================================
+extern "C" {
+
+typedef struct {
+    int32_t kind;               // 0 smooth, 1 gaussian random rough, 2 sinusoidal grating
+    double height_um;           // rough: RMS height; grating: amplitude A
+    double length_um;           // rough: 1/e correlation length; grating: pitch
+    double gdir[3];             // grating vector direction (world)
+    double reflectance;
+} or_material;
+
+typedef struct {
+    double origin[3], axis_u[3], axis_v[3], dir[3];
+    int32_t width, height;
+    double pitch_m, sigma_m;
+} or_sensor;
+
+typedef struct {
+    int32_t kind;               // 0 plane wave, 1 gaussian-schell area emitter
+    double dir[3], pos[3], eu[3], ev[3];
+    double rc_um, power;
+} or_source;
+
+typedef struct {
+    int64_t spp_begin, spp_count;
+    double spp_norm;            // contributions are divided by this (total samples per pixel)
+    int32_t max_depth;
+    int32_t rr_enable;
+    uint32_t rr_threshold24;    // survive iff (draw >> 8) < threshold
+    double rr_p;
+    uint64_t seed;
+    int32_t use_bvh;            // 0: brute-force closest hit
+    int32_t n_threads;
+} or_opts;
+
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------------------------------------------------
+// Scattering of a curvature-free generalized ray by one surface patch (Sec. "Interaction
+// Kernels": reflection, sinusoidal grating, rough surface).  The windowed diffraction
+// density p_w over the outgoing tangential wavevector is the squared Fourier transform of
+// the window times the surface phase screen, normalised by the window energy.  With the
+// Gaussian window of the generalized ray it becomes a Gaussian mixture (see design notes).
+// ------------------------------------------------------------------------------------------
+
+// Bivariate normal density N(x; 0, S), S = [[a, c], [c, b]].
+double gauss2(double x, double y, double a, double b, double c) {
+    double det = a * b - c * c;
+    double q = (b * x * x - 2.0 * c * x * y + a * y * y) / det;
+    return std::exp(-0.5 * q) / (2.0 * kPi * std::sqrt(det));
+}
+
+// Bessel function of the first kind of integer order (library primitive; J_{-n} = (-1)^n J_n).
+double besselj(int n, double x) {
+    int an = std::abs(n);
+    double v = (x < 0.0) ? ((an & 1) ? -std::cyl_bessel_j((double)an, -x)
+                                     : std::cyl_bessel_j((double)an, -x))
+                         : std::cyl_bessel_j((double)an, x);
+    if (n < 0 && (an & 1)) v = -v;
+    return v;
+}
+
+struct Mat {
+    int kind; double h, L, refl; V3 gdir;
+};
+
+// p_w(k_i,t -> k_o,t), a density over the outgoing tangential wavevector (um^2).
+// kit, kot: tangential wavevectors in the material frame (um^-1); k = 2 pi / lambda;
+// (sxx, syy, sxy): intensity footprint covariance of the window on the surface (um^2);
+// (gx, gy): grating direction in the frame.
+double pw_eval(const Mat& m, double k, double kix, double kiy, double kox, double koy,
+               double sxx, double syy, double sxy, double gx, double gy) {
+    double ni = (kix * kix + kiy * kiy) / (k * k);
+    double no = (kox * kox + koy * koy) / (k * k);
+    if (ni >= 1.0 || no >= 1.0) return 0.0;
+    double ci = std::sqrt(1.0 - ni), co = std::sqrt(1.0 - no);
+    double qz = k * (ci + co);                       // normal wavevector transfer (reflection)
+    double kx = kox - kix, ky = koy - kiy;            // tangential transfer kappa
+    // Window spectrum covariance: the amplitude window exp(-x^T S^-1 x / 4) has a squared
+    // Fourier transform with covariance S^-1 / 4.
+    double det = sxx * syy - sxy * sxy;
+    double a = 0.25 * syy / det, b = 0.25 * sxx / det, c = -0.25 * sxy / det;
+    if (m.kind == 0) {
+        return m.refl * gauss2(kx, ky, a, b, c);
+    }
+    if (m.kind == 2) {
+        // Phase screen h(x) = A sin(K g.x): Jacobi-Anger expansion into orders j with
+        // weights J_j(q_z A)^2 centred on kappa = -j K g (grating equation).
+        double K = 2.0 * kPi / m.L;
+        double mm = qz * m.h;
+        int J = (int)std::ceil(std::fabs(mm)) + 40;
+        double s = 0.0;
+        for (int j = -J; j <= J; ++j) {
+            double bj = besselj(j, mm);
+            s += bj * bj * gauss2(kx + j * K * gx, ky + j * K * gy, a, b, c);
+        }
+        return m.refl * s;
+    }
+    // Gaussian random surface, RMS s, autocorrelation exp(-tau^2 / l^2), ensemble average:
+    // exp(-g (1 - C)) expanded as a Poisson series in g = (q_z s)^2; term n carries the
+    // window spectrum convolved with an isotropic Gaussian of variance 2 n / l^2.
+    double g = qz * qz * m.h * m.h;
+    double s = 0.0;
+    if (g == 0.0) return m.refl * gauss2(kx, ky, a, b, c);
+    int M = (int)std::ceil(g + 20.0 * std::sqrt(g) + 40.0);
+    double lg = std::log(g);
+    for (int n = 0; n <= M; ++n) {
+        double lw = -g + n * lg - std::lgamma((double)n + 1.0);
+        double w = std::exp(lw);
+        if (w == 0.0) continue;
+        double add = 2.0 * n / (m.L * m.L);
+        s += w * gauss2(kx, ky, a + add, b + add, c);
+    }
+    return m.refl * s;
+}
+
+// Continuation sampling from the unwindowed kernel f_inf (the delta-lobe limit of p_w),
+// Sec. "Interaction Kernels" (grating orders, rough-surface Monte Carlo) with the incident
+// wave taken along the generalized ray's own travel direction (time reversal = wavevector
+// reversal; the kernels used here are reciprocal).  Returns false when the path ends.
+bool sample_finf(const Mat& m, double k, double kix, double kiy, double ci, double u0, double u1,
+                 double u2, double gx, double gy, double& kox, double& koy, double& weight,
+                 int& evanescent) {
+    evanescent = 0;
+    if (m.kind == 0) {
+        kox = kix; koy = kiy; weight = m.refl;
+        return true;
+    }
+    if (m.kind == 2) {
+        double K = 2.0 * kPi / m.L;
+        int J = (int)std::ceil(2.0 * k / K) + 2;
+        std::vector<double> w;
+        std::vector<int> js;
+        double W = 0.0;
+        for (int j = -J; j <= J; ++j) {
+            double ox = kix - j * K * gx, oy = kiy - j * K * gy;
+            double no = (ox * ox + oy * oy) / (k * k);
+            if (no >= 1.0) continue;                  // evanescent orders are dropped
+            double mj = k * m.h * (ci + std::sqrt(1.0 - no));
+            double bj = besselj(j, mj);
+            w.push_back(bj * bj);
+            js.push_back(j);
+            W += bj * bj;
+        }
+        if (W <= 0.0) { evanescent = 1; return false; }
+        double target = u0 * W, c = 0.0;
+        int pick = js.back();
+        for (size_t i = 0; i < w.size(); ++i) {
+            c += w[i];
+            if (target < c) { pick = js[i]; break; }
+        }
+        kox = kix - pick * K * gx;
+        koy = kiy - pick * K * gy;
+        weight = m.refl * W;
+        return true;
+    }
+    // rough: term n ~ Poisson(g) at the specular normal transfer, then kappa ~ N(0, 2n/l^2 I)
+    double g = 4.0 * k * k * ci * ci * m.h * m.h;
+    int n = 0;
+    if (g > 0.0) {
+        int M = (int)std::ceil(g + 20.0 * std::sqrt(g) + 40.0);
+        double lg = std::log(g), c = 0.0;
+        n = M;
+        for (int i = 0; i <= M; ++i) {
+            c += std::exp(-g + i * lg - std::lgamma((double)i + 1.0));
+            if (u0 < c) { n = i; break; }
+        }
+    }
+    double z1, z2;
+    box_muller(u1, u2, z1, z2);
+    double sd = std::sqrt(2.0 * n) / m.L;
+    kox = kix + sd * z1;
+    koy = kiy + sd * z2;
+    if ((kox * kox + koy * koy) >= k * k) { evanescent = 1; return false; }
+    weight = m.refl;
+    return true;
+}
+
+// ------------------------------------------------------------------------------------------
+// Geometry: FP64 Moller-Trumbore intersection, a median-split binary BVH, and brute force.
+// Closest hit: smallest t > eps; equal t resolved to the lower triangle index.
+// ------------------------------------------------------------------------------------------
+struct Tri { V3 p0, p1, p2; };
+
+bool isect_tri(const Tri& T, V3 o, V3 d, double tmin, double& t, double& u, double& v) {
+    V3 e1 = T.p1 - T.p0, e2 = T.p2 - T.p0;
+    V3 p = cross(d, e2);
+    double det = dot(e1, p);
+    if (det == 0.0) return false;
+    double inv = 1.0 / det;
+    V3 s = o - T.p0;
+    u = dot(s, p) * inv;
+    if (u < 0.0 || u > 1.0) return false;
+    V3 q = cross(s, e1);
+    v = dot(d, q) * inv;
+    if (v < 0.0 || u + v > 1.0) return false;
+    t = dot(e2, q) * inv;
+    return t > tmin;
+}
+
+struct Node { V3 lo, hi; int left, right, first, count; };
+
+struct SceneO {
+    std::vector<Tri> tris;
+    std::vector<V3> vn;            // per-vertex normals (3 per triangle); zero = use geometric
+    std::vector<int> mat;
+    std::vector<Mat> mats;
+    std::vector<Node> nodes;
+    std::vector<int> order;        // triangle indices referenced by leaves
+};
+
+void tri_bounds(const Tri& T, V3& lo, V3& hi) {
+    lo = {std::min({T.p0.x, T.p1.x, T.p2.x}), std::min({T.p0.y, T.p1.y, T.p2.y}),
+          std::min({T.p0.z, T.p1.z, T.p2.z})};
+    hi = {std::max({T.p0.x, T.p1.x, T.p2.x}), std::max({T.p0.y, T.p1.y, T.p2.y}),
+          std::max({T.p0.z, T.p1.z, T.p2.z})};
+}
+
+int build_rec(SceneO& S, int first, int count) {
+    Node nd;
+    V3 lo{1e300, 1e300, 1e300}, hi{-1e300, -1e300, -1e300};
+    for (int i = first; i < first + count; ++i) {
+        V3 a, b;
+        tri_bounds(S.tris[S.order[i]], a, b);
+        lo = {std::min(lo.x, a.x), std::min(lo.y, a.y), std::min(lo.z, a.z)};
+        hi = {std::max(hi.x, b.x), std::max(hi.y, b.y), std::max(hi.z, b.z)};
+    }
+    nd.lo = lo; nd.hi = hi; nd.left = nd.right = -1; nd.first = first; nd.count = count;
+    int id = (int)S.nodes.size();
+    S.nodes.push_back(nd);
+    if (count <= 4) return id;
+    V3 ext = hi - lo;
+    int axis = (ext.x >= ext.y && ext.x >= ext.z) ? 0 : (ext.y >= ext.z ? 1 : 2);
+    auto cen = [&](int t) {
+        const Tri& T = S.tris[t];
+        V3 c = (1.0 / 3.0) * (T.p0 + T.p1 + T.p2);
+        return axis == 0 ? c.x : (axis == 1 ? c.y : c.z);
+    };
+    int mid = first + count / 2;
+    std::nth_element(S.order.begin() + first, S.order.begin() + mid,
+                     S.order.begin() + first + count,
+                     [&](int a, int b) { return cen(a) < cen(b) || (cen(a) == cen(b) && a < b); });
+    int l = build_rec(S, first, mid - first);
+    int r = build_rec(S, mid, first + count - mid);
+    S.nodes[id].left = l;
+    S.nodes[id].right = r;
+    S.nodes[id].count = 0;
+    return id;
+}
+
+// Slab test; returns the entry distance in tnear.
+bool box_hit(const Node& n, V3 o, V3 d, double tmax, double& tnear) {
+    double t0 = 0.0, t1 = tmax;
+    const double oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+    const double lo[3] = {n.lo.x, n.lo.y, n.lo.z}, hi[3] = {n.hi.x, n.hi.y, n.hi.z};
+    for (int a = 0; a < 3; ++a) {
+        if (dd[a] == 0.0) {
+            if (oo[a] < lo[a] || oo[a] > hi[a]) return false;
+            continue;
+        }
+        double inv = 1.0 / dd[a];
+        double ta = (lo[a] - oo[a]) * inv, tb = (hi[a] - oo[a]) * inv;
+        if (ta > tb) std::swap(ta, tb);
+        t0 = std::max(t0, ta);
+        t1 = std::min(t1, tb);
+        if (t0 > t1) return false;
+    }
+    tnear = t0;
+    return true;
+}
+
+struct Hit { int tri; double t, u, v; };
+
+// Closest hit along o + t d, t in (tmin, tmax).  any=true stops at the first hit found.
+bool trace_ray(const SceneO& S, V3 o, V3 d, double tmin, double tmax, bool use_bvh, bool any,
+               Hit& h) {
+    h.tri = -1;
+    h.t = tmax;
+    auto consider = [&](int ti) {
+        double t, u, v;
+        if (isect_tri(S.tris[ti], o, d, tmin, t, u, v) && t < tmax) {
+            if (t < h.t || (t == h.t && ti < h.tri)) { h.t = t; h.u = u; h.v = v; h.tri = ti; }
+        }
+    };
+    if (!use_bvh) {
+        for (int i = 0; i < (int)S.tris.size(); ++i) {
+            consider(i);
+            if (any && h.tri >= 0) return true;
+        }
+        return h.tri >= 0;
+    }
+    std::vector<int> stack;
+    stack.reserve(128);
+    stack.push_back(0);
+    while (!stack.empty()) {
+        int ni = stack.back();
+        stack.pop_back();
+        const Node& n = S.nodes[ni];
+        double tn;
+        if (!box_hit(n, o, d, h.t, tn)) continue;
+        if (n.left < 0) {
+            for (int i = n.first; i < n.first + n.count; ++i) consider(S.order[i]);
+            if (any && h.tri >= 0) return true;
+        } else {
+            stack.push_back(n.left);
+            stack.push_back(n.right);
+        }
+    }
+    return h.tri >= 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// One backward path (Algorithm 1 specialised to the interactive assumption of Sec.
+// "Interactive Rendering": rays are traced as rays, the generalized-ray parameters are
+// carried along; measurement by next-event estimation at every interaction).
+// ------------------------------------------------------------------------------------------
+struct Stats { uint64_t segments = 0, shadow = 0, evanescent = 0, backfacing = 0; };
+
+struct Ctx {
+    const SceneO* S;
+    const or_sensor* sen;
+    const or_source* src;
+    int nsrc;
+    const double* lambdas;
+    int nl;
+    const or_opts* op;
+};
+
+// Build the tangent frame of the interaction: x axis = grating direction (gratings) or the
+// projection of the travel direction (otherwise).
+void make_frame(const Mat& m, V3 n, V3 d, V3& xa, V3& ya) {
+    V3 t;
+    if (m.kind == 2) {
+        t = m.gdir - dot(m.gdir, n) * n;
+        if (norm(t) > 1e-9) { xa = unit(t); ya = cross(n, xa); return; }
+    }
+    t = d - dot(d, n) * n;
+    if (norm(t) > 1e-12) {
+        xa = unit(t);
+    } else {
+        V3 a = std::fabs(n.x) < 0.9 ? V3{1, 0, 0} : V3{0, 1, 0};
+        xa = unit(cross(n, a));
+    }
+    ya = cross(n, xa);
+}
+
+double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
+    const SceneO& S = *C.S;
+    const or_sensor& sen = *C.sen;
+    const or_opts& op = *C.op;
+    const uint64_t W = (uint64_t)sen.width, H = (uint64_t)sen.height;
+    const uint64_t pid = ((((uint64_t)s * H) + (uint64_t)py) * W + (uint64_t)px) * (uint64_t)C.nl +
+                         (uint64_t)w;
+    const double lam = C.lambdas[w];
+    const double k = 2.0 * kPi / lam;                     // um^-1
+
+    // Sourcing (Sec. "Interactive Rendering", implementation details): mean position uniform
+    // on the pixel, mean direction the sensor axis, beta^2 / 2 = sigma^2, rho = 0, alpha = 1.
+    U4 r0 = draw(pid, 0, STREAM_SOURCE, op.seed);
+    V3 o = ld3(sen.origin) + ((px + unif(r0.v[0])) * sen.pitch_m) * ld3(sen.axis_u) +
+           ((py + unif(r0.v[1])) * sen.pitch_m) * ld3(sen.axis_v);
+    V3 d = ld3(sen.dir);
+    double sig_um = sen.sigma_m * 1e6;
+    double beta2 = 2.0 * sig_um * sig_um;
+    double rho = 0.0;
+    double alpha = 1.0;
+    double contrib = 0.0;
+
+    for (int depth = 0; depth < op.max_depth; ++depth) {
+        st.segments++;
+        Hit h;
+        if (!trace_ray(S, o, d, t_eps(o), 1e300, op.use_bvh != 0, false, h)) break;
+        // Free-space propagation of the generalized ray over the hit distance
+        // (eq. K_free_space_propagation), with zbar = z / |k0| and the pre-update beta, rho.
+        double z = h.t * 1e6;
+        double zb = z / k;
+        double rho_new = rho + zb * (1.0 + rho * rho) / beta2;
+        double beta2_new = beta2 + zb * (2.0 * rho + zb * (1.0 + rho * rho) / beta2);
+        rho = rho_new;
+        beta2 = beta2_new;
+        V3 P = o + h.t * d;
+        const Tri& T = S.tris[h.tri];
+        V3 ng = unit(cross(T.p1 - T.p0, T.p2 - T.p0));
+        V3 ns = ng;
+        {
+            V3 n0 = S.vn[3 * h.tri], n1 = S.vn[3 * h.tri + 1], n2 = S.vn[3 * h.tri + 2];
+            if (dot(n0, n0) > 0.0 && dot(n1, n1) > 0.0 && dot(n2, n2) > 0.0)
+                ns = unit((1.0 - h.u - h.v) * n0 + h.u * n1 + h.v * n2);
+        }
+        if (dot(d, ng) > 0.0) ng = -1.0 * ng;
+        if (dot(ns, ng) < 0.0) ns = -1.0 * ns;
+        double ci = -dot(d, ns);
+        if (ci <= 0.0) { st.backfacing++; break; }
+        const Mat& m = S.mats[S.mat[h.tri]];
+        V3 xa, ya;
+        make_frame(m, ns, d, xa, ya);
+        // Footprint of the generalized ray on the surface: intensity variance beta^2/2
+        // across the beam, stretched by 1/cos along the plane of incidence.
+        double sr2 = 0.5 * beta2;
+        double dx = dot(d, xa), dy = dot(d, ya);
+        double sxx = sr2 * (1.0 + dx * dx / (ci * ci));
+        double syy = sr2 * (1.0 + dy * dy / (ci * ci));
+        double sxy = sr2 * (dx * dy / (ci * ci));
+        // The frame's x axis is the grating direction, so the grating vector is (1, 0).
+        const double gx = 1.0, gy = 0.0;
+
+        // Measurement by next-event estimation (measurement operator, eq.
+        // measurement_operator, with the ensemble-averaged source WDF).
+        U4 rn = draw(pid, depth, STREAM_NEE, op.seed);
+        if (C.nsrc > 0) {
+            int si = std::min((int)(unif(rn.v[0]) * C.nsrc), C.nsrc - 1);
+            const or_source& L = C.src[si];
+            V3 om{0, 0, 0};
+            bool ok = false;
+            double tmax = 1e300;
+            if (L.kind == 0) {
+                om = unit(ld3(L.dir));
+                ok = true;
+            } else {
+                double z1, z2;
+                box_muller(unif(rn.v[1]), unif(rn.v[2]), z1, z2);
+                double du = z1 / L.rc_um, dv = z2 / L.rc_um;      // um^-1
+                double tt = (du * du + dv * dv) / (k * k);
+                if (tt < 1.0) {
+                    V3 ax = unit(ld3(L.dir));
+                    V3 eu = ld3(L.eu), ev = ld3(L.ev);
+                    double lu = norm(eu), lv = norm(ev);
+                    V3 bu = (1.0 / lu) * eu, bv = (1.0 / lv) * ev;
+                    om = (du / k) * bu + (dv / k) * bv + std::sqrt(1.0 - tt) * ax;
+                    double den = dot(om, ax);
+                    double te = dot(ld3(L.pos) - P, ax) / (-den);
+                    if (te > t_eps(P)) {
+                        V3 Q = P - te * om;
+                        double a = dot(Q - ld3(L.pos), bu) / lu, b = dot(Q - ld3(L.pos), bv) / lv;
+                        if (std::fabs(a) <= 1.0 && std::fabs(b) <= 1.0) { ok = true; tmax = te; }
+                    }
+                }
+            }
+            if (ok && dot(om, ng) < 0.0 && dot(om, ns) < 0.0) {
+                st.shadow++;
+                Hit hs;
+                bool occ = trace_ray(S, P, -1.0 * om, t_eps(P), tmax, op.use_bvh != 0, true, hs);
+                if (!occ) {
+                    double kix = k * dot(om, xa), kiy = k * dot(om, ya);
+                    double kox = -k * dx, koy = -k * dy;
+                    double p = pw_eval(m, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
+                    contrib += alpha * L.power * p * (double)C.nsrc;
+                }
+            }
+        }
+        if (depth + 1 >= op.max_depth) break;
+
+        // Light-matter interaction: sample the continuation generalized ray.
+        U4 rs = draw(pid, depth, STREAM_SCATTER, op.seed);
+        double kix = k * dx, kiy = k * dy, kox, koy, wgt;
+        int ev;
+        if (!sample_finf(m, k, kix, kiy, ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), gx, gy,
+                         kox, koy, wgt, ev)) {
+            st.evanescent += ev;
+            break;
+        }
+        alpha *= wgt;
+        if (op.rr_enable && depth + 1 >= 2) {
+            if (!((rs.v[3] >> 8) < op.rr_threshold24)) break;
+            alpha /= op.rr_p;
+        }
+        double kn = std::sqrt(std::max(0.0, 1.0 - (kox * kox + koy * koy) / (k * k)));
+        d = (kox / k) * xa + (koy / k) * ya + kn * ns;
+        d = unit(d);
+        o = P;
+    }
+    return contrib;
+}
+
+}  // namespace
+
+// ==========================================================================================
+// Exported entry points (ctypes).
+// ==========================================================================================
+extern "C" {
+
+void or_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    U4 r = philox(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+    std::memcpy(out, r.v, 16);
+}
+
+void or_philox_batch(const uint32_t* ctr, int64_t n, const uint32_t* key, uint32_t* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        U4 r = philox(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], key[0], key[1]);
+        std::memcpy(out + 4 * i, r.v, 16);
+    }
+}
+
+double or_besselj(int n, double x) { return besselj(n, x); }
+
+// Free-space propagation of the generalized-ray parameters (eq. K_free_space_propagation):
+// beta^2 -> beta^2 + zbar (2 rho + zbar (1 + rho^2) / beta^2), rho -> rho + zbar (1 + rho^2) /
+// beta^2 with zbar = z / |k0|; z in um, k in um^-1, beta^2 in um^2.  out = (beta^2, rho).
+void or_propagate(double beta2, double rho, double z_um, double k, double* out) {
+    double zb = z_um / k;
+    out[1] = rho + zb * (1.0 + rho * rho) / beta2;
+    out[0] = beta2 + zb * (2.0 * rho + zb * (1.0 + rho * rho) / beta2);
+}
+
+// p_w for one query; material given by its fields.
+double or_pw(int kind, double h, double L, double refl, double k, double kix, double kiy,
+             double kox, double koy, double sxx, double syy, double sxy, double gx, double gy) {
+    Mat m{kind, h, L, refl, {1, 0, 0}};
+    return pw_eval(m, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
+}
+
+void or_pw_batch(const double* q, int64_t n, double* out) {
+    // q rows: kind, h, L, refl, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy
+    for (int64_t i = 0; i < n; ++i) {
+        const double* r = q + 14 * i;
+        Mat m{(int)r[0], r[1], r[2], r[3], {1, 0, 0}};
+        out[i] = pw_eval(m, r[4], r[5], r[6], r[7], r[8], r[9], r[10], r[11], r[12], r[13]);
+    }
+}
+
+// Continuation sample; returns 1 when a direction was produced.
+int or_sample(int kind, double h, double L, double refl, double k, double kix, double kiy,
+              double ci, double u0, double u1, double u2, double gx, double gy, double* out3) {
+    Mat m{kind, h, L, refl, {1, 0, 0}};
+    double kox = 0, koy = 0, w = 0;
+    int ev = 0;
+    bool ok = sample_finf(m, k, kix, kiy, ci, u0, u1, u2, gx, gy, kox, koy, w, ev);
+    out3[0] = kox; out3[1] = koy; out3[2] = w;
+    return ok ? 1 : 0;
+}
+
+void* or_scene_create(const double* verts, int64_t nv, const double* normals,
+                      const int32_t* tris, int64_t nt, const int32_t* tri_mat,
+                      const or_material* mats, int32_t nm) {
+    SceneO* S = new SceneO();
+    S->tris.resize(nt);
+    S->vn.assign(3 * nt, V3{0, 0, 0});
+    S->mat.resize(nt);
+    for (int64_t i = 0; i < nt; ++i) {
+        int a = tris[3 * i], b = tris[3 * i + 1], c = tris[3 * i + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv) { delete S; return nullptr; }
+        S->tris[i] = Tri{ld3(verts + 3 * a), ld3(verts + 3 * b), ld3(verts + 3 * c)};
+        if (normals) {
+            S->vn[3 * i] = ld3(normals + 3 * a);
+            S->vn[3 * i + 1] = ld3(normals + 3 * b);
+            S->vn[3 * i + 2] = ld3(normals + 3 * c);
+        }
+        S->mat[i] = tri_mat[i];
+        if (tri_mat[i] < 0 || tri_mat[i] >= nm) { delete S; return nullptr; }
+    }
+    for (int i = 0; i < nm; ++i) {
+        const or_material& M = mats[i];
+        V3 g = ld3(M.gdir);
+        if (M.kind == 2) g = unit(g);
+        S->mats.push_back(Mat{M.kind, M.height_um, M.length_um, M.reflectance, g});
+    }
+    S->order.resize(nt);
+    for (int64_t i = 0; i < nt; ++i) S->order[i] = (int)i;
+    if (nt > 0) build_rec(*S, 0, (int)nt);
+    return S;
+}
+
+void or_scene_destroy(void* s) { delete (SceneO*)s; }
+
+// Closest hit for a batch of rays (tests).  rays: [n][6] (origin, direction).  out: [n][4]
+// (triangle, t, u, v); triangle = -1 on a miss.  tmin < 0 selects the default offset.
+void or_intersect(void* s, const double* rays, int64_t n, double tmin, int use_bvh, double* out) {
+    const SceneO& S = *(SceneO*)s;
+    for (int64_t i = 0; i < n; ++i) {
+        V3 o = ld3(rays + 6 * i), d = ld3(rays + 6 * i + 3);
+        Hit h;
+        double tm = tmin < 0 ? t_eps(o) : tmin;
+        bool hit = trace_ray(S, o, d, tm, 1e300, use_bvh != 0, false, h);
+        out[4 * i] = hit ? h.tri : -1;
+        out[4 * i + 1] = hit ? h.t : 0;
+        out[4 * i + 2] = hit ? h.u : 0;
+        out[4 * i + 3] = hit ? h.v : 0;
+    }
+}
+
+// Render.  pixels: optional list of (x, y) pairs (npix of them); when null, every pixel of
+// the sensor in row-major order.  image: [nl][npix].  paths (optional):
+// [spp_count][npix][nl] per-path contributions (already divided by spp_norm).
+// stats: [segments, shadow rays, evanescent kills, backfacing kills].
+int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
+             const double* lambdas, int32_t nl, const or_opts* op, const int32_t* pixels,
+             int64_t npix, double* image, double* paths, uint64_t* stats) {
+    if (!s || !sen || !op || nl <= 0 || op->spp_count < 0 || op->max_depth < 0) return -1;
+    const SceneO* S = (const SceneO*)s;
+    if (!pixels) npix = (int64_t)sen->width * sen->height;
+    Ctx C{S, sen, src, nsrc, lambdas, nl, op};
+    int nt = op->n_threads > 0 ? op->n_threads : (int)std::thread::hardware_concurrency();
+    nt = std::max(1, nt);
+    std::atomic<int64_t> next(0);
+    std::vector<Stats> sts(nt);
+    auto work = [&](int tid) {
+        Stats& st = sts[tid];
+        for (;;) {
+            int64_t p = next.fetch_add(1);
+            if (p >= npix) break;
+            int px, py;
+            if (pixels) { px = pixels[2 * p]; py = pixels[2 * p + 1]; }
+            else { px = (int)(p % sen->width); py = (int)(p / sen->width); }
+            for (int w = 0; w < nl; ++w) {
+                double acc = 0.0;
+                for (int64_t sl = 0; sl < op->spp_count; ++sl) {
+                    double c = trace_path(C, px, py, op->spp_begin + sl, w, st) / op->spp_norm;
+                    if (paths) paths[(sl * npix + p) * nl + w] = c;
+                    acc += c;
+                }
+                image[(int64_t)w * npix + p] = acc;
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int i = 0; i < nt; ++i) th.emplace_back(work, i);
+    for (auto& t : th) t.join();
+    uint64_t tot[4] = {0, 0, 0, 0};
+    for (auto& st : sts) {
+        tot[0] += st.segments; tot[1] += st.shadow; tot[2] += st.evanescent; tot[3] += st.backfacing;
+    }
+    if (stats) std::memcpy(stats, tot, sizeof(tot));
+    return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Coherent measurement of mutually coherent emitters (Sec. "Linearity of Generalized Rays",
+// two-point interference, and "Numeric Validation", Rayleigh-Sommerfeld diffraction).
+//
+// Field at a sensor point X (um, x along the row, y across it), z = distance to the aperture
+// plane:
+//   points: U = sum_e exp(i k L_e) / L_e,   L_e = |X - s_e| (3-D spherical waves)
+//   slits : U = sum_e c_e (i k z / 2) H1(k rho_e) / rho_e, the 2-D Rayleigh-Sommerfeld
+//           first-kind kernel of a y-invariant aperture, integrated with Gauss-Legendre nodes
+//           (positions xs, weights ws) over each slit under normal plane-wave illumination.
+// A detection state centred at r0 with intensity standard deviation sigma, integrated over
+// all mean wavevectors, measures |U|^2 averaged over the Gaussian N(r0, sigma^2) (the
+// spatial marginal of the coherent state).
+// ------------------------------------------------------------------------------------------
+typedef struct {
+    int32_t kind;          // 0 points, 1 slits
+    int32_t n_nodes;       // points: number of emitters; slits: total quadrature nodes
+    const double* xs;      // node x positions (um)
+    const double* ws;      // node weights (slits) / ignored (points)
+    double z_um, lambda_um;
+    int32_t width, height;
+    double pitch_um, sigma_um;
+    int64_t spp;
+    uint64_t seed;
+} or_coherent;
+
+static std::complex<double> field_at(const or_coherent& c, double X, double Y) {
+    const double k = 2.0 * kPi / c.lambda_um;
+    std::complex<double> U(0.0, 0.0);
+    for (int e = 0; e < c.n_nodes; ++e) {
+        double dx = X - c.xs[e];
+        if (c.kind == 0) {
+            double L = std::sqrt(c.z_um * c.z_um + dx * dx + Y * Y);
+            U += std::polar(1.0 / L, k * L);
+        } else {
+            double rho = std::sqrt(c.z_um * c.z_um + dx * dx);
+            double kr = k * rho;
+            std::complex<double> H1(std::cyl_bessel_j(1.0, kr), std::cyl_neumann(1.0, kr));
+            U += c.ws[e] * std::complex<double>(0.0, 0.5 * k * c.z_um) * H1 / rho;
+        }
+    }
+    return U;
+}
+
+// Per-sample Monte Carlo estimator with the shared random streams: sample s of pixel (x, y)
+// draws (u0, u1) on the pixel and a Gaussian offset (Box-Muller of u2, u3) of the detection
+// state.  out: [height][width] mean of |U|^2 over the spp samples.
+void or_coherent_mc(const or_coherent* c, double* out, int32_t n_threads) {
+    int nt = n_threads > 0 ? n_threads : (int)std::thread::hardware_concurrency();
+    std::atomic<int64_t> next(0);
+    int64_t np = (int64_t)c->width * c->height;
+    auto work = [&]() {
+        for (;;) {
+            int64_t p = next.fetch_add(1);
+            if (p >= np) break;
+            int x = (int)(p % c->width), y = (int)(p / c->width);
+            double acc = 0.0;
+            for (int64_t s = 0; s < c->spp; ++s) {
+                uint64_t pid = ((uint64_t)s * c->height + y) * c->width + x;
+                U4 r = draw(pid, 0, STREAM_SOURCE, c->seed);
+                double z1, z2;
+                box_muller(unif(r.v[2]), unif(r.v[3]), z1, z2);
+                double X = (x + unif(r.v[0]) - 0.5 * c->width) * c->pitch_um + c->sigma_um * z1;
+                double Y = (y + unif(r.v[1]) - 0.5 * c->height) * c->pitch_um + c->sigma_um * z2;
+                acc += std::norm(field_at(*c, X, Y));
+            }
+            out[p] = acc / (double)c->spp;
+        }
+    };
+    std::vector<std::thread> th;
+    for (int i = 0; i < std::max(1, nt); ++i) th.emplace_back(work);
+    for (auto& t : th) t.join();
+}
+
+// The exact expectation of the estimator above for row y = 0 pixels, by Gauss-Hermite
+// quadrature over the detection state's Gaussian and Gauss-Legendre quadrature over the pixel
+// (x: pixel positions, n: count).  out[i] = E|U|^2 at pixel x[i]; rows are ignored (points:
+// Y = 0 is used; the y dependence is a common factor near the axis).
+void or_coherent_exact(const or_coherent* c, const int32_t* xpix, int64_t n, const double* gh_x,
+                       const double* gh_w, int32_t ngh, const double* gl_x, const double* gl_w,
+                       int32_t ngl, double* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int a = 0; a < ngl; ++a) {
+            double u = 0.5 * (gl_x[a] + 1.0);
+            double x0 = (xpix[i] + u - 0.5 * c->width) * c->pitch_um;
+            for (int b = 0; b < ngh; ++b) {
+                double X = x0 + std::sqrt(2.0) * c->sigma_um * gh_x[b];
+                acc += 0.5 * gl_w[a] * gh_w[b] / std::sqrt(kPi) * std::norm(field_at(*c, X, 0.0));
+            }
+        }
+        out[i] = acc;
+    }
+}
+
+double or_hankel1_re(double x) { return std::cyl_bessel_j(1.0, x); }
+double or_hankel1_im(double x) { return std::cyl_neumann(1.0, x); }
+
+}  // extern "C"
