@@ -1,0 +1,254 @@
+/* grwave: backward generalized-ray wave-optical path tracing on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libgrwave.so.  Plain pointers and sizes only.
+ *
+ * Paper: "A Generalized Ray Formulation for Wave-Optics Rendering" (arXiv 2303.15762).
+ *
+ * Conventions (all entry points):
+ *  - Every function returns GR_OK (0) or a negative GR_E_* status; gr_last_error() then holds a
+ *    message.  No C++ exception and no abort crosses the ABI.
+ *  - "host" pointers are read (and copied) before the call returns.  "device" pointers must
+ *    point to memory on the context's device, be suitably aligned (4 bytes for float data,
+ *    16 bytes for workspaces) and stay alive until the work enqueued on the context's stream has
+ *    completed; they are owned by the caller.
+ *  - Work is enqueued on the stream given to gr_create and is asynchronous unless stated.
+ *  - Geometry is in metres, surface heights, lengths, coherence radii and wavelengths in
+ *    micrometres.
+ *  - A context is not thread-safe; use one per thread (and per device / stream).
+ */
+#ifndef GRWAVE_H
+#define GRWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gr_ctx gr_ctx;
+
+enum {
+    GR_OK = 0,
+    GR_E_INVALID = -1,      /* bad argument: null pointer, size, enum or range */
+    GR_E_NO_SCENE = -2,     /* trace before scene / sensor upload */
+    GR_E_DEVICE = -3,       /* HIP runtime error */
+    GR_E_OOM = -4,          /* device allocation failed (scene upload, surrogate upload) */
+    GR_E_UNSUPPORTED = -5,  /* valid request this build does not implement */
+    GR_E_WORKSPACE = -6     /* workspace missing or smaller than gr_workspace_size */
+};
+
+enum { GR_MAT_SMOOTH = 0, GR_MAT_ROUGH = 1, GR_MAT_GRATING = 2 };
+enum { GR_SRC_PLANE_WAVE = 0, GR_SRC_GSM_AREA = 1 };
+enum { GR_BSDF_PLAIN = 0, GR_BSDF_SURROGATE_BF16 = 1, GR_BSDF_SURROGATE_FP8 = 2 };
+
+/* Surface material.  Sec. "Interaction Kernels":
+ *   SMOOTH  : reflection by a flat interface (eq. K_reflection_refraction), Fresnel factor
+ *             = reflectance.
+ *   GRATING : 1-D sinusoidal height h(x) = height_um * sin(2 pi g.x / length_um) (eq. K_grating):
+ *             height_um = amplitude A (half the peak-to-valley depth), length_um = pitch,
+ *             gdir = grating vector direction in world space (projected onto the surface).
+ *   ROUGH   : Gaussian random surface (eq. K_surface_HS, ensemble-averaged scatter):
+ *             height_um = RMS height, length_um = 1/e correlation length of the Gaussian
+ *             autocorrelation. */
+typedef struct {
+    int32_t kind;
+    float height_um;
+    float length_um;
+    float gdir[3];
+    float reflectance;
+} gr_material;
+
+/* Orthographic sensor: pixel (x, y) covers origin + [x, x+1) pitch axis_u + [y, y+1) pitch axis_v.
+ * Each detection state (Sec. "Measurement of the WDF", coherent states) is sourced with its mean
+ * position uniform on the pixel, mean direction dir, intensity standard deviation sigma_m
+ * (beta^2 / 2 = sigma^2) and rho = 0 (Sec. "Interactive Rendering", implementation details).
+ * axis_u, axis_v, dir must be unit vectors; width, height >= 1; pitch_m, sigma_m > 0. */
+typedef struct {
+    float origin[3];
+    float axis_u[3];
+    float axis_v[3];
+    float dir[3];
+    int32_t width;
+    int32_t height;
+    float pitch_m;
+    float sigma_m;
+} gr_sensor;
+
+/* Light source (Sec. "Interactive Rendering": distant sources and emitting areas).
+ *   PLANE_WAVE: spatially coherent plane wave travelling along dir (unit); power = irradiance
+ *               scale.  Visible where a ray along -dir escapes the scene.
+ *   GSM_AREA  : Gaussian-Schell emitter: parallelogram pos +- eu +- ev (eu, ev orthogonal to
+ *               the unit emission axis dir and to each other) emitting around dir with the
+ *               tangential wavevector density N(0, coherence_radius_um^-2 I) (Sec.
+ *               "Sample-Solve": source coherence fixes the angular spread). */
+typedef struct {
+    int32_t kind;
+    float dir[3];
+    float pos[3];
+    float eu[3];
+    float ev[3];
+    float coherence_radius_um;
+    float power;
+} gr_source;
+
+enum { GR_TRACE_KEEP_PATHS = 1 };
+
+/* Trace options.
+ *   spp_begin, spp_count : sample indices [spp_begin, spp_begin + spp_count) of every pixel and
+ *                          wavelength.  The random streams are keyed by the absolute index, so
+ *                          disjoint ranges add up to the full render.
+ *   spp_norm             : every path contribution is divided by this (normally the total
+ *                          number of samples per pixel).
+ *   max_depth            : number of surface interactions per path (>= 1, <= 64).
+ *   bsdf_mode            : GR_BSDF_* (surrogate modes need gr_set_surrogate).
+ *   rr_enable, rr_p      : Russian roulette from the third path segment on, survival
+ *                          probability rr_p in (0, 1].
+ *   seed                 : Philox key.
+ *   flags                : GR_TRACE_KEEP_PATHS keeps the per-path contributions in the
+ *                          workspace (see gr_workspace_paths). */
+typedef struct {
+    int64_t spp_begin;
+    int64_t spp_count;
+    int64_t spp_norm;
+    int32_t max_depth;
+    int32_t bsdf_mode;
+    int32_t rr_enable;
+    float rr_p;
+    uint64_t seed;
+    int32_t flags;
+    int32_t reserved;
+} gr_trace_opts;
+
+/* Counters of one trace (filled only when a gr_stats pointer is passed; that call then
+ * synchronises the stream). */
+typedef struct {
+    uint64_t paths;
+    uint64_t segments;          /* closest-hit queries, escaping ones included */
+    uint64_t shadow_rays;       /* any-hit queries of next-event estimation */
+    uint64_t surrogate_evals;
+    uint64_t fallbacks;         /* surrogate mode queries outside the trained domain */
+    uint64_t evanescent;        /* paths ended by an evanescent continuation */
+    uint64_t backfacing;        /* paths ended at a back-facing shading normal */
+    uint64_t nonfinite;         /* non-finite contributions dropped */
+    uint64_t node_visits;       /* BVH nodes fetched (closest-hit and any-hit) */
+    uint64_t tri_tests;         /* triangle tests (closest-hit and any-hit) */
+    float ms;                   /* device time of the path-tracing kernel */
+    float ms_reduce;            /* device time of the per-pixel reduction */
+} gr_stats;
+
+typedef struct {
+    int64_t n_tris;
+    int64_t n_nodes;            /* 4-wide BVH nodes (128 bytes each) */
+    int32_t depth;              /* deepest node level (root = 0) */
+    int32_t max_leaf;           /* largest leaf size */
+    int64_t device_bytes;       /* scene bytes resident on the device */
+    float build_ms;             /* host BVH build time */
+    float reserved;
+} gr_scene_info;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t, or
+ * NULL for the default stream).  The library allocates device memory only in
+ * gr_scene_upload and gr_set_surrogate; the trace path uses the caller's workspace. */
+int gr_create(gr_ctx** out, int device, void* hip_stream);
+void gr_destroy(gr_ctx* ctx);
+const char* gr_last_error(const gr_ctx* ctx);
+
+/* Upload a triangle scene (host arrays, copied).  verts_m: [nv][3]; normals: [nv][3] unit
+ * per-vertex shading normals or NULL (a zero normal selects the geometric normal of the
+ * triangles using that vertex); tris: [nt][3] vertex indices; tri_mat: [nt] material
+ * indices into mats[nm].  Builds a 4-wide SAH BVH on the host.  Replaces any previous scene.
+ * Ray tracing of the generalized ray's mean is valid under the paper's interactive assumption
+ * (footprint small against geometric detail, Sec. "Interactive Rendering"). */
+int gr_scene_upload(gr_ctx* ctx, const float* verts_m, int64_t nv, const float* normals,
+                    const int32_t* tris, int64_t nt, const int32_t* tri_mat,
+                    const gr_material* mats, int32_t nm);
+int gr_scene_info_get(const gr_ctx* ctx, gr_scene_info* info);
+
+int gr_set_sensor(gr_ctx* ctx, const gr_sensor* sensor);
+/* Up to 16 sources; next-event estimation picks one uniformly per interaction. */
+int gr_set_sources(gr_ctx* ctx, const gr_source* sources, int32_t n);
+
+/* Workspace (device memory) needed by gr_trace for these options and n_lambda wavelengths. */
+int gr_workspace_size(const gr_ctx* ctx, const gr_trace_opts* opts, int32_t n_lambda,
+                      size_t* bytes);
+/* Device pointer (inside `workspace`) of the per-path contributions kept by
+ * GR_TRACE_KEEP_PATHS: float [spp_count][height][width][n_lambda], already divided by
+ * spp_norm. */
+int gr_workspace_paths(const gr_ctx* ctx, void* workspace, float** paths_dev);
+
+/* Render: Algorithm 1 under the interactive assumption (ray-traced propagation, next-event
+ * estimation as the measurement, continuation sampled from the interaction kernel).
+ *   lambda_um : host [n_lambda] wavelengths (um), 1 <= n_lambda <= 64.
+ *   workspace : device, >= gr_workspace_size bytes.
+ *   image     : device float [n_lambda][height][width]; contributions are ADDED to it.
+ *   stats     : optional; when given the call synchronises the stream and fills it.
+ * Same options and seed give a bitwise identical image. */
+int gr_trace(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_trace_opts* opts,
+             void* workspace, size_t workspace_bytes, float* image, gr_stats* stats);
+
+/* Windowed diffraction density p_w(k_i,t -> k_o,t) (um^2) for a batch of queries (device).
+ * Row layout (14 floats): kind, height_um, length_um, reflectance, k (um^-1), kix, kiy, kox,
+ * koy (tangential wavevectors in the material frame, um^-1), sxx, syy, sxy (footprint
+ * covariance of the window on the surface, um^2), gx, gy (grating direction in the frame).
+ * mode GR_BSDF_PLAIN evaluates the closed form; surrogate modes evaluate the uploaded network
+ * where the query is inside its domain and the closed form elsewhere.  out: device [n]. */
+int gr_bsdf_eval(gr_ctx* ctx, const float* queries, int64_t n, int32_t mode, float* out);
+
+/* Draw n training queries for the learned scattering model and their targets log p_w
+ * (closed form), on the device.  box: host [10] lo/hi pairs of (lambda, s, ell, log sigma_x
+ * ..., see the surrogate section); x_out: device [n][10] network inputs; y_out: device [n];
+ * q_out: device [n][14] raw queries (may be NULL). */
+int gr_surrogate_samples(gr_ctx* ctx, int64_t n, uint64_t seed, float* x_out, float* y_out,
+                         float* q_out);
+
+/* Learned scattering model: 10 -> 64 -> 64 -> 64 -> 64 -> 1 perceptron with GELU.
+ * params: device float [13249] laid out W1[10][64], b1[64], W2[64][64], b2, W3, b3, W4, b4,
+ * W5[64][1], b5[1] (row-major [fan_in][fan_out]).  The BF16 path rounds weights and
+ * activations to bfloat16 for the matrix cores and accumulates in FP32. */
+enum { GR_MLP_PARAMS = 13249 };
+int gr_mlp_forward(gr_ctx* ctx, const float* params, const float* x, int64_t n, int32_t dtype,
+                   float* y);
+/* Mean-squared-error gradient of the batch (x [n][10], target [n]) into grad (device float
+ * [13249], overwritten) and the loss into loss_dev (device float [1]).  workspace: device,
+ * >= gr_mlp_workspace_size(n) bytes. */
+int gr_mlp_workspace_size(int64_t n, size_t* bytes);
+int gr_mlp_backward(gr_ctx* ctx, const float* params, const float* x, const float* target,
+                    int64_t n, void* workspace, float* grad, float* loss_dev);
+/* Adam (bias-corrected) update of params in place with first/second moments m, v (device
+ * float [13249] each, start at zero); step t >= 1. */
+int gr_adam_step(gr_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t t,
+                 float lr, float beta1, float beta2, float eps);
+/* Install a trained network for the surrogate trace modes.  params: device [13249] FP32
+ * (converted to BF16 and FP8 internally).  domain: host [4] = {min g, max g, min footprint
+ * sigma (um), max footprint sigma (um)}: rough-surface queries inside it use the network. */
+int gr_set_surrogate(gr_ctx* ctx, const float* params, const float* domain);
+
+/* Coherent measurement of mutually coherent emitters (Sec. "Linearity of Generalized Rays",
+ * two-point interference; Sec. "Numeric Validation", double slit).  For each pixel and sample,
+ * a point is drawn from the detection state's spatial density (uniform on the pixel plus a
+ * Gaussian of std sigma_um) and |sum_e c_e G_e exp(i k L_e)|^2 is accumulated, L_e the exact
+ * distance from emitter node e to the point.  phase_mode: 0 FP32, 1 FP64, 2 compensated
+ * two-float.  image: device float [height][width], overwritten with the per-pixel mean. */
+enum { GR_PHASE_FP32 = 0, GR_PHASE_FP64 = 1, GR_PHASE_TWO_FLOAT = 2 };
+typedef struct {
+    int32_t kind;          /* 0 points (3-D spherical waves), 1 slits (2-D, y-invariant) */
+    int32_t n_slits;       /* points: number of points; slits: number of slits (<= 8) */
+    double centre_um[8];   /* x centres */
+    double width_um;       /* slit width */
+    int32_t nodes_per_slit;/* Gauss-Legendre nodes per slit (<= 64) */
+    int32_t phase_mode;
+    double z_um;           /* aperture plane to sensor distance */
+    double lambda_um;
+    int32_t width, height;
+    double pitch_um, sigma_um;
+    int64_t spp;
+    uint64_t seed;
+} gr_coherent_desc;
+int gr_coherent_measure(gr_ctx* ctx, const gr_coherent_desc* desc, float* image, float* ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRWAVE_H */

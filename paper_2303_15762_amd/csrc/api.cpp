@@ -1,0 +1,407 @@
+// C ABI of libgrwave.so: argument validation, scene upload, launch orchestration.
+// Validation runs before any HIP call, so every error path is reachable without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/grwave.h"
+#include "bvh_build.hpp"
+#include "kernels.hpp"
+#include "surrogate.hpp"
+
+struct gr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // scene (device)
+    void* d_nodes = nullptr;
+    void* d_tris = nullptr;
+    void* d_tnorm = nullptr;
+    void* d_mats = nullptr;
+    int64_t n_tris = 0;
+    int64_t n_nodes = 0;
+    int bvh_depth = 0;
+    int max_leaf = 0;
+    int64_t scene_bytes = 0;
+    float build_ms = 0.0f;
+    bool has_scene = false;
+    // sensor and sources (host copies)
+    bool has_sensor = false;
+    gr_sensor sensor{};
+    std::vector<gr_source> sources;
+    int grid = 0;
+    int grid_stack = -1;
+    grw::SurrogateState sur;
+};
+
+namespace {
+
+int fail(gr_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(gr_ctx* c, int code, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define GR_HIP(c, call)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(c, GR_E_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+bool unit3(const float* v) {
+    if (!finite3(v)) return false;
+    const double n = std::sqrt((double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2]);
+    return std::fabs(n - 1.0) < 1e-3;
+}
+
+void free_scene(gr_ctx* c) {
+    if (c->d_nodes) (void)hipFree(c->d_nodes);
+    if (c->d_tris) (void)hipFree(c->d_tris);
+    if (c->d_tnorm) (void)hipFree(c->d_tnorm);
+    if (c->d_mats) (void)hipFree(c->d_mats);
+    c->d_nodes = c->d_tris = c->d_tnorm = c->d_mats = nullptr;
+    c->has_scene = false;
+}
+
+constexpr size_t kWsHeader = 4096;   // dispenser counter + statistics
+
+int stack_for_depth(int depth) { return 3 * (depth + 1) + 1; }
+
+}  // namespace
+
+extern "C" {
+
+int gr_create(gr_ctx** out, int device, void* hip_stream) {
+    if (!out) return GR_E_INVALID;
+    *out = nullptr;
+    if (device < 0) return GR_E_INVALID;
+    // No HIP call here: the device is selected (and checked) by the first entry point that
+    // touches it, so argument validation is usable without a GPU.
+    gr_ctx* c = new gr_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return GR_OK;
+}
+
+void gr_destroy(gr_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    free_scene(c);
+    grw::surrogate_free(c->sur);
+    delete c;
+}
+
+const char* gr_last_error(const gr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* normals, const int32_t* tris,
+                    int64_t nt, const int32_t* tri_mat, const gr_material* mats, int32_t nm) {
+    if (!c) return GR_E_INVALID;
+    if (!verts || !tris || !tri_mat || !mats) return fail(c, GR_E_INVALID, "scene: null pointer");
+    if (nv < 3 || nt < 1 || nm < 1) return fail(c, GR_E_INVALID, "scene: nv=%lld nt=%lld nm=%d", (long long)nv, (long long)nt, nm);
+    if (nt >= (1ll << 28)) return fail(c, GR_E_UNSUPPORTED, "scene: at most 2^28 triangles");
+    for (int64_t i = 0; i < nv; ++i)
+        if (!finite3(verts + 3 * i)) return fail(c, GR_E_INVALID, "scene: vertex %lld not finite", (long long)i);
+    for (int64_t i = 0; i < 3 * nt; ++i)
+        if (tris[i] < 0 || tris[i] >= nv) return fail(c, GR_E_INVALID, "scene: triangle index out of range at %lld", (long long)i);
+    for (int64_t i = 0; i < nt; ++i)
+        if (tri_mat[i] < 0 || tri_mat[i] >= nm) return fail(c, GR_E_INVALID, "scene: material index out of range at %lld", (long long)i);
+    for (int i = 0; i < nm; ++i) {
+        const gr_material& m = mats[i];
+        if (m.kind < 0 || m.kind > 2) return fail(c, GR_E_INVALID, "material %d: kind %d", i, m.kind);
+        if (!(m.reflectance >= 0.0f && m.reflectance <= 1.0f)) return fail(c, GR_E_INVALID, "material %d: reflectance", i);
+        if (m.kind != GR_MAT_SMOOTH) {
+            // the scattering kernels are meant for optical surface detail: heights up to 10 um,
+            // lengths (correlation length, pitch) from 0.01 um to 1 mm
+            if (!(m.height_um >= 0.0f && m.height_um <= 10.0f)) return fail(c, GR_E_INVALID, "material %d: height_um outside [0, 10]", i);
+            if (!(m.length_um >= 0.01f && m.length_um <= 1000.0f)) return fail(c, GR_E_INVALID, "material %d: length_um outside [0.01, 1000]", i);
+        }
+        if (m.kind == GR_MAT_GRATING && !unit3(m.gdir)) return fail(c, GR_E_INVALID, "material %d: grating direction not unit", i);
+    }
+    if (normals)
+        for (int64_t i = 0; i < nv; ++i)
+            if (!finite3(normals + 3 * i)) return fail(c, GR_E_INVALID, "scene: normal %lld not finite", (long long)i);
+
+    const auto t0 = std::chrono::steady_clock::now();
+    grw::BuiltBVH bvh = grw::build_bvh4(verts, tris, nt);
+    const auto t1 = std::chrono::steady_clock::now();
+    if (stack_for_depth(bvh.depth) > 96) return fail(c, GR_E_UNSUPPORTED, "scene: BVH depth %d too deep", bvh.depth);
+
+    std::vector<float> tri_data(12 * (size_t)nt), tri_norm(12 * (size_t)nt, 0.0f);
+    for (int64_t j = 0; j < nt; ++j) {
+        const int32_t t = bvh.tri_order[j];
+        for (int cidx = 0; cidx < 3; ++cidx) {
+            const float* p = verts + 3 * (int64_t)tris[3 * t + cidx];
+            float* q = &tri_data[12 * j + 4 * cidx];
+            q[0] = p[0];
+            q[1] = p[1];
+            q[2] = p[2];
+            q[3] = 0.0f;
+            if (normals) {
+                const float* n = normals + 3 * (int64_t)tris[3 * t + cidx];
+                float* r = &tri_norm[12 * j + 4 * cidx];
+                r[0] = n[0];
+                r[1] = n[1];
+                r[2] = n[2];
+            }
+        }
+        int32_t orig = t, mat = tri_mat[t];
+        std::memcpy(&tri_data[12 * j + 3], &orig, 4);
+        std::memcpy(&tri_data[12 * j + 7], &mat, 4);
+    }
+    std::vector<grw::DMat> dm(nm);
+    for (int i = 0; i < nm; ++i) {
+        dm[i].kind = mats[i].kind;
+        dm[i].h = mats[i].height_um;
+        dm[i].L = mats[i].length_um;
+        dm[i].refl = mats[i].reflectance;
+        dm[i].gx = mats[i].gdir[0];
+        dm[i].gy = mats[i].gdir[1];
+        dm[i].gz = mats[i].gdir[2];
+        dm[i].pad = 0.0f;
+    }
+    GR_HIP(c, hipSetDevice(c->device));
+    free_scene(c);
+    const size_t nb = bvh.nodes.size() * sizeof(grw::BVH4Node);
+    const size_t tb = tri_data.size() * 4, mb = dm.size() * sizeof(grw::DMat);
+    if (hipMalloc(&c->d_nodes, nb) != hipSuccess || hipMalloc(&c->d_tris, tb) != hipSuccess ||
+        hipMalloc(&c->d_tnorm, tb) != hipSuccess || hipMalloc(&c->d_mats, mb) != hipSuccess) {
+        free_scene(c);
+        (void)hipGetLastError();
+        return fail(c, GR_E_OOM, "scene: device allocation of %zu bytes failed", nb + 2 * tb + mb);
+    }
+    GR_HIP(c, hipMemcpy(c->d_nodes, bvh.nodes.data(), nb, hipMemcpyHostToDevice));
+    GR_HIP(c, hipMemcpy(c->d_tris, tri_data.data(), tb, hipMemcpyHostToDevice));
+    GR_HIP(c, hipMemcpy(c->d_tnorm, tri_norm.data(), tb, hipMemcpyHostToDevice));
+    GR_HIP(c, hipMemcpy(c->d_mats, dm.data(), mb, hipMemcpyHostToDevice));
+    c->n_tris = nt;
+    c->n_nodes = (int64_t)bvh.nodes.size();
+    c->bvh_depth = bvh.depth;
+    c->max_leaf = bvh.max_leaf;
+    c->scene_bytes = (int64_t)(nb + 2 * tb + mb);
+    c->build_ms = std::chrono::duration<float, std::milli>(t1 - t0).count();
+    c->has_scene = true;
+    c->grid_stack = -1;
+    return GR_OK;
+}
+
+int gr_scene_info_get(const gr_ctx* c, gr_scene_info* info) {
+    if (!c || !info) return GR_E_INVALID;
+    if (!c->has_scene) return GR_E_NO_SCENE;
+    info->n_tris = c->n_tris;
+    info->n_nodes = c->n_nodes;
+    info->depth = c->bvh_depth;
+    info->max_leaf = c->max_leaf;
+    info->device_bytes = c->scene_bytes;
+    info->build_ms = c->build_ms;
+    info->reserved = 0.0f;
+    return GR_OK;
+}
+
+int gr_set_sensor(gr_ctx* c, const gr_sensor* s) {
+    if (!c) return GR_E_INVALID;
+    if (!s) return fail(c, GR_E_INVALID, "sensor: null");
+    if (!finite3(s->origin) || !unit3(s->axis_u) || !unit3(s->axis_v) || !unit3(s->dir))
+        return fail(c, GR_E_INVALID, "sensor: origin must be finite and axes / direction unit vectors");
+    if (s->width < 1 || s->height < 1 || s->width > (1 << 16) || s->height > (1 << 16))
+        return fail(c, GR_E_INVALID, "sensor: %d x %d pixels", s->width, s->height);
+    if (!(s->pitch_m > 0.0f) || !(s->sigma_m > 0.0f) || !std::isfinite(s->pitch_m) || !std::isfinite(s->sigma_m))
+        return fail(c, GR_E_INVALID, "sensor: pitch and sigma must be positive");
+    c->sensor = *s;
+    c->has_sensor = true;
+    return GR_OK;
+}
+
+int gr_set_sources(gr_ctx* c, const gr_source* s, int32_t n) {
+    if (!c) return GR_E_INVALID;
+    if (n < 0 || n > grw::kMaxSources) return fail(c, GR_E_INVALID, "sources: count %d (max %d)", n, grw::kMaxSources);
+    if (n > 0 && !s) return fail(c, GR_E_INVALID, "sources: null");
+    for (int i = 0; i < n; ++i) {
+        const gr_source& q = s[i];
+        if (q.kind != GR_SRC_PLANE_WAVE && q.kind != GR_SRC_GSM_AREA) return fail(c, GR_E_INVALID, "source %d: kind %d", i, q.kind);
+        if (!unit3(q.dir)) return fail(c, GR_E_INVALID, "source %d: direction not unit", i);
+        if (!(q.power >= 0.0f) || !std::isfinite(q.power)) return fail(c, GR_E_INVALID, "source %d: power", i);
+        if (q.kind == GR_SRC_GSM_AREA) {
+            if (!(q.coherence_radius_um > 0.0f) || !finite3(q.pos) || !finite3(q.eu) || !finite3(q.ev))
+                return fail(c, GR_E_INVALID, "source %d: emitter geometry / coherence radius", i);
+            const double lu = std::sqrt((double)q.eu[0] * q.eu[0] + (double)q.eu[1] * q.eu[1] + (double)q.eu[2] * q.eu[2]);
+            const double lv = std::sqrt((double)q.ev[0] * q.ev[0] + (double)q.ev[1] * q.ev[1] + (double)q.ev[2] * q.ev[2]);
+            if (!(lu > 0.0) || !(lv > 0.0)) return fail(c, GR_E_INVALID, "source %d: empty emitter", i);
+            const double du = (q.eu[0] * q.dir[0] + q.eu[1] * q.dir[1] + q.eu[2] * q.dir[2]) / lu;
+            const double dv = (q.ev[0] * q.dir[0] + q.ev[1] * q.dir[1] + q.ev[2] * q.dir[2]) / lv;
+            const double uv = (q.eu[0] * q.ev[0] + q.eu[1] * q.ev[1] + q.eu[2] * q.ev[2]) / (lu * lv);
+            if (std::fabs(du) > 1e-4 || std::fabs(dv) > 1e-4 || std::fabs(uv) > 1e-4)
+                return fail(c, GR_E_INVALID, "source %d: emitter edges must be orthogonal to each other and the axis", i);
+        }
+    }
+    c->sources.assign(s, s + n);
+    return GR_OK;
+}
+
+int gr_workspace_size(const gr_ctx* c, const gr_trace_opts* o, int32_t nl, size_t* bytes) {
+    if (!c || !o || !bytes) return GR_E_INVALID;
+    if (!c->has_sensor) return GR_E_NO_SCENE;
+    if (o->spp_count < 0 || nl < 1 || nl > grw::kMaxLambda) return GR_E_INVALID;
+    const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
+    *bytes = kWsHeader + (size_t)(per * (uint64_t)o->spp_count) * sizeof(float);
+    return GR_OK;
+}
+
+int gr_workspace_paths(const gr_ctx* c, void* ws, float** paths) {
+    if (!c || !ws || !paths) return GR_E_INVALID;
+    *paths = reinterpret_cast<float*>(static_cast<char*>(ws) + kWsHeader);
+    return GR_OK;
+}
+
+int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, void* ws, size_t ws_bytes,
+             float* image, gr_stats* st) {
+    if (!c) return GR_E_INVALID;
+    if (!lambda || !o || !image) return fail(c, GR_E_INVALID, "trace: null argument");
+    if (nl < 1 || nl > grw::kMaxLambda) return fail(c, GR_E_INVALID, "trace: n_lambda %d", nl);
+    for (int i = 0; i < nl; ++i)
+        if (!(lambda[i] >= 0.1f && lambda[i] <= 20.0f)) return fail(c, GR_E_INVALID, "trace: wavelength %d outside [0.1, 20] um", i);
+    if (o->spp_begin < 0 || o->spp_count < 0 || o->spp_norm < 1) return fail(c, GR_E_INVALID, "trace: spp range");
+    if (o->max_depth < 1 || o->max_depth > 64) return fail(c, GR_E_INVALID, "trace: max_depth %d", o->max_depth);
+    if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
+    if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
+    if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
+    if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
+        return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
+    if (o->bsdf_mode == GR_BSDF_SURROGATE_FP8) return fail(c, GR_E_UNSUPPORTED, "trace: FP8 surrogate in the tracer");
+    size_t need = 0;
+    gr_workspace_size(c, o, nl, &need);
+    if (!ws || ws_bytes < need) return fail(c, GR_E_WORKSPACE, "trace: workspace %zu < %zu bytes", ws_bytes, need);
+    if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) return fail(c, GR_E_INVALID, "trace: workspace alignment");
+    const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
+    if (per >= (1ull << 32)) return fail(c, GR_E_UNSUPPORTED, "trace: width * height * n_lambda >= 2^32");
+
+    grw::TraceArgs a{};
+    a.scene.nodes = static_cast<const float4*>(c->d_nodes);
+    a.scene.tris = static_cast<const float4*>(c->d_tris);
+    a.scene.tnorm = static_cast<const float4*>(c->d_tnorm);
+    a.scene.mats = static_cast<const grw::DMat*>(c->d_mats);
+    a.scene.n_tris = c->n_tris;
+    const gr_sensor& s = c->sensor;
+    for (int i = 0; i < 3; ++i) {
+        a.sensor.o[i] = s.origin[i];
+        a.sensor.u[i] = s.axis_u[i];
+        a.sensor.v[i] = s.axis_v[i];
+        a.sensor.d[i] = s.dir[i];
+    }
+    a.sensor.W = s.width;
+    a.sensor.H = s.height;
+    a.sensor.pitch = s.pitch_m;
+    a.sensor.sigma_um = s.sigma_m * 1e6f;
+    a.nsrc = (int)c->sources.size();
+    for (int i = 0; i < a.nsrc; ++i) {
+        const gr_source& q = c->sources[i];
+        grw::SourceDev& d = a.src[i];
+        d.kind = q.kind;
+        for (int j = 0; j < 3; ++j) {
+            d.dir[j] = q.dir[j];
+            d.pos[j] = q.pos[j];
+        }
+        if (q.kind == GR_SRC_GSM_AREA) {
+            const float lu = std::sqrt(q.eu[0] * q.eu[0] + q.eu[1] * q.eu[1] + q.eu[2] * q.eu[2]);
+            const float lv = std::sqrt(q.ev[0] * q.ev[0] + q.ev[1] * q.ev[1] + q.ev[2] * q.ev[2]);
+            for (int j = 0; j < 3; ++j) {
+                d.bu[j] = q.eu[j] / lu;
+                d.bv[j] = q.ev[j] / lv;
+            }
+            d.lu = lu;
+            d.lv = lv;
+        }
+        d.rc_um = q.coherence_radius_um;
+        d.power = q.power;
+    }
+    a.nl = nl;
+    for (int i = 0; i < nl; ++i) a.lambda[i] = lambda[i];
+    a.spp_begin = o->spp_begin;
+    a.n_paths = per * (uint64_t)o->spp_count;
+    a.per_sample = (uint32_t)per;
+    a.inv_spp_norm = (float)(1.0 / (double)o->spp_norm);
+    a.max_depth = o->max_depth;
+    a.rr_enable = o->rr_enable;
+    a.rr_thr = (uint32_t)std::lround((double)o->rr_p * 16777216.0);
+    a.inv_rr_p = o->rr_enable ? 1.0f / o->rr_p : 1.0f;
+    a.seed = o->seed;
+    a.bsdf_mode = o->bsdf_mode;
+    if (o->bsdf_mode != GR_BSDF_PLAIN) grw::surrogate_fill(c->sur, a.sur);
+    char* base = static_cast<char*>(ws);
+    a.counter = reinterpret_cast<unsigned long long*>(base);
+    a.stats = reinterpret_cast<unsigned long long*>(base + 256);
+    a.records = reinterpret_cast<float*>(base + kWsHeader);
+
+    GR_HIP(c, hipSetDevice(c->device));
+    const int stack = stack_for_depth(c->bvh_depth);
+    if (c->grid_stack != stack) {
+        c->grid = grw::trace_grid_size(c->device, stack);
+        c->grid_stack = stack;
+        if (c->grid <= 0) return fail(c, GR_E_DEVICE, "trace: occupancy query failed");
+    }
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (st)
+        for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));
+    GR_HIP(c, hipMemsetAsync(ws, 0, kWsHeader, c->stream));
+    if (st) GR_HIP(c, hipEventRecord(ev[0], c->stream));
+    if (a.n_paths > 0) GR_HIP(c, grw::launch_trace(a, stack, c->grid, c->stream));
+    if (st) GR_HIP(c, hipEventRecord(ev[1], c->stream));
+    if (a.n_paths > 0)
+        GR_HIP(c, grw::launch_reduce(a.records, image, o->spp_count, (uint32_t)s.height, (uint32_t)s.width,
+                                     (uint32_t)nl, c->stream));
+    if (st) {
+        GR_HIP(c, hipEventRecord(ev[2], c->stream));
+        GR_HIP(c, hipStreamSynchronize(c->stream));
+        unsigned long long h[grw::ST_COUNT];
+        GR_HIP(c, hipMemcpy(h, a.stats, sizeof(h), hipMemcpyDeviceToHost));
+        float ms = 0.0f, ms_r = 0.0f;
+        GR_HIP(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+        GR_HIP(c, hipEventElapsedTime(&ms_r, ev[1], ev[2]));
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        st->paths = h[grw::ST_PATHS];
+        st->segments = h[grw::ST_SEGMENTS];
+        st->shadow_rays = h[grw::ST_SHADOW];
+        st->surrogate_evals = h[grw::ST_SUR];
+        st->fallbacks = h[grw::ST_FALLBACK];
+        st->evanescent = h[grw::ST_EVANESCENT];
+        st->backfacing = h[grw::ST_BACKFACING];
+        st->nonfinite = h[grw::ST_NONFINITE];
+        st->node_visits = h[grw::ST_NODES];
+        st->tri_tests = h[grw::ST_TRIS];
+        st->ms = ms;
+        st->ms_reduce = ms_r;
+    }
+    return GR_OK;
+}
+
+int gr_bsdf_eval(gr_ctx* c, const float* q, int64_t n, int32_t mode, float* out) {
+    if (!c) return GR_E_INVALID;
+    if (n < 0 || (n > 0 && (!q || !out))) return fail(c, GR_E_INVALID, "bsdf_eval: arguments");
+    if (mode != GR_BSDF_PLAIN) {
+        if (!c->sur.ready) return fail(c, GR_E_INVALID, "bsdf_eval: surrogate mode without gr_set_surrogate");
+        if (mode == GR_BSDF_SURROGATE_FP8) return fail(c, GR_E_UNSUPPORTED, "bsdf_eval: FP8");
+    }
+    GR_HIP(c, hipSetDevice(c->device));
+    if (mode == GR_BSDF_PLAIN) {
+        GR_HIP(c, grw::launch_bsdf_eval(q, n, out, c->stream));
+    } else {
+        GR_HIP(c, grw::launch_bsdf_eval_surrogate(c->sur, q, n, out, c->stream));
+    }
+    return GR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,307 @@
+// Device-side arithmetic of the generalized-ray tracer (gfx950, FP32 with FP64 where a
+// discrete decision needs it).
+//
+// Paper: "A Generalized Ray Formulation for Wave-Optics Rendering" (arXiv 2303.15762).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grw {
+
+constexpr float kPiF = 3.14159265358979f;
+constexpr float kTwoPiF = 6.28318530717959f;
+
+// ------------------------------------------------------------------------------------------
+// Small float3 helpers (registers only).
+// ------------------------------------------------------------------------------------------
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 mk3(float x, float y, float z) { return f3{x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return f3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return f3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ f3 operator*(float s, f3 a) { return f3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross3(f3 a, f3 b) {
+    return f3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ f3 normalize3(f3 a) { return rsqrtf(dot3(a, a)) * a; }
+__device__ __forceinline__ float maxabs3(f3 a) {
+    return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z)));
+}
+
+// ------------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 multiplies by the published
+// multipliers, xor of the high halves with the other counter words and the key, Weyl-sequence
+// key schedule.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// Streams of one path: counter = (path id lo, path id hi, interaction index, stream).
+enum { STREAM_SOURCE = 0, STREAM_NEE = 1, STREAM_SCATTER = 2 };
+
+__device__ __forceinline__ uint4 draw(uint64_t pid, uint32_t depth, uint32_t stream, uint64_t seed) {
+    return philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), depth, stream, (uint32_t)seed,
+                         (uint32_t)(seed >> 32));
+}
+
+// 24-bit uniform in [0, 1), exact in float.
+__device__ __forceinline__ float unif(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+// Box-Muller pair from two uniforms.
+__device__ __forceinline__ void box_muller(float u1, float u2, float& z1, float& z2) {
+    const float r = sqrtf(-2.0f * logf(1.0f - u1));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    z1 = r * c;
+    z2 = r * s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Bivariate normal density N(x; 0, S), S = [[a, c], [c, b]].
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float gauss2(float x, float y, float a, float b, float c) {
+    const float det = a * b - c * c;
+    const float q = (b * x * x - 2.0f * c * x * y + a * y * y) / det;
+    return __expf(-0.5f * q) * (1.0f / kTwoPiF) * rsqrtf(det);
+}
+
+// ------------------------------------------------------------------------------------------
+// Bessel function of the first kind, integer order n >= 0, by Miller's downward recurrence
+// J_{k-1} = (2k / x) J_k - J_{k+1} from a start well above max(n, x), normalised with the
+// identity J_0 + 2 sum_k J_2k = 1.  Stable in both regimes; rescaled to stay in range.
+// ------------------------------------------------------------------------------------------
+// x >= 0 (the phase-screen modulation depth q_z A is never negative here).
+__device__ inline float bessel_jn(int n, float x) {
+    if (x < 1e-20f) return n == 0 ? 1.0f : 0.0f;
+    const int big = max(n, (int)x);
+    // even start; capped so that any argument terminates quickly (callers keep x < 2000)
+    const int start = min(2 * ((big + 16 + (int)sqrtf(40.0f * (float)big)) / 2), 4096);
+    const float tox = 2.0f / x;
+    float jp = 0.0f, j = 1.0f, ans = 0.0f, sum = 0.0f;
+    bool add = false;   // true when the index just produced (kk - 1) is even
+    for (int kk = start; kk > 0; --kk) {
+        const float jm = (float)kk * tox * j - jp;
+        jp = j;          // J_kk
+        j = jm;          // J_{kk-1}
+        if (fabsf(j) > 1e15f) {
+            j *= 1e-15f;
+            jp *= 1e-15f;
+            ans *= 1e-15f;
+            sum *= 1e-15f;
+        }
+        if (add) sum += j;
+        add = !add;
+        if (kk == n) ans = jp;
+    }
+    const float norm = 2.0f * sum - j;   // J_0 + 2 (J_2 + J_4 + ...)
+    return (n == 0 ? j : ans) / norm;
+}
+
+// ------------------------------------------------------------------------------------------
+// log Poisson(m; g) without cancellation: Stirling's series for log m! in the form
+// -m log1p((m - g) / g) + (m - g) - log(2 pi m) / 2 - 1 / (12 m) + 1 / (360 m^3).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float log_poisson(int m, float g, float logg) {
+    if (m == 0) return -g;
+    if (m < 10) {
+        float lf = 0.0f;   // log m!
+        for (int i = 2; i <= m; ++i) lf += logf((float)i);
+        return -g + (float)m * logg - lf;
+    }
+    const float mf = (float)m;
+    const float d = mf - g;
+    return -mf * log1pf(d / g) + d - 0.5f * logf(kTwoPiF * mf) - 1.0f / (12.0f * mf) +
+           1.0f / (360.0f * mf * mf * mf);
+}
+
+// Material record on the device.
+struct DMat {
+    int kind;
+    float h, L, refl;
+    float gx, gy, gz, pad;
+};
+
+enum { MAT_SMOOTH = 0, MAT_ROUGH = 1, MAT_GRATING = 2 };
+
+// ------------------------------------------------------------------------------------------
+// Windowed diffraction density p_w(k_i,t -> k_o,t) (um^2) of a curvature-free generalized ray
+// on a surface patch (Sec. "Interaction Kernels"): the squared Fourier transform of the
+// Gaussian window times the surface phase screen exp(i q_z h(x)), normalised by the window
+// energy, as a Gaussian mixture in the tangential transfer kappa = k_o,t - k_i,t:
+//   smooth : N(kappa; 0, Sk)
+//   grating: sum_j J_j(q_z A)^2 N(kappa; -j K g, Sk)          (Jacobi-Anger, eq. K_grating)
+//   rough  : sum_m Poisson(m; q_z^2 s^2) N(kappa; 0, Sk + 2m/l^2 I)   (ensemble average)
+// with Sk = S_fp^-1 / 4, S_fp the footprint covariance, q_z = k (cos i + cos o).
+// ------------------------------------------------------------------------------------------
+__device__ inline float pw_plain(int kind, float h, float L, float refl, float k, float kix,
+                                 float kiy, float kox, float koy, float sxx, float syy, float sxy,
+                                 float gx, float gy) {
+    const float ik2 = 1.0f / (k * k);
+    const float ni = (kix * kix + kiy * kiy) * ik2;
+    const float no = (kox * kox + koy * koy) * ik2;
+    if (ni >= 1.0f || no >= 1.0f) return 0.0f;
+    const float qz = k * (sqrtf(1.0f - ni) + sqrtf(1.0f - no));
+    const float kx = kox - kix, ky = koy - kiy;
+    const float det = sxx * syy - sxy * sxy;
+    const float idet = 0.25f / det;
+    const float a = syy * idet, b = sxx * idet, c = -sxy * idet;
+    if (kind == MAT_SMOOTH) return refl * gauss2(kx, ky, a, b, c);
+    if (kind == MAT_GRATING) {
+        const float K = kTwoPiF / L;
+        const float m = qz * h;
+        const float proj = kx * gx + ky * gy;
+        const float sg = sqrtf(fmaxf(a * gx * gx + 2.0f * c * gx * gy + b * gy * gy, 0.0f));
+        int jlo = (int)ceilf((-proj - 8.0f * sg) / K);
+        int jhi = (int)floorf((-proj + 8.0f * sg) / K);
+        if (jhi < jlo) return 0.0f;
+        jhi = min(jhi, jlo + 15);
+        float s = 0.0f;
+        for (int j = jlo; j <= jhi; ++j) {
+            const float bj = bessel_jn(abs(j), m);
+            s += bj * bj * gauss2(kx + (float)j * K * gx, ky + (float)j * K * gy, a, b, c);
+        }
+        return refl * s;
+    }
+    // rough
+    const float g = qz * qz * h * h;
+    if (g < 1e-12f) return refl * gauss2(kx, ky, a, b, c);
+    const float sq = sqrtf(g);
+    int mlo = max(0, (int)floorf(g - 6.0f * sq - 3.0f));
+    int mhi = (int)ceilf(g + 6.0f * sq + 3.0f);
+    if (mhi - mlo > 4095) {   // bound the work for out-of-range inputs
+        mlo = max(0, (int)g - 2048);
+        mhi = mlo + 4095;
+    }
+    const float add = 2.0f / (L * L);
+    const float logg = logf(g);
+    const float c2 = c * c;
+    float s = 0.0f;
+    for (int m = mlo; m <= mhi; ++m) {
+        const float aa = a + (float)m * add, bb = b + (float)m * add;
+        const float dm = aa * bb - c2;
+        const float q = (bb * kx * kx - 2.0f * c * kx * ky + aa * ky * ky) / dm;
+        s += __expf(log_poisson(m, g, logg) - 0.5f * q) * rsqrtf(dm);
+    }
+    return refl * s * (1.0f / kTwoPiF);
+}
+
+// ------------------------------------------------------------------------------------------
+// Continuation sampling from the unwindowed kernel f_inf (the delta-lobe limit of p_w),
+// taking the generalized ray's own travel direction as the incident wave (time reversal is
+// wavevector reversal, and these kernels are reciprocal).
+//   smooth : mirror direction, weight = reflectance
+//   grating: order j among the propagating ones with probability J_j(m_j)^2 / W,
+//            m_j = k A (cos i + cos o_j); weight = reflectance * W (evanescent orders dropped)
+//   rough  : term m ~ Poisson(g), g = (2 k cos i s)^2, then kappa ~ N(0, 2m/l^2 I);
+//            weight = reflectance; an evanescent draw ends the path
+// Returns 0 on success, 1 when the path ends evanescently.
+// ------------------------------------------------------------------------------------------
+__device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, float ci,
+                                  float u0, float u1, float u2, float& kox, float& koy,
+                                  float& weight) {
+    if (m.kind == MAT_SMOOTH) {
+        kox = kix;
+        koy = kiy;
+        weight = m.refl;
+        return 0;
+    }
+    const float k2 = k * k;
+    if (m.kind == MAT_GRATING) {
+        // grating vector = frame x axis; propagating orders: (kix - jK)^2 + kiy^2 < k^2
+        const float K = kTwoPiF / m.L;
+        const float rem = k2 - kiy * kiy;
+        if (rem <= 0.0f) return 1;
+        const float r = sqrtf(rem);
+        const int jlo = (int)floorf((kix - r) / K) - 1;
+        const int jhi = min((int)ceilf((kix + r) / K) + 1, jlo + 4096);
+        float W = 0.0f;
+        for (int j = jlo; j <= jhi; ++j) {
+            const float ox = kix - (float)j * K;
+            const float no = (ox * ox + kiy * kiy) / k2;
+            if (no >= 1.0f) continue;
+            const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
+            W += bj * bj;
+        }
+        if (!(W > 0.0f)) return 1;
+        const float target = u0 * W;
+        float c = 0.0f;
+        int pick = jhi;
+        bool found = false;
+        int last = jlo;
+        for (int j = jlo; j <= jhi; ++j) {
+            const float ox = kix - (float)j * K;
+            const float no = (ox * ox + kiy * kiy) / k2;
+            if (no >= 1.0f) continue;
+            const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
+            c += bj * bj;
+            last = j;
+            if (!found && target < c) {
+                pick = j;
+                found = true;
+                break;
+            }
+        }
+        if (!found) pick = last;
+        kox = kix - (float)pick * K;
+        koy = kiy;
+        weight = m.refl * W;
+        return 0;
+    }
+    // rough: Poisson term by inversion of the CDF in double precision (the decision must not
+    // depend on FP32 rounding of a long sum); terms below g - 7 sqrt(g) hold < 1e-11 mass.
+    const double g = 4.0 * (double)k2 * (double)ci * (double)ci * (double)m.h * (double)m.h;
+    int n = 0;
+    if (g > 0.0) {
+        const double sq = sqrt(g);
+        const int mlo = g > 49.0 ? (int)floor(g - 7.0 * sq) : 0;
+        const int mhi = min((int)ceil(g + 20.0 * sq + 40.0), mlo + 65536);
+        // log of the first term: log Poisson(mlo; g) via Stirling (mlo >= 10 here) or exactly
+        double lw;
+        if (mlo == 0) {
+            lw = -g;
+        } else {
+            const double mf = (double)mlo, d = mf - g;
+            lw = -mf * log1p(d / g) + d - 0.5 * log(6.283185307179586 * mf) - 1.0 / (12.0 * mf) +
+                 1.0 / (360.0 * mf * mf * mf);
+        }
+        double w = exp(lw), c = 0.0;
+        const double uu = (double)u0;
+        n = mhi;
+        for (int i = mlo; i <= mhi; ++i) {
+            c += w;
+            if (uu < c) {
+                n = i;
+                break;
+            }
+            w *= g / (double)(i + 1);
+        }
+    }
+    float z1, z2;
+    box_muller(u1, u2, z1, z2);
+    const float sd = sqrtf(2.0f * (float)n) / m.L;
+    kox = kix + sd * z1;
+    koy = kiy + sd * z2;
+    if (kox * kox + koy * koy >= k2) return 1;
+    weight = m.refl;
+    return 0;
+}
+
+}  // namespace grw

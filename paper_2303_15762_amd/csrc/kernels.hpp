@@ -1,0 +1,84 @@
+// Device-side argument blocks shared by the kernels and the host ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.hpp"
+
+namespace grw {
+
+constexpr int kMaxSources = 16;
+constexpr int kMaxLambda = 64;
+
+struct SceneDev {
+    const float4* nodes;     // BVH4Node as 8 float4 each
+    const float4* tris;      // 3 float4 per triangle in leaf order: v0 (w = original id), v1 (w = material), v2
+    const float4* tnorm;     // 3 float4 per triangle: per-vertex shading normals (zero = geometric)
+    const DMat* mats;
+    int64_t n_tris;
+};
+
+struct SensorDev {
+    float o[3], u[3], v[3], d[3];
+    int W, H;
+    float pitch;      // metres
+    float sigma_um;
+};
+
+struct SourceDev {
+    int kind;         // 0 plane wave, 1 gaussian-schell area
+    float dir[3];     // travel direction / emission axis (unit)
+    float pos[3];
+    float bu[3], bv[3];   // unit in-plane axes of the emitter
+    float lu, lv;         // half extents (m)
+    float rc_um, power;
+};
+
+// Surrogate (learned p_w) parameters prepared for the matrix cores.
+struct SurrogateDev {
+    const uint16_t* w_bf16;   // packed weights, see mlp.hip
+    const float* bias;        // [4 * 64 + 1]
+    const float* w_out;       // [64]
+    float gmin, gmax, smin, smax;
+    int enabled;
+};
+
+struct TraceArgs {
+    SceneDev scene;
+    SensorDev sensor;
+    SourceDev src[kMaxSources];
+    int nsrc;
+    int nl;
+    float lambda[kMaxLambda];
+    int64_t spp_begin;
+    uint64_t n_paths;          // spp_count * H * W * nl
+    uint32_t per_sample;       // H * W * nl
+    float inv_spp_norm;
+    int max_depth;
+    int rr_enable;
+    uint32_t rr_thr;           // survive iff (draw >> 8) < rr_thr
+    float inv_rr_p;
+    uint64_t seed;
+    int bsdf_mode;
+    SurrogateDev sur;
+    float* records;                  // [n_paths]
+    unsigned long long* counter;     // path dispenser
+    unsigned long long* stats;       // [16]
+};
+
+enum {
+    ST_PATHS = 0, ST_SEGMENTS, ST_SHADOW, ST_SUR, ST_FALLBACK, ST_EVANESCENT, ST_BACKFACING,
+    ST_NONFINITE, ST_NODES, ST_TRIS, ST_COUNT
+};
+
+// Launchers (trace.hip).
+hipError_t launch_trace(const TraceArgs& a, int stack_depth, int grid, hipStream_t s);
+hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
+                         uint32_t nl, hipStream_t s);
+int trace_grid_size(int device, int stack_depth);
+
+// Batch p_w evaluation (trace.hip).
+hipError_t launch_bsdf_eval(const float* q, int64_t n, float* out, hipStream_t s);
+
+}  // namespace grw

@@ -1,0 +1,471 @@
+// Backward generalized-ray path tracing on gfx950: one persistent kernel per trace.
+//
+// Each wave keeps 64 paths in registers.  Lanes whose path ended are refilled together: a
+// ballot of the dead lanes, one atomic on the global path dispenser per wave, and the lane's
+// rank among the dead lanes (mbcnt) as its offset.  Every iteration advances each live path by
+// one segment: closest hit (4-wide BVH, per-lane stack in LDS), free-space update of the
+// generalized ray, measurement by next-event estimation, continuation sampling.  Paths write
+// one float each; a second kernel sums them per pixel in a fixed order, so the image does not
+// depend on scheduling.
+//
+// Paper: "A Generalized Ray Formulation for Wave-Optics Rendering" (arXiv 2303.15762),
+// Algorithm 1 under the interactive assumption of Sec. "Interactive Rendering".
+#include <float.h>
+
+#include "kernels.hpp"
+
+namespace grw {
+
+struct RayT {
+    f3 o, d, inv;
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ float comp(f3 v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : v.z); }
+
+__device__ __forceinline__ void ray_setup(RayT& r, f3 o, f3 d) {
+    r.o = o;
+    r.d = d;
+    const float tiny = 1e-30f;
+    r.inv = mk3(1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
+                1.0f / (fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y)),
+                1.0f / (fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z)));
+    // Watertight ray/triangle test set-up (Woop, Benthin, Wald, JCGT 2013): permute so that
+    // the dominant direction axis is z, keep the winding, shear onto the ray.
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    const int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    const float dz = comp(d, kz);
+    if (dz < 0.0f) {
+        const int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.Sx = comp(d, kx) / dz;
+    r.Sy = comp(d, ky) / dz;
+    r.Sz = 1.0f / dz;
+}
+
+// Returns true with t and the barycentric weights (bu of v1, bv of v2) when the ray's line
+// crosses the triangle (edges inclusive, shared edges decided consistently).
+__device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, float4 c4, float& t,
+                                          float& bu, float& bv) {
+    const f3 A = mk3(a4.x - r.o.x, a4.y - r.o.y, a4.z - r.o.z);
+    const f3 B = mk3(b4.x - r.o.x, b4.y - r.o.y, b4.z - r.o.z);
+    const f3 C = mk3(c4.x - r.o.x, c4.y - r.o.y, c4.z - r.o.z);
+    const float Az0 = comp(A, r.kz), Bz0 = comp(B, r.kz), Cz0 = comp(C, r.kz);
+    const float Ax = comp(A, r.kx) - r.Sx * Az0, Ay = comp(A, r.ky) - r.Sy * Az0;
+    const float Bx = comp(B, r.kx) - r.Sx * Bz0, By = comp(B, r.ky) - r.Sy * Bz0;
+    const float Cx = comp(C, r.kx) - r.Sx * Cz0, Cy = comp(C, r.ky) - r.Sy * Cz0;
+    // edge functions with explicit rounding (no contraction), so that an edge shared by two
+    // triangles gets exactly opposite values
+    float U = __fsub_rn(__fmul_rn(Cx, By), __fmul_rn(Cy, Bx));
+    float V = __fsub_rn(__fmul_rn(Ax, Cy), __fmul_rn(Ay, Cx));
+    float W = __fsub_rn(__fmul_rn(Bx, Ay), __fmul_rn(By, Ax));
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = U + V + W;
+    if (det == 0.0f) return false;
+    const float T = U * (r.Sz * Az0) + V * (r.Sz * Bz0) + W * (r.Sz * Cz0);
+    const float rcp = 1.0f / det;
+    t = T * rcp;
+    bu = V * rcp;
+    bv = W * rcp;
+    return true;
+}
+
+// BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
+// triangle index; any: stop at the first t in (tmin, tmax).  stk: this lane's LDS stack, stride
+// 64.  Returns the triangle (leaf order) or -1.
+template <int STACK>
+__device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
+                                        bool any, int* stk, uint32_t& n_nodes, uint32_t& n_tris,
+                                        float& hu, float& hv) {
+    int best = -1;
+    int best_orig = 0x7FFFFFFF;
+    float best_t = tmax;
+    int sp = 0;
+    int cur = 0;
+    const float ox = r.o.x, oy = r.o.y, oz = r.o.z;
+    const float ix = r.inv.x, iy = r.inv.y, iz = r.inv.z;
+    while (true) {
+        if (cur >= 0) {
+            ++n_nodes;
+            const float4* N = S.nodes + (size_t)cur * 8;
+            const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
+            const int4 ch = *reinterpret_cast<const int4*>(N + 6);
+            float k[4];
+            int c[4] = {ch.x, ch.y, ch.z, ch.w};
+            const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
+            const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
+            const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float t0x = (lxa[i] - ox) * ix, t1x = (hxa[i] - ox) * ix;
+                const float t0y = (lya[i] - oy) * iy, t1y = (hya[i] - oy) * iy;
+                const float t0z = (lza[i] - oz) * iz, t1z = (hza[i] - oz) * iz;
+                const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+                const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), best_t));
+                k[i] = (tn <= tf && c[i] != 0x7FFFFFFF) ? tn : FLT_MAX;
+            }
+            // sort descending (misses, keyed FLT_MAX, first; nearest hit last)
+#define GRW_CSWAP(i, j)                                  \
+    if (k[i] < k[j]) {                                   \
+        const float tk = k[i]; k[i] = k[j]; k[j] = tk;   \
+        const int tc = c[i]; c[i] = c[j]; c[j] = tc;     \
+    }
+            GRW_CSWAP(0, 1)
+            GRW_CSWAP(2, 3)
+            GRW_CSWAP(0, 2)
+            GRW_CSWAP(1, 3)
+            GRW_CSWAP(1, 2)
+#undef GRW_CSWAP
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (k[i] != FLT_MAX) stk[(sp++) * 64] = c[i];
+            if (k[3] != FLT_MAX) {
+                cur = c[3];
+                continue;
+            }
+        } else {
+            const int first = cur & 0x0FFFFFFF;
+            const int cnt = ((cur >> 28) & 7) + 1;
+            for (int i = 0; i < cnt; ++i) {
+                const float4* T = S.tris + (size_t)(first + i) * 3;
+                const float4 a = T[0], b = T[1], cc = T[2];
+                ++n_tris;
+                float t, u, v;
+                if (tri_isect(r, a, b, cc, t, u, v) && t > tmin) {
+                    const int orig = __float_as_int(a.w);
+                    if (t < best_t || (t == best_t && orig < best_orig)) {
+                        best_t = t;
+                        best = first + i;
+                        best_orig = orig;
+                        hu = u;
+                        hv = v;
+                        if (any) {
+                            tmax = best_t;
+                            return best;
+                        }
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        cur = stk[(--sp) * 64];
+    }
+    tmax = best_t;
+    return best;
+}
+
+__device__ __forceinline__ f3 ld3(const float* p) { return mk3(p[0], p[1], p[2]); }
+
+__device__ __forceinline__ unsigned long long wave_sum(uint32_t v) {
+    unsigned long long x = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+
+template <int STACK>
+__global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
+    __shared__ int lds_stack[4][STACK][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    int* stk = &lds_stack[wv][0][lane];
+
+    const SensorDev& sen = A.sensor;
+    const uint32_t Wd = (uint32_t)sen.W, Hd = (uint32_t)sen.H, nl = (uint32_t)A.nl;
+
+    bool live = false, exhausted = false;
+    uint64_t idx = 0, pid = 0;
+    int depth = 0;
+    f3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
+    float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
+    uint32_t c_paths = 0, c_seg = 0, c_sh = 0, c_ev = 0, c_bf = 0, c_nf = 0, c_nodes = 0, c_tris = 0;
+
+    while (true) {
+        if (!exhausted) {
+            const unsigned long long need = __ballot(!live);
+            if (need) {
+                const int first = __ffsll((long long)need) - 1;
+                const unsigned cnt = (unsigned)__popcll(need);
+                unsigned long long base = 0;
+                if (lane == first) base = atomicAdd(A.counter, (unsigned long long)cnt);
+                base = __shfl(base, first);
+                if (base + cnt >= A.n_paths) exhausted = true;
+                if (!live) {
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                    const uint64_t my = base + rank;
+                    if (my < A.n_paths) {
+                        // Sourcing (Sec. "Interactive Rendering"): mean position uniform on the
+                        // pixel, mean direction the sensor axis, beta^2 = 2 sigma^2, rho = 0,
+                        // alpha = 1.
+                        idx = my;
+                        const uint64_t sl = my / A.per_sample;
+                        const uint32_t rem = (uint32_t)(my - sl * A.per_sample);
+                        const uint32_t w = rem % nl;
+                        const uint32_t pix = rem / nl;
+                        const uint32_t x = pix % Wd, y = pix / Wd;
+                        const uint64_t s_abs = (uint64_t)A.spp_begin + sl;
+                        pid = ((s_abs * Hd + y) * Wd + x) * nl + w;
+                        k = kTwoPiF / A.lambda[w];
+                        const uint4 r0 = draw(pid, 0, STREAM_SOURCE, A.seed);
+                        const float fx = ((float)x + unif(r0.x)) * sen.pitch;
+                        const float fy = ((float)y + unif(r0.y)) * sen.pitch;
+                        o = mk3(sen.o[0] + fx * sen.u[0] + fy * sen.v[0],
+                                sen.o[1] + fx * sen.u[1] + fy * sen.v[1],
+                                sen.o[2] + fx * sen.u[2] + fy * sen.v[2]);
+                        d = mk3(sen.d[0], sen.d[1], sen.d[2]);
+                        beta2 = 2.0f * sen.sigma_um * sen.sigma_um;
+                        rho = 0.0f;
+                        alpha = 1.0f;
+                        contrib = 0.0f;
+                        depth = 0;
+                        live = true;
+                        ++c_paths;
+                    }
+                }
+            }
+        }
+        if (!__any(live)) break;
+        if (!live) continue;
+
+        // ---- one segment -------------------------------------------------------------
+        bool finish = false;
+        ++c_seg;
+        RayT ray;
+        ray_setup(ray, o, d);
+        const float tmin = 1e-7f * (1.0f + maxabs3(o));
+        float thit = FLT_MAX, bu = 0.0f, bv = 0.0f;
+        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, stk, c_nodes, c_tris, bu, bv);
+        if (tri < 0) {
+            finish = true;
+        } else {
+            // Free-space propagation of the generalized ray (eq. K_free_space_propagation)
+            // over the hit distance, zbar = z / |k0|, pre-update beta and rho on the right.
+            const float zb = thit * 1e6f / k;
+            const float orr = 1.0f + rho * rho;
+            const float rho_n = rho + zb * orr / beta2;
+            beta2 = beta2 + zb * (2.0f * rho + zb * orr / beta2);
+            rho = rho_n;
+            const f3 P = o + thit * d;
+            const float4* T = A.scene.tris + (size_t)tri * 3;
+            const float4 v0 = T[0], v1 = T[1], v2 = T[2];
+            const DMat m = A.scene.mats[__float_as_int(v1.w)];
+            f3 ng = normalize3(cross3(mk3(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z),
+                                      mk3(v2.x - v0.x, v2.y - v0.y, v2.z - v0.z)));
+            f3 ns = ng;
+            {
+                const float4* NN = A.scene.tnorm + (size_t)tri * 3;
+                const float4 n0 = NN[0], n1 = NN[1], n2 = NN[2];
+                if ((n0.x != 0.f || n0.y != 0.f || n0.z != 0.f) && (n1.x != 0.f || n1.y != 0.f || n1.z != 0.f) &&
+                    (n2.x != 0.f || n2.y != 0.f || n2.z != 0.f)) {
+                    const float w0 = 1.0f - bu - bv;
+                    ns = normalize3(mk3(w0 * n0.x + bu * n1.x + bv * n2.x, w0 * n0.y + bu * n1.y + bv * n2.y,
+                                        w0 * n0.z + bu * n1.z + bv * n2.z));
+                }
+            }
+            if (dot3(d, ng) > 0.0f) ng = -1.0f * ng;
+            if (dot3(ns, ng) < 0.0f) ns = -1.0f * ns;
+            const float ci = -dot3(d, ns);
+            if (ci <= 0.0f) {
+                ++c_bf;
+                finish = true;
+            } else {
+                // Tangent frame: x = grating direction (gratings), else the travel direction
+                // projected onto the surface.
+                f3 xa;
+                bool have = false;
+                if (m.kind == MAT_GRATING) {
+                    const f3 g = mk3(m.gx, m.gy, m.gz);
+                    const f3 t = g - dot3(g, ns) * ns;
+                    if (dot3(t, t) > 1e-18f) {
+                        xa = normalize3(t);
+                        have = true;
+                    }
+                }
+                if (!have) {
+                    const f3 t = d - dot3(d, ns) * ns;
+                    if (dot3(t, t) > 1e-24f) {
+                        xa = normalize3(t);
+                    } else {
+                        const f3 a = fabsf(ns.x) < 0.9f ? mk3(1, 0, 0) : mk3(0, 1, 0);
+                        xa = normalize3(cross3(ns, a));
+                    }
+                }
+                const f3 ya = cross3(ns, xa);
+                // Footprint on the surface: beam variance beta^2/2, stretched by 1/cos along
+                // the plane of incidence.
+                const float sr2 = 0.5f * beta2;
+                const float dx = dot3(d, xa), dy = dot3(d, ya);
+                const float ic2 = 1.0f / (ci * ci);
+                const float sxx = sr2 * (1.0f + dx * dx * ic2);
+                const float syy = sr2 * (1.0f + dy * dy * ic2);
+                const float sxy = sr2 * (dx * dy * ic2);
+
+                // Measurement by next-event estimation (eq. measurement_operator).
+                if (A.nsrc > 0) {
+                    const uint4 rn = draw(pid, (uint32_t)depth, STREAM_NEE, A.seed);
+                    const int si = min((int)(unif(rn.x) * (float)A.nsrc), A.nsrc - 1);
+                    const SourceDev& L = A.src[si];
+                    f3 om = mk3(0, 0, 0);
+                    bool ok = false;
+                    float tmax_s = FLT_MAX;
+                    const float tminP = 1e-7f * (1.0f + maxabs3(P));
+                    if (L.kind == 0) {
+                        om = ld3(L.dir);
+                        ok = true;
+                    } else {
+                        float z1, z2;
+                        box_muller(unif(rn.y), unif(rn.z), z1, z2);
+                        const float du = z1 / L.rc_um, dv = z2 / L.rc_um;
+                        const float tt = (du * du + dv * dv) / (k * k);
+                        if (tt < 1.0f) {
+                            const f3 ax = ld3(L.dir), eu = ld3(L.bu), ev = ld3(L.bv);
+                            om = (du / k) * eu + (dv / k) * ev + sqrtf(1.0f - tt) * ax;
+                            const f3 pos = ld3(L.pos);
+                            const float te = dot3(pos - P, ax) / (-dot3(om, ax));
+                            if (te > tminP) {
+                                const f3 Q = P - te * om;
+                                const float a = dot3(Q - pos, eu) / L.lu, b = dot3(Q - pos, ev) / L.lv;
+                                if (fabsf(a) <= 1.0f && fabsf(b) <= 1.0f) {
+                                    ok = true;
+                                    tmax_s = te;
+                                }
+                            }
+                        }
+                    }
+                    if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
+                        ++c_sh;
+                        RayT sray;
+                        ray_setup(sray, P, -1.0f * om);
+                        float tm = tmax_s, su, sv;
+                        const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, stk, c_nodes, c_tris, su, sv);
+                        if (occ < 0) {
+                            const float p = pw_plain(m.kind, m.h, m.L, m.refl, k, k * dot3(om, xa),
+                                                     k * dot3(om, ya), -k * dx, -k * dy, sxx, syy, sxy,
+                                                     1.0f, 0.0f);
+                            contrib += alpha * L.power * p * (float)A.nsrc;
+                        }
+                    }
+                }
+                if (depth + 1 >= A.max_depth) {
+                    finish = true;
+                } else {
+                    // Light-matter interaction: sample the continuation generalized ray.
+                    const uint4 rs = draw(pid, (uint32_t)depth, STREAM_SCATTER, A.seed);
+                    float kox, koy, wgt;
+                    if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt)) {
+                        ++c_ev;
+                        finish = true;
+                    } else {
+                        alpha *= wgt;
+                        if (A.rr_enable && depth + 1 >= 2) {
+                            if ((rs.w >> 8) < A.rr_thr) alpha *= A.inv_rr_p;
+                            else finish = true;
+                        }
+                        if (!finish) {
+                            const float kn = sqrtf(fmaxf(0.0f, 1.0f - (kox * kox + koy * koy) / (k * k)));
+                            d = normalize3((kox / k) * xa + (koy / k) * ya + kn * ns);
+                            o = P;
+                            ++depth;
+                        }
+                    }
+                }
+            }
+        }
+        if (finish) {
+            float val = contrib * A.inv_spp_norm;
+            if (!isfinite(val)) {
+                ++c_nf;
+                val = 0.0f;
+            }
+            A.records[idx] = val;
+            live = false;
+        }
+    }
+
+    const unsigned long long s0 = wave_sum(c_paths), s1 = wave_sum(c_seg), s2 = wave_sum(c_sh),
+                             s5 = wave_sum(c_ev), s6 = wave_sum(c_bf), s7 = wave_sum(c_nf),
+                             s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris);
+    if (lane == 0) {
+        atomicAdd(A.stats + ST_PATHS, s0);
+        atomicAdd(A.stats + ST_SEGMENTS, s1);
+        atomicAdd(A.stats + ST_SHADOW, s2);
+        atomicAdd(A.stats + ST_EVANESCENT, s5);
+        atomicAdd(A.stats + ST_BACKFACING, s6);
+        atomicAdd(A.stats + ST_NONFINITE, s7);
+        atomicAdd(A.stats + ST_NODES, s8);
+        atomicAdd(A.stats + ST_TRIS, s9);
+    }
+}
+
+// Per-pixel sum of the path records in sample order (deterministic).
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ rec, float* __restrict__ img,
+                                                     int64_t S, uint32_t H, uint32_t W, uint32_t nl) {
+    const uint32_t per = H * W * nl;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per) return;
+    float acc = 0.0f;
+    for (int64_t s = 0; s < S; ++s) acc += rec[(size_t)s * per + t];
+    const uint32_t w = t % nl;
+    const uint32_t pix = t / nl;
+    img[(size_t)w * H * W + pix] += acc;
+}
+
+__global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict__ q, int64_t n,
+                                                        float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* r = q + i * 14;
+    out[i] = pw_plain((int)r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9], r[10], r[11],
+                      r[12], r[13]);
+}
+
+template <int STACK>
+static int grid_for(int device) {
+    int ncu = 0, nb = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<STACK>, 256, 0) != hipSuccess) return 0;
+    return ncu * (nb > 0 ? nb : 1);
+}
+
+int trace_grid_size(int device, int stack_depth) {
+    if (stack_depth <= 32) return grid_for<32>(device);
+    if (stack_depth <= 64) return grid_for<64>(device);
+    return grid_for<96>(device);
+}
+
+hipError_t launch_trace(const TraceArgs& a, int stack_depth, int grid, hipStream_t s) {
+    if (stack_depth <= 32) hipLaunchKernelGGL(trace_kernel<32>, dim3(grid), dim3(256), 0, s, a);
+    else if (stack_depth <= 64) hipLaunchKernelGGL(trace_kernel<64>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(trace_kernel<96>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
+                         uint32_t nl, hipStream_t s) {
+    const uint32_t per = H * W * nl;
+    hipLaunchKernelGGL(reduce_kernel, dim3((per + 255) / 256), dim3(256), 0, s, records, image, spp_count,
+                       H, W, nl);
+    return hipGetLastError();
+}
+
+hipError_t launch_bsdf_eval(const float* q, int64_t n, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(bsdf_eval_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace grw
