@@ -371,11 +371,14 @@ bool box_hit(const Node& n, V3 o, V3 d, double tmax, double& tnear) {
 struct Hit { int tri; double t, u, v; };
 
 // Closest hit along o + t d, t in (tmin, tmax).  any=true stops at the first hit found.
+// skip: the triangle the ray leaves (a flat triangle cannot be hit again by a ray leaving
+// it), or -1.
 bool trace_ray(const SceneO& S, V3 o, V3 d, double tmin, double tmax, bool use_bvh, bool any,
-               Hit& h) {
+               Hit& h, int skip = -1) {
     h.tri = -1;
     h.t = tmax;
     auto consider = [&](int ti) {
+        if (ti == skip) return;
         double t, u, v;
         if (isect_tri(S.tris[ti], o, d, tmin, t, u, v) && t < tmax) {
             if (t < h.t || (t == h.t && ti < h.tri)) { h.t = t; h.u = u; h.v = v; h.tri = ti; }
@@ -464,11 +467,13 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
     double rho = 0.0;
     double alpha = 1.0;
     double contrib = 0.0;
+    int prev = -1;   // triangle the current segment leaves
 
     for (int depth = 0; depth < op.max_depth; ++depth) {
         st.segments++;
         Hit h;
-        if (!trace_ray(S, o, d, t_eps(o), 1e300, op.use_bvh != 0, false, h)) break;
+        if (!trace_ray(S, o, d, t_eps(o), 1e300, op.use_bvh != 0, false, h, prev)) break;
+        prev = h.tri;
         // Free-space propagation of the generalized ray over the hit distance
         // (eq. K_free_space_propagation), with zbar = z / |k0| and the pre-update beta, rho.
         double z = h.t * 1e6;
@@ -538,7 +543,7 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
             if (ok && dot(om, ng) < 0.0 && dot(om, ns) < 0.0) {
                 st.shadow++;
                 Hit hs;
-                bool occ = trace_ray(S, P, -1.0 * om, t_eps(P), tmax, op.use_bvh != 0, true, hs);
+                bool occ = trace_ray(S, P, -1.0 * om, t_eps(P), tmax, op.use_bvh != 0, true, hs, h.tri);
                 if (!occ) {
                     double kix = k * dot(om, xa), kiy = k * dot(om, ya);
                     double kox = -k * dx, koy = -k * dy;

@@ -84,12 +84,13 @@ __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, f
 }
 
 // BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
-// triangle index; any: stop at the first t in (tmin, tmax).  stk: this lane's LDS stack, stride
-// 64.  Returns the triangle (leaf order) or -1.
+// triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
+// triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack, stride 64.
+// Returns the triangle (leaf order) or -1.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
-                                        bool any, int* stk, uint32_t& n_nodes, uint32_t& n_tris,
-                                        float& hu, float& hv) {
+                                        bool any, int skip, int* stk, uint32_t& n_nodes,
+                                        uint32_t& n_tris, float& hu, float& hv) {
     int best = -1;
     int best_orig = 0x7FFFFFFF;
     float best_t = tmax;
@@ -143,9 +144,9 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 const float4* T = S.tris + (size_t)(first + i) * 3;
                 const float4 a = T[0], b = T[1], cc = T[2];
                 ++n_tris;
+                const int orig = __float_as_int(a.w);
                 float t, u, v;
-                if (tri_isect(r, a, b, cc, t, u, v) && t > tmin) {
-                    const int orig = __float_as_int(a.w);
+                if (orig != skip && tri_isect(r, a, b, cc, t, u, v) && t > tmin) {
                     if (t < best_t || (t == best_t && orig < best_orig)) {
                         best_t = t;
                         best = first + i;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
 
     bool live = false, exhausted = false;
     uint64_t idx = 0, pid = 0;
-    int depth = 0;
+    int depth = 0, prev = -1;
     f3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
     uint32_t c_paths = 0, c_seg = 0, c_sh = 0, c_ev = 0, c_bf = 0, c_nf = 0, c_nodes = 0, c_tris = 0;
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                         alpha = 1.0f;
                         contrib = 0.0f;
                         depth = 0;
+                        prev = -1;
                         live = true;
                         ++c_paths;
                     }
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
         ray_setup(ray, o, d);
         const float tmin = 1e-7f * (1.0f + maxabs3(o));
         float thit = FLT_MAX, bu = 0.0f, bv = 0.0f;
-        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, stk, c_nodes, c_tris, bu, bv);
+        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk, c_nodes, c_tris, bu, bv);
         if (tri < 0) {
             finish = true;
         } else {
@@ -262,6 +264,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
             const f3 P = o + thit * d;
             const float4* T = A.scene.tris + (size_t)tri * 3;
             const float4 v0 = T[0], v1 = T[1], v2 = T[2];
+            prev = __float_as_int(v0.w);
             const DMat m = A.scene.mats[__float_as_int(v1.w)];
             f3 ng = normalize3(cross3(mk3(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z),
                                       mk3(v2.x - v0.x, v2.y - v0.y, v2.z - v0.z)));
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                         RayT sray;
                         ray_setup(sray, P, -1.0f * om);
                         float tm = tmax_s, su, sv;
-                        const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, stk, c_nodes, c_tris, su, sv);
+                        const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, c_nodes, c_tris, su, sv);
                         if (occ < 0) {
                             const float p = pw_plain(m.kind, m.h, m.L, m.refl, k, k * dot3(om, xa),
                                                      k * dot3(om, ya), -k * dx, -k * dy, sxx, syy, sxy,
