@@ -63,7 +63,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--surrogate", action="store_true", help="also time the surrogate mode")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (scales the "
+                         "HBM byte counters of a profiler run)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the tracer is data-parallel over samples and the "
               "multi-GPU split is not built (see the sharding notes).", file=sys.stderr)

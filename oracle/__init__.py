@@ -97,7 +97,7 @@ def lib():
                                    C.POINTER(C.c_int32), C.c_int64, dp, dp,
                                    C.POINTER(C.c_uint64)]
             L.or_trace.restype = C.c_int
-            L.or_coherent_mc.argtypes = [C.POINTER(OrCoherent), dp, C.c_int32]
+            L.or_coherent_mc.argtypes = [C.POINTER(OrCoherent), dp, C.c_int32, C.c_int32]
             L.or_coherent_exact.argtypes = [C.POINTER(OrCoherent), C.POINTER(C.c_int32),
                                             C.c_int64, dp, dp, C.c_int32, dp, dp, C.c_int32, dp]
             L.or_hankel1_re.argtypes = [C.c_double]
@@ -316,16 +316,16 @@ def _coh_struct(case, xs, ws, spp=None):
     return st
 
 
-def coherent_mc(case, n_per_slit=16, n_threads=0, height=None):
-    """Per-sample estimator of the coherent measurement, [height, width]."""
+def coherent_mc(case, n_per_slit=16, n_threads=0, rows=None):
+    """Per-sample estimator of the coherent measurement, [rows, width] (the leading rows of
+    the case's sensor; sample streams use its full height)."""
     xs, ws = coherent_nodes(case, n_per_slit)
     xs = np.ascontiguousarray(xs)
     ws = np.ascontiguousarray(ws)
     st = _coh_struct(case, xs, ws)
-    if height is not None:
-        st.height = height
-    out = np.empty((st.height, case.width))
-    lib().or_coherent_mc(C.byref(st), _dp(out), n_threads)
+    rows = case.height if rows is None else rows
+    out = np.empty((rows, case.width))
+    lib().or_coherent_mc(C.byref(st), _dp(out), n_threads, rows)
     return out
 
 

@@ -774,10 +774,12 @@ static std::complex<double> field_at(const or_coherent& c, double X, double Y) {
 // Per-sample Monte Carlo estimator with the shared random streams: sample s of pixel (x, y)
 // draws (u0, u1) on the pixel and a Gaussian offset (Box-Muller of u2, u3) of the detection
 // state.  out: [height][width] mean of |U|^2 over the spp samples.
-void or_coherent_mc(const or_coherent* c, double* out, int32_t n_threads) {
+// rows: number of leading sensor rows to compute (<= height; path ids use the full height).
+void or_coherent_mc(const or_coherent* c, double* out, int32_t n_threads, int32_t rows) {
     int nt = n_threads > 0 ? n_threads : (int)std::thread::hardware_concurrency();
     std::atomic<int64_t> next(0);
-    int64_t np = (int64_t)c->width * c->height;
+    if (rows <= 0 || rows > c->height) rows = c->height;
+    int64_t np = (int64_t)c->width * rows;
     auto work = [&]() {
         for (;;) {
             int64_t p = next.fetch_add(1);

@@ -15,6 +15,9 @@
 #include "kernels.hpp"
 #include "surrogate.hpp"
 
+extern "C" int grw_coherent_launch(const gr_coherent_desc* d, float* image, hipStream_t stream, float* ms,
+                                   char* err, size_t errn);
+
 struct gr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -401,6 +404,15 @@ int gr_bsdf_eval(gr_ctx* c, const float* q, int64_t n, int32_t mode, float* out)
     } else {
         GR_HIP(c, grw::launch_bsdf_eval_surrogate(c->sur, q, n, out, c->stream));
     }
+    return GR_OK;
+}
+
+int gr_coherent_measure(gr_ctx* c, const gr_coherent_desc* d, float* image, float* ms) {
+    if (!c) return GR_E_INVALID;
+    GR_HIP(c, hipSetDevice(c->device));
+    char buf[256] = {0};
+    const int rc = grw_coherent_launch(d, image, c->stream, ms, buf, sizeof(buf));
+    if (rc != GR_OK) return fail(c, rc, "%s", buf);
     return GR_OK;
 }
 

@@ -39,5 +39,4 @@ int gr_adam_step(gr_ctx*, float*, const float*, float*, float*, int32_t, float, 
     return GR_E_UNSUPPORTED;
 }
 int gr_set_surrogate(gr_ctx*, const float*, const float*) { return GR_E_UNSUPPORTED; }
-int gr_coherent_measure(gr_ctx*, const gr_coherent_desc*, float*, float*) { return GR_E_UNSUPPORTED; }
 }

@@ -194,3 +194,29 @@ class Renderer:
         self._check(self.lib.gr_bsdf_eval(self.h, _fptr(q), q.shape[0], int(mode), _fptr(out)),
                     "gr_bsdf_eval")
         return out
+
+    # -- coherent measurement -------------------------------------------------------------
+    def coherent(self, case, phase_mode=1, nodes_per_slit=16, timing=False):
+        """Coherent measurement of a two-point / double-slit case (workloads.CoherentCase).
+        phase_mode: 0 FP32, 1 FP64, 2 two-float.  Returns (image [H, W] tensor, ms or None)."""
+        d = L.GrCoherentDesc()
+        d.kind = 0 if case.kind == "points" else 1
+        c = list(np.asarray(case.centres_um, np.float64))
+        d.n_slits = len(c)
+        d.centre_um = (C.c_double * 8)(*(c + [0.0] * (8 - len(c))))
+        d.width_um = float(case.width_um)
+        d.nodes_per_slit = int(nodes_per_slit)
+        d.phase_mode = int(phase_mode)
+        d.z_um = float(case.z_m * 1e6)
+        d.lambda_um = float(case.lambda_um)
+        d.width = int(case.width)
+        d.height = int(case.height)
+        d.pitch_um = float(case.pitch_um)
+        d.sigma_um = float(case.sigma_um)
+        d.spp = int(case.spp)
+        d.seed = int(case.seed)
+        img = self.torch.empty((case.height, case.width), dtype=self.torch.float32, device=self.dev)
+        ms = C.c_float(0.0)
+        rc = self.lib.gr_coherent_measure(self.h, C.byref(d), _fptr(img), C.byref(ms) if timing else None)
+        self._check(rc, "gr_coherent_measure")
+        return img, (ms.value if timing else None)
