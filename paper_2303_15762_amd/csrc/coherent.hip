@@ -35,33 +35,43 @@ struct CohArgs {
 };
 
 // ---- two-float arithmetic --------------------------------------------------------------
+// Error-free transformations need every rounding to happen where it is written, so FP
+// contraction is switched off in them (a rounded product fused into a later add would count
+// its rounding error twice).  Plain operators are used: the pragma governs only operations
+// written in its scope, not those inside library intrinsics.
 struct df {
     float hi, lo;
 };
-__device__ __forceinline__ df two_sum(float a, float b) {
+__device__ __forceinline__ df two_sum(float a, float b) {          // Knuth
+#pragma clang fp contract(off)
     const float s = a + b;
     const float bb = s - a;
     return df{s, (a - (s - bb)) + (b - bb)};
 }
-__device__ __forceinline__ df quick_two_sum(float a, float b) {
+__device__ __forceinline__ df quick_two_sum(float a, float b) {    // |a| >= |b|
+#pragma clang fp contract(off)
     const float s = a + b;
     return df{s, b - (s - a)};
 }
-__device__ __forceinline__ df two_prod(float a, float b) {
+__device__ __forceinline__ df two_prod(float a, float b) {         // exact by FMA
+#pragma clang fp contract(off)
     const float p = a * b;
     return df{p, fmaf(a, b, -p)};
 }
 __device__ __forceinline__ df df_add(df x, df y) {
+#pragma clang fp contract(off)
     df s = two_sum(x.hi, y.hi);
-    s.lo += x.lo + y.lo;
+    s.lo = s.lo + (x.lo + y.lo);
     return quick_two_sum(s.hi, s.lo);
 }
 __device__ __forceinline__ df df_mul(df x, df y) {
+#pragma clang fp contract(off)
     df p = two_prod(x.hi, y.hi);
-    p.lo += x.hi * y.lo + x.lo * y.hi;
+    p.lo = p.lo + (x.hi * y.lo + x.lo * y.hi);
     return quick_two_sum(p.hi, p.lo);
 }
-__device__ __forceinline__ df df_sqrt(df x) {
+__device__ __forceinline__ df df_sqrt(df x) {                       // one Newton correction
+#pragma clang fp contract(off)
     const float s = sqrtf(x.hi);
     const df p = two_prod(s, s);
     const float diff = ((x.hi - p.hi) - p.lo) + x.lo;

@@ -55,6 +55,9 @@ __device__ __forceinline__ void ray_setup(RayT& r, f3 o, f3 d) {
 // crosses the triangle (edges inclusive, shared edges decided consistently).
 __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, float4 c4, float& t,
                                           float& bu, float& bv) {
+    // no FP contraction here: an edge shared by two triangles must get exactly opposite edge
+    // function values (a fused multiply-add would round the two orientations differently)
+#pragma clang fp contract(off)
     const f3 A = mk3(a4.x - r.o.x, a4.y - r.o.y, a4.z - r.o.z);
     const f3 B = mk3(b4.x - r.o.x, b4.y - r.o.y, b4.z - r.o.z);
     const f3 C = mk3(c4.x - r.o.x, c4.y - r.o.y, c4.z - r.o.z);
@@ -62,11 +65,9 @@ __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, f
     const float Ax = comp(A, r.kx) - r.Sx * Az0, Ay = comp(A, r.ky) - r.Sy * Az0;
     const float Bx = comp(B, r.kx) - r.Sx * Bz0, By = comp(B, r.ky) - r.Sy * Bz0;
     const float Cx = comp(C, r.kx) - r.Sx * Cz0, Cy = comp(C, r.ky) - r.Sy * Cz0;
-    // edge functions with explicit rounding (no contraction), so that an edge shared by two
-    // triangles gets exactly opposite values
-    float U = __fsub_rn(__fmul_rn(Cx, By), __fmul_rn(Cy, Bx));
-    float V = __fsub_rn(__fmul_rn(Ax, Cy), __fmul_rn(Ay, Cx));
-    float W = __fsub_rn(__fmul_rn(Bx, Ay), __fmul_rn(By, Ax));
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
     if (U == 0.0f || V == 0.0f || W == 0.0f) {
         U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
         V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
