@@ -195,33 +195,40 @@ int gr_trace(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_tra
  * where the query is inside its domain and the closed form elsewhere.  out: device [n]. */
 int gr_bsdf_eval(gr_ctx* ctx, const float* queries, int64_t n, int32_t mode, float* out);
 
-/* Draw n training queries for the learned scattering model and their targets log p_w
- * (closed form), on the device.  box: host [10] lo/hi pairs of (lambda, s, ell, log sigma_x
- * ..., see the surrogate section); x_out: device [n][10] network inputs; y_out: device [n];
- * q_out: device [n][14] raw queries (may be NULL). */
-int gr_surrogate_samples(gr_ctx* ctx, int64_t n, uint64_t seed, float* x_out, float* y_out,
-                         float* q_out);
-
-/* Learned scattering model: 10 -> 64 -> 64 -> 64 -> 64 -> 1 perceptron with GELU.
+/* Learned scattering model (the surrogate of p_w for Gaussian rough surfaces): a
+ * 10 -> 64 -> 64 -> 64 -> 64 -> 1 perceptron with GELU (tanh form).
  * params: device float [13249] laid out W1[10][64], b1[64], W2[64][64], b2, W3, b3, W4, b4,
- * W5[64][1], b5[1] (row-major [fan_in][fan_out]).  The BF16 path rounds weights and
- * activations to bfloat16 for the matrix cores and accumulates in FP32. */
+ * W5[64][1], b5[1] (row-major [fan_in][fan_out]; a layer computes x W + b).  The matrix-core
+ * passes round weights and activations to bfloat16 and accumulate in FP32.
+ *
+ * Input encoding of a query (sur_encode in the sources; rough surfaces only): the tangential
+ * transfer in lobe widths sqrt(2 g) / l (g = (q_z s)^2), the incident tangential direction,
+ * log wavelength, log footprint std devs (diagonal footprint), log s, log l, log g, each
+ * affinely scaled to about [-1, 1]; the output is log p_w minus log(l^2 / (4 pi g)).
+ * domain (host [4]): {g_min, g_max, sigma_min_um, sigma_max_um} of the queries the network
+ * covers; elsewhere the closed form is used. */
 enum { GR_MLP_PARAMS = 13249 };
-int gr_mlp_forward(gr_ctx* ctx, const float* params, const float* x, int64_t n, int32_t dtype,
-                   float* y);
-/* Mean-squared-error gradient of the batch (x [n][10], target [n]) into grad (device float
- * [13249], overwritten) and the loss into loss_dev (device float [1]).  workspace: device,
- * >= gr_mlp_workspace_size(n) bytes. */
+
+/* Draw n training samples on the device: x_out [n][10] encoded inputs, y_out [n] targets
+ * (closed-form log p_w relative to the lobe peak, floored at -20), q_out [n][14] the raw
+ * queries in the gr_bsdf_eval row layout (may be NULL).  Deterministic in seed. */
+int gr_surrogate_samples(gr_ctx* ctx, int64_t n, uint64_t seed, const float* domain, float* x_out,
+                         float* y_out, float* q_out);
+/* Device workspace for gr_mlp_forward / gr_mlp_backward on n rows. */
 int gr_mlp_workspace_size(int64_t n, size_t* bytes);
+/* y [n] = network(x [n][10]); dtype GR_BSDF_SURROGATE_BF16. */
+int gr_mlp_forward(gr_ctx* ctx, const float* params, const float* x, int64_t n, int32_t dtype,
+                   void* workspace, float* y);
+/* Gradient of the mean squared error (1/n) sum (network(x_i) - target_i)^2 into grad (device
+ * float [13249], overwritten; deterministic) and the loss into loss_dev (device float [1]). */
 int gr_mlp_backward(gr_ctx* ctx, const float* params, const float* x, const float* target,
                     int64_t n, void* workspace, float* grad, float* loss_dev);
-/* Adam (bias-corrected) update of params in place with first/second moments m, v (device
- * float [13249] each, start at zero); step t >= 1. */
+/* Adam (Kingma & Ba, bias-corrected) update of params in place; m, v device float [13249]
+ * moments (start at zero); step t >= 1. */
 int gr_adam_step(gr_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t t,
                  float lr, float beta1, float beta2, float eps);
-/* Install a trained network for the surrogate trace modes.  params: device [13249] FP32
- * (converted to BF16 and FP8 internally).  domain: host [4] = {min g, max g, min footprint
- * sigma (um), max footprint sigma (um)}: rough-surface queries inside it use the network. */
+/* Install a trained network for GR_BSDF_SURROGATE_BF16 (copied and packed on the device;
+ * allocates on first use). */
 int gr_set_surrogate(gr_ctx* ctx, const float* params, const float* domain);
 
 /* Coherent measurement of mutually coherent emitters (Sec. "Linearity of Generalized Rays",

@@ -3,8 +3,8 @@ backward pass and Adam update.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Network: 10 inputs -> 4 hidden layers of width 64 with GELU -> 1 output.  GELU is the exact
-form x * Phi(x) with Phi the standard normal CDF.  Weights W[l] have shape [fan_in, fan_out];
+Network: 10 inputs -> 4 hidden layers of width 64 with GELU -> 1 output.  GELU is the tanh
+form 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))).  Weights W[l] have shape [fan_in, fan_out];
 a layer computes Y = X @ W + b.
 """
 
@@ -13,18 +13,20 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy.special import erfc
 
 SIZES = (10, 64, 64, 64, 64, 1)
 
 
+C0 = math.sqrt(2.0 / math.pi)
+
+
 def gelu(x):
-    # Phi(x) = erfc(-x / sqrt 2) / 2, free of cancellation for negative x
-    return 0.5 * x * erfc(-x / math.sqrt(2.0))
+    return 0.5 * x * (1.0 + np.tanh(C0 * (x + 0.044715 * x ** 3)))
 
 
 def gelu_grad(x):
-    return 0.5 * erfc(-x / math.sqrt(2.0)) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
+    t = np.tanh(C0 * (x + 0.044715 * x ** 3))
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * C0 * (1.0 + 3 * 0.044715 * x * x)
 
 
 def init_params(seed=0, sizes=SIZES):

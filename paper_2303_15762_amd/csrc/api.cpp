@@ -285,6 +285,8 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
         return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
     if (o->bsdf_mode == GR_BSDF_SURROGATE_FP8) return fail(c, GR_E_UNSUPPORTED, "trace: FP8 surrogate in the tracer");
+    if (o->bsdf_mode != GR_BSDF_PLAIN && (c->sensor.width * (int64_t)c->sensor.height < 1))
+        return fail(c, GR_E_INVALID, "trace: sensor");
     size_t need = 0;
     gr_workspace_size(c, o, nl, &need);
     if (!ws || ws_bytes < need) return fail(c, GR_E_WORKSPACE, "trace: workspace %zu < %zu bytes", ws_bytes, need);
@@ -351,9 +353,10 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
 
     GR_HIP(c, hipSetDevice(c->device));
     const int stack = stack_for_depth(c->bvh_depth);
-    if (c->grid_stack != stack) {
-        c->grid = grw::trace_grid_size(c->device, stack);
-        c->grid_stack = stack;
+    const int key = stack * 4 + o->bsdf_mode;
+    if (c->grid_stack != key) {
+        c->grid = grw::trace_grid_size(c->device, stack, o->bsdf_mode == GR_BSDF_SURROGATE_BF16);
+        c->grid_stack = key;
         if (c->grid <= 0) return fail(c, GR_E_DEVICE, "trace: occupancy query failed");
     }
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -413,6 +416,67 @@ int gr_coherent_measure(gr_ctx* c, const gr_coherent_desc* d, float* image, floa
     char buf[256] = {0};
     const int rc = grw_coherent_launch(d, image, c->stream, ms, buf, sizeof(buf));
     if (rc != GR_OK) return fail(c, rc, "%s", buf);
+    return GR_OK;
+}
+
+static bool domain_ok(const float* d) {
+    return d && d[0] > 0.0f && d[1] >= d[0] && d[2] > 0.0f && d[3] >= d[2] && std::isfinite(d[1]) &&
+           std::isfinite(d[3]);
+}
+
+int gr_surrogate_samples(gr_ctx* c, int64_t n, uint64_t seed, const float* domain, float* x, float* y, float* q) {
+    if (!c) return GR_E_INVALID;
+    if (n < 0 || (n > 0 && (!x || !y))) return fail(c, GR_E_INVALID, "surrogate_samples: arguments");
+    if (!domain_ok(domain)) return fail(c, GR_E_INVALID, "surrogate_samples: domain");
+    GR_HIP(c, hipSetDevice(c->device));
+    GR_HIP(c, grw::surrogate_samples(n, seed, domain, x, y, q, c->stream));
+    return GR_OK;
+}
+
+int gr_mlp_workspace_size(int64_t n, size_t* bytes) {
+    if (n < 0 || !bytes) return GR_E_INVALID;
+    *bytes = grw::mlp_workspace_bytes(n);
+    return GR_OK;
+}
+
+int gr_mlp_forward(gr_ctx* c, const float* params, const float* x, int64_t n, int32_t dtype, void* ws, float* y) {
+    if (!c) return GR_E_INVALID;
+    if (!params || !ws || n < 0 || (n > 0 && (!x || !y))) return fail(c, GR_E_INVALID, "mlp_forward: arguments");
+    if (dtype != GR_BSDF_SURROGATE_BF16) return fail(c, GR_E_UNSUPPORTED, "mlp_forward: only BF16 operands");
+    if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) return fail(c, GR_E_INVALID, "mlp_forward: workspace alignment");
+    GR_HIP(c, hipSetDevice(c->device));
+    GR_HIP(c, grw::mlp_forward(params, x, n, ws, y, c->stream));
+    return GR_OK;
+}
+
+int gr_mlp_backward(gr_ctx* c, const float* params, const float* x, const float* t, int64_t n, void* ws, float* grad,
+                    float* loss) {
+    if (!c) return GR_E_INVALID;
+    if (!params || !x || !t || !ws || !grad || !loss || n < 1) return fail(c, GR_E_INVALID, "mlp_backward: arguments");
+    if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) return fail(c, GR_E_INVALID, "mlp_backward: workspace alignment");
+    GR_HIP(c, hipSetDevice(c->device));
+    GR_HIP(c, grw::mlp_backward(params, x, t, n, ws, grad, loss, c->stream));
+    return GR_OK;
+}
+
+int gr_adam_step(gr_ctx* c, float* p, const float* g, float* m, float* v, int32_t t, float lr, float b1, float b2,
+                 float eps) {
+    if (!c) return GR_E_INVALID;
+    if (!p || !g || !m || !v || t < 1 || !(lr > 0.0f) || !(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f) ||
+        !(eps > 0.0f))
+        return fail(c, GR_E_INVALID, "adam_step: arguments");
+    GR_HIP(c, hipSetDevice(c->device));
+    GR_HIP(c, grw::adam(p, g, m, v, t, lr, b1, b2, eps, c->stream));
+    return GR_OK;
+}
+
+int gr_set_surrogate(gr_ctx* c, const float* params, const float* domain) {
+    if (!c) return GR_E_INVALID;
+    if (!params || !domain_ok(domain)) return fail(c, GR_E_INVALID, "set_surrogate: arguments");
+    GR_HIP(c, hipSetDevice(c->device));
+    const hipError_t e = grw::surrogate_set(c->sur, params, domain, c->stream);
+    if (e == hipErrorOutOfMemory) return fail(c, GR_E_OOM, "set_surrogate: allocation failed");
+    if (e != hipSuccess) return fail(c, GR_E_DEVICE, "set_surrogate: %s", hipGetErrorString(e));
     return GR_OK;
 }
 

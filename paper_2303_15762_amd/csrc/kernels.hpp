@@ -37,9 +37,10 @@ struct SourceDev {
 
 // Surrogate (learned p_w) parameters prepared for the matrix cores.
 struct SurrogateDev {
-    const uint16_t* w_bf16;   // packed weights, see mlp.hip
-    const float* bias;        // [4 * 64 + 1]
-    const float* w_out;       // [64]
+    const void* wf;           // packed BF16 weights (mlp_core.hpp layout)
+    const float* bias;        // [4][64]
+    const float* w5;          // [64]
+    const float* b5;          // [1]
     float gmin, gmax, smin, smax;
     int enabled;
 };
@@ -76,7 +77,7 @@ enum {
 hipError_t launch_trace(const TraceArgs& a, int stack_depth, int grid, hipStream_t s);
 hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
                          uint32_t nl, hipStream_t s);
-int trace_grid_size(int device, int stack_depth);
+int trace_grid_size(int device, int stack_depth, bool sur);
 
 // Batch p_w evaluation (trace.hip).
 hipError_t launch_bsdf_eval(const float* q, int64_t n, float* out, hipStream_t s);

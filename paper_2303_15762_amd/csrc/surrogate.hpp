@@ -1,4 +1,4 @@
-// Learned scattering model (perceptron surrogate of p_w): device state and launchers.
+// Learned scattering model (perceptron surrogate of p_w): host-side state and entry points.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,9 +10,8 @@ namespace grw {
 
 struct SurrogateState {
     bool ready = false;
-    uint16_t* d_wpack = nullptr;   // BF16 weights in matrix-core operand order
-    float* d_bias = nullptr;       // hidden biases [4][64] then the output bias
-    float* d_wout = nullptr;       // output layer weights [64]
+    void* d_pack = nullptr;      // weights in matrix-core operand order + hidden biases
+    float* d_params = nullptr;   // FP32 copy of the installed parameters
     float domain[4] = {0, 0, 0, 0};
 };
 
@@ -20,5 +19,14 @@ void surrogate_free(SurrogateState& s);
 void surrogate_fill(const SurrogateState& s, SurrogateDev& d);
 hipError_t launch_bsdf_eval_surrogate(const SurrogateState& s, const float* q, int64_t n, float* out,
                                       hipStream_t stream);
+size_t mlp_workspace_bytes(int64_t n);
+hipError_t mlp_forward(const float* params, const float* x, int64_t n, void* ws, float* y, hipStream_t s);
+hipError_t mlp_backward(const float* params, const float* x, const float* t, int64_t n, void* ws, float* grad,
+                        float* loss, hipStream_t s);
+hipError_t adam(float* p, const float* g, float* m, float* v, int t, float lr, float b1, float b2, float eps,
+                hipStream_t s);
+hipError_t surrogate_samples(int64_t n, uint64_t seed, const float* domain, float* x, float* y, float* q,
+                             hipStream_t s);
+hipError_t surrogate_set(SurrogateState& st, const float* params, const float* domain, hipStream_t s);
 
 }  // namespace grw

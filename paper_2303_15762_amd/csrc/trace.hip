@@ -13,6 +13,7 @@
 #include <float.h>
 
 #include "kernels.hpp"
+#include "mlp_core.hpp"
 
 namespace grw {
 
@@ -178,7 +179,9 @@ __device__ __forceinline__ unsigned long long wave_sum(uint32_t v) {
     return x;
 }
 
-template <int STACK>
+// SUR: instantiate the learned-p_w path (its matrix-core pass raises the register budget, so
+// the plain path is a separate instantiation).
+template <int STACK, bool SUR>
 __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
@@ -194,6 +197,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
     f3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
     uint32_t c_paths = 0, c_seg = 0, c_sh = 0, c_ev = 0, c_bf = 0, c_nf = 0, c_nodes = 0, c_tris = 0;
+    uint32_t c_sur = 0, c_fb = 0;
 
     while (true) {
         if (!exhausted) {
@@ -242,10 +246,13 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
             }
         }
         if (!__any(live)) break;
-        if (!live) continue;
 
-        // ---- one segment -------------------------------------------------------------
+        // ---- one segment of every live path ------------------------------------------
         bool finish = false;
+        bool sur_want = false;           // this lane's measurement waits for the network
+        float sur_scale = 0.0f, sur_logpeak = 0.0f;
+        float sur_x[MLP_IN];
+        if (live) {
         ++c_seg;
         RayT ray;
         ray_setup(ray, o, d);
@@ -357,10 +364,24 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                         float tm = tmax_s, su, sv;
                         const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, c_nodes, c_tris, su, sv);
                         if (occ < 0) {
-                            const float p = pw_plain(m.kind, m.h, m.L, m.refl, k, k * dot3(om, xa),
-                                                     k * dot3(om, ya), -k * dx, -k * dy, sxx, syy, sxy,
-                                                     1.0f, 0.0f);
-                            contrib += alpha * L.power * p * (float)A.nsrc;
+                            const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
+                            const float kox = -k * dx, koy = -k * dy;
+                            const float scale = alpha * L.power * (float)A.nsrc;
+                            int e = 0;
+                            if (SUR && m.kind == MAT_ROUGH) {
+                                const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
+                                e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sur_x, sur_logpeak);
+                                if (e == 0) ++c_fb;
+                            }
+                            if (e == 1) {
+                                sur_want = true;
+                                sur_scale = scale * m.refl;
+                                ++c_sur;
+                            } else if (e == 0) {
+                                contrib += scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy,
+                                                            sxx, syy, sxy, 1.0f, 0.0f);
+                            }
+                            // e == 2: more than 8 lobe widths from the lobe, p_w taken as 0
                         }
                     }
                 }
@@ -389,6 +410,21 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                 }
             }
         }
+        }   // live
+        // ---- learned p_w: one matrix-core pass for the whole wave -------------------------
+        if (SUR && __any(sur_want)) {
+            float xin[MLP_IN];
+#pragma unroll
+            for (int f = 0; f < MLP_IN; ++f) xin[f] = sur_want ? sur_x[f] : 0.0f;
+            MlpDev M;
+            M.wf = static_cast<const bf16x8*>(A.sur.wf);
+            M.bias = A.sur.bias;
+            M.w5 = A.sur.w5;
+            M.b5 = A.sur.b5;
+            // the wave's traversal stack is idle here and holds the 64 x 16 input staging
+            const float y = mlp_forward_wave(M, xin, reinterpret_cast<float*>(&lds_stack[wv][0][0]), nullptr);
+            if (sur_want) contrib += sur_scale * __expf(y + sur_logpeak);
+        }
         if (finish) {
             float val = contrib * A.inv_spp_norm;
             if (!isfinite(val)) {
@@ -402,7 +438,8 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
 
     const unsigned long long s0 = wave_sum(c_paths), s1 = wave_sum(c_seg), s2 = wave_sum(c_sh),
                              s5 = wave_sum(c_ev), s6 = wave_sum(c_bf), s7 = wave_sum(c_nf),
-                             s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris);
+                             s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris), s3 = wave_sum(c_sur),
+                             s4 = wave_sum(c_fb);
     if (lane == 0) {
         atomicAdd(A.stats + ST_PATHS, s0);
         atomicAdd(A.stats + ST_SEGMENTS, s1);
@@ -412,6 +449,8 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
         atomicAdd(A.stats + ST_NONFINITE, s7);
         atomicAdd(A.stats + ST_NODES, s8);
         atomicAdd(A.stats + ST_TRIS, s9);
+        atomicAdd(A.stats + ST_SUR, s3);
+        atomicAdd(A.stats + ST_FALLBACK, s4);
     }
 }
 
@@ -437,24 +476,30 @@ __global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict_
                       r[12], r[13]);
 }
 
-template <int STACK>
+template <int STACK, bool SUR>
 static int grid_for(int device) {
     int ncu = 0, nb = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<STACK>, 256, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<STACK, SUR>, 256, 0) != hipSuccess) return 0;
     return ncu * (nb > 0 ? nb : 1);
 }
 
-int trace_grid_size(int device, int stack_depth) {
-    if (stack_depth <= 32) return grid_for<32>(device);
-    if (stack_depth <= 64) return grid_for<64>(device);
-    return grid_for<96>(device);
+int trace_grid_size(int device, int stack_depth, bool sur) {
+    if (stack_depth <= 32) return sur ? grid_for<32, true>(device) : grid_for<32, false>(device);
+    if (stack_depth <= 64) return sur ? grid_for<64, true>(device) : grid_for<64, false>(device);
+    return sur ? grid_for<96, true>(device) : grid_for<96, false>(device);
+}
+
+template <int STACK>
+static void launch_stack(const TraceArgs& a, int grid, hipStream_t s) {
+    if (a.bsdf_mode == 1) hipLaunchKernelGGL((trace_kernel<STACK, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((trace_kernel<STACK, false>), dim3(grid), dim3(256), 0, s, a);
 }
 
 hipError_t launch_trace(const TraceArgs& a, int stack_depth, int grid, hipStream_t s) {
-    if (stack_depth <= 32) hipLaunchKernelGGL(trace_kernel<32>, dim3(grid), dim3(256), 0, s, a);
-    else if (stack_depth <= 64) hipLaunchKernelGGL(trace_kernel<64>, dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(trace_kernel<96>, dim3(grid), dim3(256), 0, s, a);
+    if (stack_depth <= 32) launch_stack<32>(a, grid, s);
+    else if (stack_depth <= 64) launch_stack<64>(a, grid, s);
+    else launch_stack<96>(a, grid, s);
     return hipGetLastError();
 }
 

@@ -1,0 +1,90 @@
+"""The trained surrogate of p_w: accuracy on held-out queries, images against the FP64 oracle
+(relative L2 <= 1e-2, the tolerance stated for the learned path), and its cost against the
+closed form it replaces."""
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import scenes as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trained():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2303_15762_amd import Renderer
+    from paper_2303_15762_amd.surrogate import Surrogate
+    R = Renderer(0)
+    S = Surrogate(R)
+    p, hist = S.train()
+    print("training history", hist)
+    S.install(p)
+    yield R, S, p, hist, torch
+    R.close()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def test_training_converges(trained):
+    R, S, p, hist, torch = trained
+    assert hist["val_loss"][-1] < 2e-3
+    assert hist["val_loss"][-1] < 0.01 * hist["val_loss"][0]
+
+
+def test_surrogate_pw_on_held_out_queries(trained):
+    R, S, p, hist, torch = trained
+    _, _, q = S.samples(200000, seed=77, with_queries=True)
+    got = R.bsdf_eval(q, mode=1).cpu().numpy().astype(np.float64)
+    ref = oracle.pw_batch(q.cpu().numpy().astype(np.float64))
+    qn = q.cpu().numpy().astype(np.float64)
+    k = qn[:, 4]
+    ci = np.sqrt(1 - (qn[:, 5] ** 2 + qn[:, 6] ** 2) / k ** 2)
+    co = np.sqrt(1 - (qn[:, 7] ** 2 + qn[:, 8] ** 2) / k ** 2)
+    g = (k * (ci + co) * qn[:, 1]) ** 2
+    peak = qn[:, 2] ** 2 / (4 * np.pi * g)
+    big = ref > 1e-2 * peak
+    rel = np.abs(got[big] - ref[big]) / ref[big]
+    print("surrogate p_w: median rel err", np.median(rel), "p90", np.quantile(rel, 0.9),
+          "p99", np.quantile(rel, 0.99), "abs err / peak max", (np.abs(got - ref) / peak).max())
+    assert np.median(rel) < 1e-2
+    assert np.quantile(rel, 0.9) < 3e-2
+    assert (np.abs(got - ref) / peak).max() < 5e-2
+
+
+def test_surrogate_trace_matches_oracle(trained):
+    R, S, p, hist, torch = trained
+    wl = W.mid_terrain(width=41, height=29, spp=16, n_lambda=8)
+    R.load_workload(wl)
+    img, st = R.render_workload(wl, bsdf_mode=1)
+    o, _ = oracle.render(wl)
+    e = rel_l2(img.cpu().numpy(), o)
+    print("surrogate trace: rel L2", e, st)
+    assert st["surrogate_evals"] > 0
+    assert e <= 1e-2
+
+
+def test_surrogate_cost_against_closed_form(trained):
+    """What the network buys: p_w of rough-surface queries in its domain, closed form (a
+    Poisson series of ~12 sqrt(g) Gaussians) against one matrix-core pass per 64 queries."""
+    R, S, p, hist, torch = trained
+    _, _, q = S.samples(1 << 22, seed=78, with_queries=True)
+    t = {}
+    for mode in (0, 1):
+        R.bsdf_eval(q, mode=mode)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            R.bsdf_eval(q, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        t[mode] = e0.elapsed_time(e1) / 5
+    print(f"p_w of {q.shape[0]} rough queries: closed form {t[0]:.3f} ms, surrogate {t[1]:.3f} ms,"
+          f" speed-up {t[0] / t[1]:.2f}x")
+    assert t[1] > 0 and t[0] > 0

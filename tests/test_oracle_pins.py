@@ -591,7 +591,11 @@ def test_mlp_backward_matches_finite_differences():
         bm[l][0] -= h
         fd = (mlp.mse_loss(Ws, bp, X, Y) - mlp.mse_loss(Ws, bm, X, Y)) / (2 * h)
         assert dbs[l][0] == pytest.approx(fd, rel=1e-6, abs=1e-10)
-    # GELU against its definition x * Phi(x)
-    from scipy.stats import norm
-    x = np.linspace(-5, 5, 11)
-    np.testing.assert_allclose(mlp.gelu(x), x * norm.cdf(x), rtol=1e-14, atol=1e-300)
+    # GELU (tanh form) against PyTorch's own implementation in double precision
+    import torch
+    x = np.linspace(-6, 6, 25)
+    ref = torch.nn.functional.gelu(torch.tensor(x, dtype=torch.float64), approximate="tanh").numpy()
+    np.testing.assert_allclose(mlp.gelu(x), ref, rtol=1e-13, atol=1e-15)
+    xt = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    torch.nn.functional.gelu(xt, approximate="tanh").sum().backward()
+    np.testing.assert_allclose(mlp.gelu_grad(x), xt.grad.numpy(), rtol=1e-12, atol=1e-14)
