@@ -74,13 +74,47 @@ def cpu_baseline(wl, target_s=15.0):
                       f"same workload ({seg} segments, {dt:.1f} s, FP64 C++ oracle, {threads} threads)"}
 
 
+def surrogate_leg(R, wl, o_plain, img, st_plain, args):
+    """Train the learned p_w (outside the timed region), then time the same workload with the
+    surrogate path.  Its image is compared with the plain-path image of this GPU."""
+    import torch
+    from paper_2303_15762_amd.surrogate import Surrogate
+    S = Surrogate(R)
+    t0 = time.perf_counter()
+    p, hist = S.train()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    S.install(p)
+    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+               rr_enable=wl.rr_enable, rr_p=wl.rr_p, bsdf_mode=1)
+    plain = img.clone()
+    img_s = torch.zeros_like(img)
+    _, st = R.trace(wl.lambdas_um, o, image=img_s, stats=True)
+    err = float((img_s - plain).norm() / plain.norm())
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(R.stream)
+    for _ in range(args.steps):
+        R.trace(wl.lambdas_um, o, image=img_s, stats=False)
+    e1.record(R.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    return {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
+            "ms_per_step": round(ms, 3), "rel_l2_vs_plain_gpu_image": err,
+            "surrogate_evals_per_step": st["surrogate_evals"], "fallbacks_per_step": st["fallbacks"],
+            "train_s": round(t_train, 2), "train_steps": hist["step"][-1],
+            "val_mse_log_pw": hist["val_loss"][-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--surrogate", action="store_true", help="also time the surrogate mode")
+    ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
+                    help="skip the learned-p_w leg (training takes a few seconds)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (scales the "
                          "HBM byte counters of a profiler run)")
@@ -163,6 +197,8 @@ def main():
                    "bvh_depth": info["depth"]},
         "roofline": roofline,
     }
+    if args.surrogate:
+        out["surrogate"] = surrogate_leg(R, wl, o, img, st, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

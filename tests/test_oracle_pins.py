@@ -599,3 +599,40 @@ def test_mlp_backward_matches_finite_differences():
     xt = torch.tensor(x, dtype=torch.float64, requires_grad=True)
     torch.nn.functional.gelu(xt, approximate="tanh").sum().backward()
     np.testing.assert_allclose(mlp.gelu_grad(x), xt.grad.numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_rough_continuation_sampling_moments():
+    """Unwindowed rough-surface kernel f_inf = sum_m Poisson(m; g) N(kappa; 0, 2m/l^2 I) with
+    g = (2 k cos(i) s)^2: the sampler leaves the direction unchanged with probability e^-g and
+    draws kappa with E|kappa|^2 = sum_m P(m) 4 m / l^2 = 4 g / l^2."""
+    from scipy.stats import poisson
+    k = 2 * math.pi / 0.6
+    s_um, ell = 0.08, 2.0
+    ci = 0.9
+    g = (2 * k * ci * s_um) ** 2
+    kit = (0.3, -0.2)
+    rng = np.random.default_rng(8)
+    n = 40000
+    u = rng.uniform(0, 1, (n, 3))
+    kap2, zero = [], 0
+    for row in u:
+        r = oracle.sample_continuation(1, s_um, ell, k, kit, ci, row)
+        assert r is not None and r[2] == 1.0
+        d2 = (r[0] - kit[0]) ** 2 + (r[1] - kit[1]) ** 2
+        zero += d2 == 0.0
+        kap2.append(d2)
+    kap2 = np.array(kap2)
+    assert zero / n == pytest.approx(math.exp(-g), abs=4 * math.sqrt(math.exp(-g) / n))
+    se = kap2.std() / math.sqrt(n)
+    assert abs(kap2.mean() - 4 * g / ell ** 2) < 4 * se
+    # the term index follows the Poisson law exactly (inverse CDF of a fine uniform grid)
+    us = (np.arange(2000) + 0.5) / 2000
+    ms = []
+    for uu in us:
+        r = oracle.sample_continuation(1, s_um, ell, k, kit, ci, (uu, 0.1, 0.25))
+        # with u1 = 0.1, u2 = 0.25 the Box-Muller pair is (0, r): |kappa| = sqrt(2m)/l * r
+        rr = math.sqrt(-2 * math.log(1 - 0.1))
+        d = math.hypot(r[0] - kit[0], r[1] - kit[1])
+        ms.append(int(round((d * ell / rr) ** 2 / 2)))
+    hist = np.bincount(ms, minlength=30)[:30] / len(us)
+    np.testing.assert_allclose(hist, poisson.pmf(np.arange(30), g), atol=1.0 / len(us) + 1e-12)
