@@ -98,8 +98,10 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
     float best_t = tmax;
     int sp = 0;
     int cur = 0;
-    const float ox = r.o.x, oy = r.o.y, oz = r.o.z;
+    // slab distances as (lo - o) / d = lo * inv - o * inv: one FMA per plane (the node boxes
+    // are widened by more than the extra rounding of o * inv)
     const float ix = r.inv.x, iy = r.inv.y, iz = r.inv.z;
+    const float oix = r.o.x * ix, oiy = r.o.y * iy, oiz = r.o.z * iz;
     while (true) {
         if (cur >= 0) {
             ++n_nodes;
@@ -113,9 +115,9 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
             const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float t0x = (lxa[i] - ox) * ix, t1x = (hxa[i] - ox) * ix;
-                const float t0y = (lya[i] - oy) * iy, t1y = (hya[i] - oy) * iy;
-                const float t0z = (lza[i] - oz) * iz, t1z = (hza[i] - oz) * iz;
+                const float t0x = fmaf(lxa[i], ix, -oix), t1x = fmaf(hxa[i], ix, -oix);
+                const float t0y = fmaf(lya[i], iy, -oiy), t1y = fmaf(hya[i], iy, -oiy);
+                const float t0z = fmaf(lza[i], iz, -oiz), t1z = fmaf(hza[i], iz, -oiz);
                 const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
                 const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), best_t));
                 k[i] = (tn <= tf && c[i] != 0x7FFFFFFF) ? tn : FLT_MAX;
@@ -391,7 +393,8 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                     // Light-matter interaction: sample the continuation generalized ray.
                     const uint4 rs = draw(pid, (uint32_t)depth, STREAM_SCATTER, A.seed);
                     float kox, koy, wgt;
-                    if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt)) {
+                    if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
+                                    reinterpret_cast<float*>(stk), STACK)) {
                         ++c_ev;
                         finish = true;
                     } else {
