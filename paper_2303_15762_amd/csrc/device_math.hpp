@@ -257,44 +257,44 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         const int jlo = (int)floorf((kix - r) / K) - 1;
         const int jhi = min((int)ceilf((kix + r) / K) + 1, jlo + 4096);
         const bool cached = jhi - jlo < cache_n;
-        float W = 0.0f;
-        for (int j = jlo; j <= jhi; ++j) {
-            const float ox = kix - (float)j * K;
-            const float no = (ox * ox + kiy * kiy) / k2;
-            float w = 0.0f;
-            if (no < 1.0f) {
-                const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
-                w = bj * bj;
-                W += w;
+        // pass 0 sums the weights W, pass 1 inverts the cumulative sum at u0 W (one Bessel
+        // evaluation site for both)
+        float W = 0.0f, c = 0.0f, target = 0.0f;
+        int pick = jhi, last = jlo;
+#pragma nounroll
+        for (int pass = 0; pass < 2; ++pass) {
+            bool found = false;
+            for (int j = jlo; j <= jhi; ++j) {
+                const float ox = kix - (float)j * K;
+                const float no = (ox * ox + kiy * kiy) / k2;
+                if (no >= 1.0f) continue;
+                float w;
+                if (pass == 1 && cached) {
+                    w = cache[(j - jlo) * 64];
+                } else {
+                    const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
+                    w = bj * bj;
+                }
+                if (pass == 0) {
+                    W += w;
+                    if (cached) cache[(j - jlo) * 64] = w;
+                } else {
+                    c += w;
+                    last = j;
+                    if (target < c) {
+                        pick = j;
+                        found = true;
+                        break;
+                    }
+                }
             }
-            if (cached) cache[(j - jlo) * 64] = w;
+            if (pass == 0) {
+                if (!(W > 0.0f)) return 1;
+                target = u0 * W;
+            } else if (!found) {
+                pick = last;
+            }
         }
-        if (!(W > 0.0f)) return 1;
-        const float target = u0 * W;
-        float c = 0.0f;
-        int pick = jhi;
-        bool found = false;
-        int last = jlo;
-        for (int j = jlo; j <= jhi; ++j) {
-            const float ox = kix - (float)j * K;
-            const float no = (ox * ox + kiy * kiy) / k2;
-            if (no >= 1.0f) continue;
-            float w;
-            if (cached) {
-                w = cache[(j - jlo) * 64];
-            } else {
-                const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
-                w = bj * bj;
-            }
-            c += w;
-            last = j;
-            if (target < c) {
-                pick = j;
-                found = true;
-                break;
-            }
-        }
-        if (!found) pick = last;
         kox = kix - (float)pick * K;
         koy = kiy;
         weight = m.refl * W;

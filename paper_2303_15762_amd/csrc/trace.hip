@@ -85,6 +85,13 @@ __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, f
     return true;
 }
 
+// Child code of the slot held in a sorted key's two low bits.
+__device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
+    const int a = (key & 1u) ? ch.y : ch.x;
+    const int b = (key & 1u) ? ch.w : ch.z;
+    return (key & 2u) ? b : a;
+}
+
 // BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
 // triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
 // triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack, stride 64.
@@ -108,11 +115,13 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
             const float4* N = S.nodes + (size_t)cur * 8;
             const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
             const int4 ch = *reinterpret_cast<const int4*>(N + 6);
-            float k[4];
-            int c[4] = {ch.x, ch.y, ch.z, ch.w};
             const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
             const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
             const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+            // key = entry distance with the slot in its two low bits (distances are positive, so
+            // their bit patterns order like the values); a miss keys as 0xFFFFFFFF.  Empty slots
+            // hold boxes at +inf and always miss.
+            uint32_t key[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float t0x = fmaf(lxa[i], ix, -oix), t1x = fmaf(hxa[i], ix, -oix);
@@ -120,13 +129,14 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 const float t0z = fmaf(lza[i], iz, -oiz), t1z = fmaf(hza[i], iz, -oiz);
                 const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
                 const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), best_t));
-                k[i] = (tn <= tf && c[i] != 0x7FFFFFFF) ? tn : FLT_MAX;
+                key[i] = tn <= tf ? ((__float_as_uint(tn) & ~3u) | (uint32_t)i) : 0xFFFFFFFFu;
             }
-            // sort descending (misses, keyed FLT_MAX, first; nearest hit last)
-#define GRW_CSWAP(i, j)                                  \
-    if (k[i] < k[j]) {                                   \
-        const float tk = k[i]; k[i] = k[j]; k[j] = tk;   \
-        const int tc = c[i]; c[i] = c[j]; c[j] = tc;     \
+            // ascending sorting network on the keys
+#define GRW_CSWAP(i, j)                               \
+    {                                                 \
+        const uint32_t lo_ = min(key[i], key[j]);     \
+        key[j] = max(key[i], key[j]);                 \
+        key[i] = lo_;                                 \
     }
             GRW_CSWAP(0, 1)
             GRW_CSWAP(2, 3)
@@ -134,11 +144,12 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
             GRW_CSWAP(1, 3)
             GRW_CSWAP(1, 2)
 #undef GRW_CSWAP
+            // push the farther hits (farthest first), descend into the nearest
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                if (k[i] != FLT_MAX) stk[(sp++) * 64] = c[i];
-            if (k[3] != FLT_MAX) {
-                cur = c[3];
+            for (int i = 3; i >= 1; --i)
+                if (key[i] != 0xFFFFFFFFu) stk[(sp++) * 64] = child_of(ch, key[i]);
+            if (key[0] != 0xFFFFFFFFu) {
+                cur = child_of(ch, key[0]);
                 continue;
             }
         } else {
@@ -183,8 +194,12 @@ __device__ __forceinline__ unsigned long long wave_sum(uint32_t v) {
 
 // SUR: instantiate the learned-p_w path (its matrix-core pass raises the register budget, so
 // the plain path is a separate instantiation).
+enum { EV_PATH = 0, EV_SEG, EV_SHADOW, EV_SUR, EV_FALLBACK, EV_EVANESCENT, EV_BACKFACING, EV_NONFINITE, EV_COUNT };
+
+// The plain instantiation asks for 4 waves per SIMD (128 VGPRs): a few path-state values
+// spill to scratch, which costs less than the latency hidden by the fourth wave.
 template <int STACK, bool SUR>
-__global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
+__global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -198,10 +213,13 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
     int depth = 0, prev = -1;
     f3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
-    uint32_t c_paths = 0, c_seg = 0, c_sh = 0, c_ev = 0, c_bf = 0, c_nf = 0, c_nodes = 0, c_tris = 0;
-    uint32_t c_sur = 0, c_fb = 0;
+    // traversal work per lane; the per-path events are flagged per lane (one bit each) and
+    // counted per wave with ballots, which keeps the counts in scalar registers
+    uint32_t c_nodes = 0, c_tris = 0;
+    unsigned long long w_cnt[EV_COUNT] = {};
 
     while (true) {
+        uint32_t ev = 0;
         if (!exhausted) {
             const unsigned long long need = __ballot(!live);
             if (need) {
@@ -242,7 +260,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                         depth = 0;
                         prev = -1;
                         live = true;
-                        ++c_paths;
+                        ev |= 1u << EV_PATH;
                     }
                 }
             }
@@ -255,7 +273,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
         float sur_scale = 0.0f, sur_logpeak = 0.0f;
         float sur_x[MLP_IN];
         if (live) {
-        ++c_seg;
+        ev |= 1u << EV_SEG;
         RayT ray;
         ray_setup(ray, o, d);
         const float tmin = 1e-7f * (1.0f + maxabs3(o));
@@ -293,7 +311,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
             if (dot3(ns, ng) < 0.0f) ns = -1.0f * ns;
             const float ci = -dot3(d, ns);
             if (ci <= 0.0f) {
-                ++c_bf;
+                ev |= 1u << EV_BACKFACING;
                 finish = true;
             } else {
                 // Tangent frame: x = grating direction (gratings), else the travel direction
@@ -360,7 +378,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                         }
                     }
                     if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
-                        ++c_sh;
+                        ev |= 1u << EV_SHADOW;
                         RayT sray;
                         ray_setup(sray, P, -1.0f * om);
                         float tm = tmax_s, su, sv;
@@ -373,12 +391,12 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                             if (SUR && m.kind == MAT_ROUGH) {
                                 const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
                                 e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sur_x, sur_logpeak);
-                                if (e == 0) ++c_fb;
+                                if (e == 0) ev |= 1u << EV_FALLBACK;
                             }
                             if (e == 1) {
                                 sur_want = true;
                                 sur_scale = scale * m.refl;
-                                ++c_sur;
+                                ev |= 1u << EV_SUR;
                             } else if (e == 0) {
                                 contrib += scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy,
                                                             sxx, syy, sxy, 1.0f, 0.0f);
@@ -395,7 +413,7 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
                     float kox, koy, wgt;
                     if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
                                     reinterpret_cast<float*>(stk), STACK)) {
-                        ++c_ev;
+                        ev |= 1u << EV_EVANESCENT;
                         finish = true;
                     } else {
                         alpha *= wgt;
@@ -431,29 +449,28 @@ __global__ __launch_bounds__(256) void trace_kernel(const TraceArgs A) {
         if (finish) {
             float val = contrib * A.inv_spp_norm;
             if (!isfinite(val)) {
-                ++c_nf;
+                ev |= 1u << EV_NONFINITE;
                 val = 0.0f;
             }
             A.records[idx] = val;
             live = false;
         }
+#pragma unroll
+        for (int b = 0; b < EV_COUNT; ++b) w_cnt[b] += (unsigned long long)__popcll(__ballot((ev >> b) & 1u));
     }
 
-    const unsigned long long s0 = wave_sum(c_paths), s1 = wave_sum(c_seg), s2 = wave_sum(c_sh),
-                             s5 = wave_sum(c_ev), s6 = wave_sum(c_bf), s7 = wave_sum(c_nf),
-                             s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris), s3 = wave_sum(c_sur),
-                             s4 = wave_sum(c_fb);
+    const unsigned long long s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris);
     if (lane == 0) {
-        atomicAdd(A.stats + ST_PATHS, s0);
-        atomicAdd(A.stats + ST_SEGMENTS, s1);
-        atomicAdd(A.stats + ST_SHADOW, s2);
-        atomicAdd(A.stats + ST_EVANESCENT, s5);
-        atomicAdd(A.stats + ST_BACKFACING, s6);
-        atomicAdd(A.stats + ST_NONFINITE, s7);
+        atomicAdd(A.stats + ST_PATHS, w_cnt[EV_PATH]);
+        atomicAdd(A.stats + ST_SEGMENTS, w_cnt[EV_SEG]);
+        atomicAdd(A.stats + ST_SHADOW, w_cnt[EV_SHADOW]);
+        atomicAdd(A.stats + ST_EVANESCENT, w_cnt[EV_EVANESCENT]);
+        atomicAdd(A.stats + ST_BACKFACING, w_cnt[EV_BACKFACING]);
+        atomicAdd(A.stats + ST_NONFINITE, w_cnt[EV_NONFINITE]);
         atomicAdd(A.stats + ST_NODES, s8);
         atomicAdd(A.stats + ST_TRIS, s9);
-        atomicAdd(A.stats + ST_SUR, s3);
-        atomicAdd(A.stats + ST_FALLBACK, s4);
+        atomicAdd(A.stats + ST_SUR, w_cnt[EV_SUR]);
+        atomicAdd(A.stats + ST_FALLBACK, w_cnt[EV_FALLBACK]);
     }
 }
 
