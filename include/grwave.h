@@ -92,7 +92,7 @@ typedef struct {
     float power;
 } gr_source;
 
-enum { GR_TRACE_KEEP_PATHS = 1 };
+enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2 };
 
 /* Trace options.
  *   spp_begin, spp_count : sample indices [spp_begin, spp_begin + spp_count) of every pixel and
@@ -106,7 +106,11 @@ enum { GR_TRACE_KEEP_PATHS = 1 };
  *                          probability rr_p in (0, 1].
  *   seed                 : Philox key.
  *   flags                : GR_TRACE_KEEP_PATHS keeps the per-path contributions in the
- *                          workspace (see gr_workspace_paths). */
+ *                          workspace (see gr_workspace_paths).  GR_TRACE_SHORT_LDS_STACK keeps
+ *                          only 4 BVH traversal-stack entries per lane in LDS and the rest in
+ *                          the workspace (normally 32 stay in LDS and only BVHs deeper than 9
+ *                          levels overflow); the image is identical, the render slower.  It
+ *                          exists to exercise the overflow path.  Other bits are invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;
@@ -169,7 +173,10 @@ int gr_set_sensor(gr_ctx* ctx, const gr_sensor* sensor);
 /* Up to 16 sources; next-event estimation picks one uniformly per interaction. */
 int gr_set_sources(gr_ctx* ctx, const gr_source* sources, int32_t n);
 
-/* Workspace (device memory) needed by gr_trace for these options and n_lambda wavelengths. */
+/* Workspace (device memory) needed by gr_trace for these options and n_lambda wavelengths:
+ * a header, one float per path, and the traversal-stack overflow of the uploaded scene's BVH
+ * (one region per persistent lane, 3 entries per BVH level beyond the LDS part).  Call it
+ * after gr_scene_upload: the size depends on the scene and the device. */
 int gr_workspace_size(const gr_ctx* ctx, const gr_trace_opts* opts, int32_t n_lambda,
                       size_t* bytes);
 /* Device pointer (inside `workspace`) of the per-path contributions kept by

@@ -22,6 +22,13 @@
 #include <thread>
 #include <vector>
 
+// Worker threads when the caller does not say: the hardware threads, at most 16 (a
+// one-GPU share of a shared host).
+static int default_threads() {
+    const int hw = (int)std::thread::hardware_concurrency();
+    return hw > 0 ? std::min(hw, 16) : 1;
+}
+
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -693,7 +700,7 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
     const SceneO* S = (const SceneO*)s;
     if (!pixels) npix = (int64_t)sen->width * sen->height;
     Ctx C{S, sen, src, nsrc, lambdas, nl, op};
-    int nt = op->n_threads > 0 ? op->n_threads : (int)std::thread::hardware_concurrency();
+    int nt = op->n_threads > 0 ? op->n_threads : default_threads();
     nt = std::max(1, nt);
     std::atomic<int64_t> next(0);
     std::vector<Stats> sts(nt);
@@ -776,7 +783,7 @@ static std::complex<double> field_at(const or_coherent& c, double X, double Y) {
 // state.  out: [height][width] mean of |U|^2 over the spp samples.
 // rows: number of leading sensor rows to compute (<= height; path ids use the full height).
 void or_coherent_mc(const or_coherent* c, double* out, int32_t n_threads, int32_t rows) {
-    int nt = n_threads > 0 ? n_threads : (int)std::thread::hardware_concurrency();
+    int nt = n_threads > 0 ? n_threads : default_threads();
     std::atomic<int64_t> next(0);
     if (rows <= 0 || rows > c->height) rows = c->height;
     int64_t np = (int64_t)c->width * rows;

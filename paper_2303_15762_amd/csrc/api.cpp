@@ -32,14 +32,15 @@ struct gr_ctx {
     int bvh_depth = 0;
     int max_leaf = 0;
     int64_t scene_bytes = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};   // vertex bounds
     float build_ms = 0.0f;
     bool has_scene = false;
     // sensor and sources (host copies)
     bool has_sensor = false;
     gr_sensor sensor{};
     std::vector<gr_source> sources;
-    int grid = 0;
-    int grid_stack = -1;
+    int grid_plain = 0;              // persistent grids (blocks), set at scene upload
+    int grid_sur = 0;
     grw::SurrogateState sur;
 };
 
@@ -82,7 +83,18 @@ void free_scene(gr_ctx* c) {
 
 constexpr size_t kWsHeader = 4096;   // dispenser counter + statistics
 
+// Traversal stack bound: at most 3 pending siblings per inner node on the root path.
 int stack_for_depth(int depth) { return 3 * (depth + 1) + 1; }
+constexpr int kMaxStack = 256;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack; }
+
+// Traversal-stack entries per lane that do not fit the LDS part.
+uint32_t overflow_entries(const gr_ctx* c, const gr_trace_opts* o) {
+    return c->has_scene ? (uint32_t)std::max(0, stack_for_depth(c->bvh_depth) - lds_cap_for(o)) : 0u;
+}
 
 }  // namespace
 
@@ -142,7 +154,8 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     const auto t0 = std::chrono::steady_clock::now();
     grw::BuiltBVH bvh = grw::build_bvh4(verts, tris, nt);
     const auto t1 = std::chrono::steady_clock::now();
-    if (stack_for_depth(bvh.depth) > 96) return fail(c, GR_E_UNSUPPORTED, "scene: BVH depth %d too deep", bvh.depth);
+    if (stack_for_depth(bvh.depth) > kMaxStack)
+        return fail(c, GR_E_UNSUPPORTED, "scene: BVH depth %d too deep", bvh.depth);
 
     std::vector<float> tri_data(12 * (size_t)nt), tri_norm(12 * (size_t)nt, 0.0f);
     for (int64_t j = 0; j < nt; ++j) {
@@ -192,13 +205,27 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     GR_HIP(c, hipMemcpy(c->d_tnorm, tri_norm.data(), tb, hipMemcpyHostToDevice));
     GR_HIP(c, hipMemcpy(c->d_mats, dm.data(), mb, hipMemcpyHostToDevice));
     c->n_tris = nt;
+    for (int a = 0; a < 3; ++a) {
+        c->lo[a] = std::numeric_limits<float>::infinity();
+        c->hi[a] = -std::numeric_limits<float>::infinity();
+    }
+    for (int64_t i = 0; i < nv; ++i)
+        for (int a = 0; a < 3; ++a) {
+            c->lo[a] = std::min(c->lo[a], verts[3 * i + a]);
+            c->hi[a] = std::max(c->hi[a], verts[3 * i + a]);
+        }
     c->n_nodes = (int64_t)bvh.nodes.size();
     c->bvh_depth = bvh.depth;
     c->max_leaf = bvh.max_leaf;
     c->scene_bytes = (int64_t)(nb + 2 * tb + mb);
     c->build_ms = std::chrono::duration<float, std::milli>(t1 - t0).count();
+    c->grid_plain = grw::trace_grid_size(c->device, false);
+    c->grid_sur = grw::trace_grid_size(c->device, true);
+    if (c->grid_plain <= 0 || c->grid_sur <= 0) {
+        free_scene(c);
+        return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
+    }
     c->has_scene = true;
-    c->grid_stack = -1;
     return GR_OK;
 }
 
@@ -260,7 +287,10 @@ int gr_workspace_size(const gr_ctx* c, const gr_trace_opts* o, int32_t nl, size_
     if (!c->has_sensor) return GR_E_NO_SCENE;
     if (o->spp_count < 0 || nl < 1 || nl > grw::kMaxLambda) return GR_E_INVALID;
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
-    *bytes = kWsHeader + (size_t)(per * (uint64_t)o->spp_count) * sizeof(float);
+    // header | path records | traversal-stack overflow of the scene's BVH (per persistent lane)
+    const size_t lanes = (size_t)std::max(c->grid_plain, c->grid_sur) * 256;
+    *bytes = kWsHeader + align256((size_t)(per * (uint64_t)o->spp_count) * sizeof(float)) +
+             lanes * overflow_entries(c, o) * sizeof(int);
     return GR_OK;
 }
 
@@ -281,6 +311,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (o->max_depth < 1 || o->max_depth > 64) return fail(c, GR_E_INVALID, "trace: max_depth %d", o->max_depth);
     if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
     if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
+    if (o->flags & ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK)) return fail(c, GR_E_INVALID, "trace: flags");
     if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
         return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
@@ -300,6 +331,10 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.scene.tnorm = static_cast<const float4*>(c->d_tnorm);
     a.scene.mats = static_cast<const grw::DMat*>(c->d_mats);
     a.scene.n_tris = c->n_tris;
+    for (int i = 0; i < 3; ++i) {
+        a.scene.lo[i] = c->lo[i];
+        a.scene.hi[i] = c->hi[i];
+    }
     const gr_sensor& s = c->sensor;
     for (int i = 0; i < 3; ++i) {
         a.sensor.o[i] = s.origin[i];
@@ -350,21 +385,19 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.counter = reinterpret_cast<unsigned long long*>(base);
     a.stats = reinterpret_cast<unsigned long long*>(base + 256);
     a.records = reinterpret_cast<float*>(base + kWsHeader);
+    a.lds_cap = lds_cap_for(o);
+    a.ovf_n = overflow_entries(c, o);
+    a.ovf = a.ovf_n ? reinterpret_cast<int*>(base + kWsHeader + align256((size_t)a.n_paths * sizeof(float)))
+                    : nullptr;
 
     GR_HIP(c, hipSetDevice(c->device));
-    const int stack = stack_for_depth(c->bvh_depth);
-    const int key = stack * 4 + o->bsdf_mode;
-    if (c->grid_stack != key) {
-        c->grid = grw::trace_grid_size(c->device, stack, o->bsdf_mode == GR_BSDF_SURROGATE_BF16);
-        c->grid_stack = key;
-        if (c->grid <= 0) return fail(c, GR_E_DEVICE, "trace: occupancy query failed");
-    }
+    const int grid = o->bsdf_mode == GR_BSDF_SURROGATE_BF16 ? c->grid_sur : c->grid_plain;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (st)
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));
     GR_HIP(c, hipMemsetAsync(ws, 0, kWsHeader, c->stream));
     if (st) GR_HIP(c, hipEventRecord(ev[0], c->stream));
-    if (a.n_paths > 0) GR_HIP(c, grw::launch_trace(a, stack, c->grid, c->stream));
+    if (a.n_paths > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
     if (st) GR_HIP(c, hipEventRecord(ev[1], c->stream));
     if (a.n_paths > 0)
         GR_HIP(c, grw::launch_reduce(a.records, image, o->spp_count, (uint32_t)s.height, (uint32_t)s.width,

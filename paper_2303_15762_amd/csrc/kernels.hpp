@@ -10,6 +10,8 @@ namespace grw {
 
 constexpr int kMaxSources = 16;
 constexpr int kMaxLambda = 64;
+// Traversal stack entries per lane kept in LDS; deeper entries go to the overflow region.
+constexpr int kLdsStack = 32;
 
 struct SceneDev {
     const float4* nodes;     // BVH4Node as 8 float4 each
@@ -17,6 +19,7 @@ struct SceneDev {
     const float4* tnorm;     // 3 float4 per triangle: per-vertex shading normals (zero = geometric)
     const DMat* mats;
     int64_t n_tris;
+    float lo[3], hi[3];      // bounds of all vertices
 };
 
 struct SensorDev {
@@ -64,6 +67,9 @@ struct TraceArgs {
     int bsdf_mode;
     SurrogateDev sur;
     float* records;                  // [n_paths]
+    int* ovf;                        // traversal stack overflow [ovf_n][grid * 256], or null
+    uint32_t ovf_n;                  // overflow entries per lane
+    int lds_cap;                     // stack entries kept in LDS (<= kLdsStack)
     unsigned long long* counter;     // path dispenser
     unsigned long long* stats;       // [16]
 };
@@ -74,10 +80,10 @@ enum {
 };
 
 // Launchers (trace.hip).
-hipError_t launch_trace(const TraceArgs& a, int stack_depth, int grid, hipStream_t s);
+hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
                          uint32_t nl, hipStream_t s);
-int trace_grid_size(int device, int stack_depth, bool sur);
+int trace_grid_size(int device, bool sur);
 
 // Batch p_w evaluation (trace.hip).
 hipError_t launch_bsdf_eval(const float* q, int64_t n, float* out, hipStream_t s);

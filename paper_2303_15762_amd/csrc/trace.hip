@@ -17,16 +17,72 @@
 
 namespace grw {
 
+// Path positions are kept in double precision: at metre-scale coordinates one float ulp is
+// 0.06 um, and steep shading-normal gradients turn such offsets into direction errors that
+// grow along the path.  A ray carries its origin as the nearest float o plus the float
+// residual lo, so that vertex - origin keeps float precision relative to the segment.
+struct d3 {
+    double x, y, z;
+};
+__device__ __forceinline__ d3 add_scaled(d3 a, float t, f3 v) {
+    return d3{a.x + (double)t * (double)v.x, a.y + (double)t * (double)v.y, a.z + (double)t * (double)v.z};
+}
+__device__ __forceinline__ f3 to_f3(d3 a) { return mk3((float)a.x, (float)a.y, (float)a.z); }
+// (a - b) rounded once to float
+__device__ __forceinline__ f3 diff_f3(d3 a, f3 b) {
+    return mk3((float)(a.x - (double)b.x), (float)(a.y - (double)b.y), (float)(a.z - (double)b.z));
+}
+
+// Distance along (o, d) at which the ray enters the scene bounds widened by 1 mm, or 0 when
+// it starts inside or misses them.  The float slab test errs by far less than the margin.
+__device__ __forceinline__ float scene_entry(const SceneDev& S, d3 o, f3 d) {
+    const float m = 1e-3f;
+    const f3 of = to_f3(o);
+    const float t0x = (S.lo[0] - m - of.x) / d.x, t1x = (S.hi[0] + m - of.x) / d.x;
+    const float t0y = (S.lo[1] - m - of.y) / d.y, t1y = (S.hi[1] + m - of.y) / d.y;
+    const float t0z = (S.lo[2] - m - of.z) / d.z, t1z = (S.hi[2] + m - of.z) / d.z;
+    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
+    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
+    return (tn > 0.0f && tn <= tf) ? tn : 0.0f;
+}
+
+// Hit distance and barycentric weights of the triangle the float test found, recomputed in
+// double precision (Moller-Trumbore on the float vertices): the position the path continues
+// from then carries no error of the float ray-space arithmetic.  Keeps the float values when
+// the double test degenerates.
+__device__ __forceinline__ void refine_hit(d3 o, f3 d, float4 a, float4 b, float4 c, float& t,
+                                           float& bu, float& bv, double& t64) {
+    t64 = (double)t;
+    const double e1x = (double)b.x - a.x, e1y = (double)b.y - a.y, e1z = (double)b.z - a.z;
+    const double e2x = (double)c.x - a.x, e2y = (double)c.y - a.y, e2z = (double)c.z - a.z;
+    const double dx = d.x, dy = d.y, dz = d.z;
+    const double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const double det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0) return;
+    const double inv = 1.0 / det;
+    const double sx = o.x - a.x, sy = o.y - a.y, sz = o.z - a.z;
+    const double u = (sx * px + sy * py + sz * pz) * inv;
+    const double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    const double v = (dx * qx + dy * qy + dz * qz) * inv;
+    const double tt = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    if (!(tt > 0.0)) return;
+    t64 = tt;
+    t = (float)tt;
+    bu = fminf(fmaxf((float)u, 0.0f), 1.0f);
+    bv = fminf(fmaxf((float)v, 0.0f), 1.0f);
+}
+
 struct RayT {
-    f3 o, d, inv;
+    f3 o, lo, d, inv;
     int kx, ky, kz;
     float Sx, Sy, Sz;
 };
 
 __device__ __forceinline__ float comp(f3 v, int i) { return i == 0 ? v.x : (i == 1 ? v.y : v.z); }
 
-__device__ __forceinline__ void ray_setup(RayT& r, f3 o, f3 d) {
-    r.o = o;
+__device__ __forceinline__ void ray_setup(RayT& r, d3 o, f3 d) {
+    r.o = to_f3(o);
+    r.lo = diff_f3(o, r.o);
     r.d = d;
     const float tiny = 1e-30f;
     r.inv = mk3(1.0f / (fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x)),
@@ -59,9 +115,9 @@ __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, f
     // no FP contraction here: an edge shared by two triangles must get exactly opposite edge
     // function values (a fused multiply-add would round the two orientations differently)
 #pragma clang fp contract(off)
-    const f3 A = mk3(a4.x - r.o.x, a4.y - r.o.y, a4.z - r.o.z);
-    const f3 B = mk3(b4.x - r.o.x, b4.y - r.o.y, b4.z - r.o.z);
-    const f3 C = mk3(c4.x - r.o.x, c4.y - r.o.y, c4.z - r.o.z);
+    const f3 A = mk3((a4.x - r.o.x) - r.lo.x, (a4.y - r.o.y) - r.lo.y, (a4.z - r.o.z) - r.lo.z);
+    const f3 B = mk3((b4.x - r.o.x) - r.lo.x, (b4.y - r.o.y) - r.lo.y, (b4.z - r.o.z) - r.lo.z);
+    const f3 C = mk3((c4.x - r.o.x) - r.lo.x, (c4.y - r.o.y) - r.lo.y, (c4.z - r.o.z) - r.lo.z);
     const float Az0 = comp(A, r.kz), Bz0 = comp(B, r.kz), Cz0 = comp(C, r.kz);
     const float Ax = comp(A, r.kx) - r.Sx * Az0, Ay = comp(A, r.ky) - r.Sy * Az0;
     const float Bx = comp(B, r.kx) - r.Sx * Bz0, By = comp(B, r.ky) - r.Sy * Bz0;
@@ -94,12 +150,15 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 
 // BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
 // triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
-// triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack, stride 64.
+// triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack (stride 64),
+// of which the first cap (<= STACK) entries are used; entry cap + i goes to
+// ovf[i * ostride + lane], ovf being the wave's slice of the overflow region, which the caller
+// sizes for the tree: at most 3 entries per inner node on the current root path.
 // Returns the triangle (leaf order) or -1.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
-                                        bool any, int skip, int* stk, uint32_t& n_nodes,
-                                        uint32_t& n_tris, float& hu, float& hv) {
+                                        bool any, int skip, int* stk, int cap, int* ovf, size_t ostride,
+                                        uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv) {
     int best = -1;
     int best_orig = 0x7FFFFFFF;
     float best_t = tmax;
@@ -146,8 +205,14 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
 #undef GRW_CSWAP
             // push the farther hits (farthest first), descend into the nearest
 #pragma unroll
-            for (int i = 3; i >= 1; --i)
-                if (key[i] != 0xFFFFFFFFu) stk[(sp++) * 64] = child_of(ch, key[i]);
+            for (int i = 3; i >= 1; --i) {
+                if (key[i] != 0xFFFFFFFFu) {
+                    const int v = child_of(ch, key[i]);
+                    if (sp < cap) stk[sp * 64] = v;
+                    else ovf[(size_t)(sp - cap) * ostride + __lane_id()] = v;
+                    ++sp;
+                }
+            }
             if (key[0] != 0xFFFFFFFFu) {
                 cur = child_of(ch, key[0]);
                 continue;
@@ -177,7 +242,8 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
             }
         }
         if (sp == 0) break;
-        cur = stk[(--sp) * 64];
+        --sp;
+        cur = sp < cap ? stk[sp * 64] : ovf[(size_t)(sp - cap) * ostride + __lane_id()];
     }
     tmax = best_t;
     return best;
@@ -204,6 +270,9 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     int* stk = &lds_stack[wv][0][lane];
+    // this wave's slice of the traversal-stack overflow (uniform; the lane adds its id)
+    const size_t ostride = (size_t)gridDim.x * 256;
+    int* ovf = A.ovf ? A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
 
     const SensorDev& sen = A.sensor;
     const uint32_t Wd = (uint32_t)sen.W, Hd = (uint32_t)sen.H, nl = (uint32_t)A.nl;
@@ -211,7 +280,8 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
     bool live = false, exhausted = false;
     uint64_t idx = 0, pid = 0;
     int depth = 0, prev = -1;
-    f3 o = mk3(0, 0, 0), d = mk3(0, 0, 1);
+    d3 o = d3{0.0, 0.0, 0.0};
+    f3 d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
     // traversal work per lane; the per-path events are flagged per lane (one bit each) and
     // counted per wave with ballots, which keeps the counts in scalar registers
@@ -247,14 +317,25 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                         pid = ((s_abs * Hd + y) * Wd + x) * nl + w;
                         k = kTwoPiF / A.lambda[w];
                         const uint4 r0 = draw(pid, 0, STREAM_SOURCE, A.seed);
-                        const float fx = ((float)x + unif(r0.x)) * sen.pitch;
-                        const float fy = ((float)y + unif(r0.y)) * sen.pitch;
-                        o = mk3(sen.o[0] + fx * sen.u[0] + fy * sen.v[0],
-                                sen.o[1] + fx * sen.u[1] + fy * sen.v[1],
-                                sen.o[2] + fx * sen.u[2] + fy * sen.v[2]);
+                        const double fx = ((double)x + (double)unif(r0.x)) * (double)sen.pitch;
+                        const double fy = ((double)y + (double)unif(r0.y)) * (double)sen.pitch;
+                        o = d3{(double)sen.o[0] + fx * (double)sen.u[0] + fy * (double)sen.v[0],
+                               (double)sen.o[1] + fx * (double)sen.u[1] + fy * (double)sen.v[1],
+                               (double)sen.o[2] + fx * (double)sen.u[2] + fy * (double)sen.v[2]};
                         d = mk3(sen.d[0], sen.d[1], sen.d[2]);
                         beta2 = 2.0f * sen.sigma_um * sen.sigma_um;
                         rho = 0.0f;
+                        // start where the ray enters the scene bounds, so that the float
+                        // ray/triangle arithmetic works on in-scene rather than sensor
+                        // distances; the free-space law composes, so the skipped stretch is
+                        // propagated here
+                        const float tadv = scene_entry(A.scene, o, d);
+                        if (tadv > 0.0f) {
+                            o = add_scaled(o, tadv, d);
+                            const float zb = tadv * 1e6f / k;
+                            rho = zb / beta2;
+                            beta2 = beta2 + zb * zb / beta2;
+                        }
                         alpha = 1.0f;
                         contrib = 0.0f;
                         depth = 0;
@@ -276,12 +357,16 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
         ev |= 1u << EV_SEG;
         RayT ray;
         ray_setup(ray, o, d);
-        const float tmin = 1e-7f * (1.0f + maxabs3(o));
+        const float tmin = 1e-7f * (1.0f + maxabs3(to_f3(o)));
         float thit = FLT_MAX, bu = 0.0f, bv = 0.0f;
-        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk, c_nodes, c_tris, bu, bv);
+        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv);
         if (tri < 0) {
             finish = true;
         } else {
+            const float4* T = A.scene.tris + (size_t)tri * 3;
+            const float4 v0 = T[0], v1 = T[1], v2 = T[2];
+            double t64;
+            refine_hit(o, d, v0, v1, v2, thit, bu, bv, t64);
             // Free-space propagation of the generalized ray (eq. K_free_space_propagation)
             // over the hit distance, zbar = z / |k0|, pre-update beta and rho on the right.
             const float zb = thit * 1e6f / k;
@@ -289,9 +374,7 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
             const float rho_n = rho + zb * orr / beta2;
             beta2 = beta2 + zb * (2.0f * rho + zb * orr / beta2);
             rho = rho_n;
-            const f3 P = o + thit * d;
-            const float4* T = A.scene.tris + (size_t)tri * 3;
-            const float4 v0 = T[0], v1 = T[1], v2 = T[2];
+            const d3 P = d3{o.x + t64 * d.x, o.y + t64 * d.y, o.z + t64 * d.z};
             prev = __float_as_int(v0.w);
             const DMat m = A.scene.mats[__float_as_int(v1.w)];
             f3 ng = normalize3(cross3(mk3(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z),
@@ -353,7 +436,7 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                     f3 om = mk3(0, 0, 0);
                     bool ok = false;
                     float tmax_s = FLT_MAX;
-                    const float tminP = 1e-7f * (1.0f + maxabs3(P));
+                    const float tminP = 1e-7f * (1.0f + maxabs3(to_f3(P)));
                     if (L.kind == 0) {
                         om = ld3(L.dir);
                         ok = true;
@@ -365,11 +448,11 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                         if (tt < 1.0f) {
                             const f3 ax = ld3(L.dir), eu = ld3(L.bu), ev = ld3(L.bv);
                             om = (du / k) * eu + (dv / k) * ev + sqrtf(1.0f - tt) * ax;
-                            const f3 pos = ld3(L.pos);
-                            const float te = dot3(pos - P, ax) / (-dot3(om, ax));
+                            const f3 pp = diff_f3(P, ld3(L.pos));   // P - emitter centre
+                            const float te = dot3(pp, ax) / dot3(om, ax);
                             if (te > tminP) {
-                                const f3 Q = P - te * om;
-                                const float a = dot3(Q - pos, eu) / L.lu, b = dot3(Q - pos, ev) / L.lv;
+                                const f3 qp = pp - te * om;           // Q - emitter centre
+                                const float a = dot3(qp, eu) / L.lu, b = dot3(qp, ev) / L.lv;
                                 if (fabsf(a) <= 1.0f && fabsf(b) <= 1.0f) {
                                     ok = true;
                                     tmax_s = te;
@@ -382,7 +465,7 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                         RayT sray;
                         ray_setup(sray, P, -1.0f * om);
                         float tm = tmax_s, su, sv;
-                        const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, c_nodes, c_tris, su, sv);
+                        const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, su, sv);
                         if (occ < 0) {
                             const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
                             const float kox = -k * dx, koy = -k * dy;
@@ -496,30 +579,19 @@ __global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict_
                       r[12], r[13]);
 }
 
-template <int STACK, bool SUR>
+template <bool SUR>
 static int grid_for(int device) {
     int ncu = 0, nb = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<STACK, SUR>, 256, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, SUR>, 256, 0) != hipSuccess) return 0;
     return ncu * (nb > 0 ? nb : 1);
 }
 
-int trace_grid_size(int device, int stack_depth, bool sur) {
-    if (stack_depth <= 32) return sur ? grid_for<32, true>(device) : grid_for<32, false>(device);
-    if (stack_depth <= 64) return sur ? grid_for<64, true>(device) : grid_for<64, false>(device);
-    return sur ? grid_for<96, true>(device) : grid_for<96, false>(device);
-}
+int trace_grid_size(int device, bool sur) { return sur ? grid_for<true>(device) : grid_for<false>(device); }
 
-template <int STACK>
-static void launch_stack(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.bsdf_mode == 1) hipLaunchKernelGGL((trace_kernel<STACK, true>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((trace_kernel<STACK, false>), dim3(grid), dim3(256), 0, s, a);
-}
-
-hipError_t launch_trace(const TraceArgs& a, int stack_depth, int grid, hipStream_t s) {
-    if (stack_depth <= 32) launch_stack<32>(a, grid, s);
-    else if (stack_depth <= 64) launch_stack<64>(a, grid, s);
-    else launch_stack<96>(a, grid, s);
+hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
+    if (a.bsdf_mode == 1) hipLaunchKernelGGL((trace_kernel<kLdsStack, true>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((trace_kernel<kLdsStack, false>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -159,6 +159,21 @@ def test_deterministic_and_spp_split(R):
     np.testing.assert_allclose((p1 + p2).cpu().numpy(), a.cpu().numpy(), rtol=1e-5, atol=1e-9)
 
 
+def test_traversal_stack_overflow_path(R):
+    """With only 4 traversal-stack entries per lane in LDS, most of the stack of the terrain's
+    BVH (depth 8: up to 27 entries) lives in the workspace's overflow region; traversal order
+    and hence the image and every counter are unchanged."""
+    wl = W.mid_terrain(width=41, height=29, spp=4, n_lambda=8)
+    R.load_workload(wl)
+    o = dict(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed)
+    a, sa = R.trace(wl.lambdas_um, R.opts(**o))
+    b, sb = R.trace(wl.lambdas_um, R.opts(short_lds_stack=True, **o))
+    print("LDS stack 32:", sa, "LDS stack 4:", sb)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    for key in ("paths", "segments", "shadow_rays", "node_visits", "tri_tests"):
+        assert sa[key] == sb[key]
+
+
 def test_edge_cases(R):
     import torch
     wl = W.mid_terrain(width=1, height=1, spp=3, n_lambda=1)

@@ -367,6 +367,33 @@ def large_workload(width=1920, height=1080, spp=64, n_lambda=16, max_depth=6, se
                     spp=spp, max_depth=max_depth, seed=seed, rr_enable=True, rr_p=0.8)
 
 
+def as_float32_inputs(wl: Workload) -> Workload:
+    """The same workload with every real-valued input rounded to float32: the values a float32
+    interface (the GPU library's scene, sensor and source structures) actually receives, so that
+    a float64 consumer of the returned workload sees identical geometry."""
+    def r(x):
+        return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+    def rf(x):
+        return float(np.float32(x))
+
+    sc = wl.scene
+    scene = Scene(verts=r(sc.verts), tris=sc.tris, tri_mat=sc.tri_mat,
+                  materials=[Material(m.kind, rf(m.height_um), rf(m.length_um),
+                                      tuple(float(v) for v in r(m.gdir)), rf(m.reflectance))
+                             for m in sc.materials],
+                  normals=None if sc.normals is None else r(sc.normals))
+    sn = wl.sensor
+    sensor = Sensor(origin=r(sn.origin), axis_u=r(sn.axis_u), axis_v=r(sn.axis_v), dir=r(sn.dir),
+                    width=sn.width, height=sn.height, pitch_m=rf(sn.pitch_m),
+                    sigma_m=rf(sn.sigma_m))
+    sources = [Source(kind=q.kind, dir=r(q.dir), pos=r(q.pos), eu=r(q.eu), ev=r(q.ev),
+                      coherence_radius_um=rf(q.coherence_radius_um), power=rf(q.power))
+               for q in wl.sources]
+    return Workload(wl.name, scene, sensor, sources, r(wl.lambdas_um), spp=wl.spp,
+                    max_depth=wl.max_depth, seed=wl.seed, rr_enable=wl.rr_enable, rr_p=wl.rr_p)
+
+
 # --------------------------------------------------------------------------------------
 # Coherent double-slit / two-point cases
 # --------------------------------------------------------------------------------------
