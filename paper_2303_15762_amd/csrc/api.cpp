@@ -332,8 +332,8 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.scene.mats = static_cast<const grw::DMat*>(c->d_mats);
     a.scene.n_tris = c->n_tris;
     for (int i = 0; i < 3; ++i) {
-        a.scene.lo[i] = c->lo[i];
-        a.scene.hi[i] = c->hi[i];
+        a.scene.lo[i] = c->lo[i] - 1e-3f;
+        a.scene.hi[i] = c->hi[i] + 1e-3f;
     }
     const gr_sensor& s = c->sensor;
     for (int i = 0; i < 3; ++i) {

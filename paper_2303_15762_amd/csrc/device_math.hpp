@@ -225,6 +225,46 @@ __device__ inline float pw_plain(int kind, float h, float L, float refl, float k
     return refl * s * (1.0f / kTwoPiF);
 }
 
+// Smallest n with u < sum_{i <= n} Poisson(i; g), by inversion of the CDF in double precision
+// (the decision must not depend on FP32 rounding of a long sum); terms below g - 7 sqrt(g)
+// hold < 1e-11 mass and are skipped.  Kept out of line: its double-precision exp/log constants
+// would otherwise be hoisted into registers for the whole path loop.
+__device__ __noinline__ int poisson_inverse(double g, float u0) {
+    int n = 0;
+    if (g > 0.0) {
+        const double sq = sqrt(g);
+        const int mlo = g > 49.0 ? (int)floor(g - 7.0 * sq) : 0;
+        const int mhi = min((int)ceil(g + 20.0 * sq + 40.0), mlo + 65536);
+        // log of the first term: log Poisson(mlo; g) via Stirling (mlo >= 10 here) or exactly
+        double lw;
+        if (mlo == 0) {
+            lw = -g;
+        } else {
+            const double mf = (double)mlo, d = mf - g;
+            lw = -mf * log1p(d / g) + d - 0.5 * log(6.283185307179586 * mf) - 1.0 / (12.0 * mf) +
+                 1.0 / (360.0 * mf * mf * mf);
+        }
+        double w = exp(lw), c = 0.0;
+        const double uu = (double)u0;
+        n = mhi;
+        // w_{i+1} = w_i g / (i + 1); the reciprocal by the hardware estimate and one
+        // Newton step (relative error ~1e-16, as a correctly rounded division)
+        double t = (double)(mlo + 1);
+        for (int i = mlo; i <= mhi; ++i) {
+            c += w;
+            if (uu < c) {
+                n = i;
+                break;
+            }
+            const double r0 = __builtin_amdgcn_rcp(t);
+            const double r1 = fma(r0, fma(-t, r0, 1.0), r0);
+            w *= g * r1;
+            t += 1.0;
+        }
+    }
+    return n;
+}
+
 // ------------------------------------------------------------------------------------------
 // Continuation sampling from the unwindowed kernel f_inf (the delta-lobe limit of p_w),
 // taking the generalized ray's own travel direction as the incident wave (time reversal is
@@ -300,41 +340,8 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         weight = m.refl * W;
         return 0;
     }
-    // rough: Poisson term by inversion of the CDF in double precision (the decision must not
-    // depend on FP32 rounding of a long sum); terms below g - 7 sqrt(g) hold < 1e-11 mass.
-    const double g = 4.0 * (double)k2 * (double)ci * (double)ci * (double)m.h * (double)m.h;
-    int n = 0;
-    if (g > 0.0) {
-        const double sq = sqrt(g);
-        const int mlo = g > 49.0 ? (int)floor(g - 7.0 * sq) : 0;
-        const int mhi = min((int)ceil(g + 20.0 * sq + 40.0), mlo + 65536);
-        // log of the first term: log Poisson(mlo; g) via Stirling (mlo >= 10 here) or exactly
-        double lw;
-        if (mlo == 0) {
-            lw = -g;
-        } else {
-            const double mf = (double)mlo, d = mf - g;
-            lw = -mf * log1p(d / g) + d - 0.5 * log(6.283185307179586 * mf) - 1.0 / (12.0 * mf) +
-                 1.0 / (360.0 * mf * mf * mf);
-        }
-        double w = exp(lw), c = 0.0;
-        const double uu = (double)u0;
-        n = mhi;
-        // w_{i+1} = w_i g / (i + 1); the reciprocal by the hardware estimate and one
-        // Newton step (relative error ~1e-16, as a correctly rounded division)
-        double t = (double)(mlo + 1);
-        for (int i = mlo; i <= mhi; ++i) {
-            c += w;
-            if (uu < c) {
-                n = i;
-                break;
-            }
-            const double r0 = __builtin_amdgcn_rcp(t);
-            const double r1 = fma(r0, fma(-t, r0, 1.0), r0);
-            w *= g * r1;
-            t += 1.0;
-        }
-    }
+    // rough: Poisson term by inversion of the CDF in double precision
+    const int n = poisson_inverse(4.0 * (double)k2 * (double)ci * (double)ci * (double)m.h * (double)m.h, u0);
     float z1, z2;
     box_muller(u1, u2, z1, z2);
     const float sd = sqrtf(2.0f * (float)n) / m.L;

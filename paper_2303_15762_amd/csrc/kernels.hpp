@@ -19,11 +19,12 @@ struct SceneDev {
     const float4* tnorm;     // 3 float4 per triangle: per-vertex shading normals (zero = geometric)
     const DMat* mats;
     int64_t n_tris;
-    float lo[3], hi[3];      // bounds of all vertices
+    float lo[3], hi[3];      // bounds of all vertices widened by 1 mm
 };
 
 struct SensorDev {
-    float o[3], u[3], v[3], d[3];
+    double o[3], u[3], v[3];  // origin and pixel axes (the float inputs, exactly)
+    float d[3];
     int W, H;
     float pitch;      // metres
     float sigma_um;

@@ -33,14 +33,14 @@ __device__ __forceinline__ f3 diff_f3(d3 a, f3 b) {
     return mk3((float)(a.x - (double)b.x), (float)(a.y - (double)b.y), (float)(a.z - (double)b.z));
 }
 
-// Distance along (o, d) at which the ray enters the scene bounds widened by 1 mm, or 0 when
-// it starts inside or misses them.  The float slab test errs by far less than the margin.
+// Distance along (o, d) at which the ray enters the scene bounds (widened by 1 mm on the
+// host), or 0 when it starts inside or misses them.  The float slab test errs by far less
+// than the margin.
 __device__ __forceinline__ float scene_entry(const SceneDev& S, d3 o, f3 d) {
-    const float m = 1e-3f;
     const f3 of = to_f3(o);
-    const float t0x = (S.lo[0] - m - of.x) / d.x, t1x = (S.hi[0] + m - of.x) / d.x;
-    const float t0y = (S.lo[1] - m - of.y) / d.y, t1y = (S.hi[1] + m - of.y) / d.y;
-    const float t0z = (S.lo[2] - m - of.z) / d.z, t1z = (S.hi[2] + m - of.z) / d.z;
+    const float t0x = (S.lo[0] - of.x) / d.x, t1x = (S.hi[0] - of.x) / d.x;
+    const float t0y = (S.lo[1] - of.y) / d.y, t1y = (S.hi[1] - of.y) / d.y;
+    const float t0z = (S.lo[2] - of.z) / d.z, t1z = (S.hi[2] - of.z) / d.z;
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
     return (tn > 0.0f && tn <= tf) ? tn : 0.0f;
@@ -319,9 +319,8 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                         const uint4 r0 = draw(pid, 0, STREAM_SOURCE, A.seed);
                         const double fx = ((double)x + (double)unif(r0.x)) * (double)sen.pitch;
                         const double fy = ((double)y + (double)unif(r0.y)) * (double)sen.pitch;
-                        o = d3{(double)sen.o[0] + fx * (double)sen.u[0] + fy * (double)sen.v[0],
-                               (double)sen.o[1] + fx * (double)sen.u[1] + fy * (double)sen.v[1],
-                               (double)sen.o[2] + fx * (double)sen.u[2] + fy * (double)sen.v[2]};
+                        o = d3{sen.o[0] + fx * sen.u[0] + fy * sen.v[0], sen.o[1] + fx * sen.u[1] + fy * sen.v[1],
+                               sen.o[2] + fx * sen.u[2] + fy * sen.v[2]};
                         d = mk3(sen.d[0], sen.d[1], sen.d[2]);
                         beta2 = 2.0f * sen.sigma_um * sen.sigma_um;
                         rho = 0.0f;
