@@ -41,6 +41,7 @@ struct gr_ctx {
     std::vector<gr_source> sources;
     int grid_plain = 0;              // persistent grids (blocks), set at scene upload
     int grid_sur = 0;
+    int grid_batch = 0;              // blocks of the batched network pass
     grw::SurrogateState sur;
 };
 
@@ -90,6 +91,15 @@ constexpr int kMaxStack = 256;
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack; }
+
+// The learned-p_w path renders in launches of at most this many paths: each launch queues at
+// most one query per path and interaction (32 B) and owns one result float per slot.
+constexpr uint64_t kSurChunk = 1ull << 22;
+
+struct WsLayout {
+    size_t records = 0, ovf = 0, queue = 0, dense = 0, total = 0;
+    uint64_t chunk = 0;
+};
 
 // Traversal-stack entries per lane that do not fit the LDS part.
 uint32_t overflow_entries(const gr_ctx* c, const gr_trace_opts* o) {
@@ -221,6 +231,11 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     c->build_ms = std::chrono::duration<float, std::milli>(t1 - t0).count();
     c->grid_plain = grw::trace_grid_size(c->device, false);
     c->grid_sur = grw::trace_grid_size(c->device, true);
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
+        c->grid_batch = 4 * std::max(ncu, 1);
+    }
     if (c->grid_plain <= 0 || c->grid_sur <= 0) {
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
@@ -282,15 +297,34 @@ int gr_set_sources(gr_ctx* c, const gr_source* s, int32_t n) {
     return GR_OK;
 }
 
+namespace {
+// header | path records | traversal-stack overflow of the scene's BVH (per persistent lane) |
+// learned-p_w queue and per-(path, interaction) results of one launch
+WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
+    WsLayout L;
+    const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
+    const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
+    const size_t lanes = (size_t)std::max(c->grid_plain, c->grid_sur) * 256;
+    L.records = kWsHeader;
+    L.ovf = L.records + align256((size_t)n * sizeof(float));
+    L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
+    L.dense = L.queue;
+    L.total = L.queue;
+    if (o->bsdf_mode != GR_BSDF_PLAIN) {
+        L.chunk = std::min<uint64_t>(n, kSurChunk);
+        const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
+        L.dense = L.queue + align256((size_t)slots * grw::kSurQueryBytes);
+        L.total = L.dense + align256((size_t)slots * sizeof(float));
+    }
+    return L;
+}
+}  // namespace
+
 int gr_workspace_size(const gr_ctx* c, const gr_trace_opts* o, int32_t nl, size_t* bytes) {
     if (!c || !o || !bytes) return GR_E_INVALID;
     if (!c->has_sensor) return GR_E_NO_SCENE;
     if (o->spp_count < 0 || nl < 1 || nl > grw::kMaxLambda) return GR_E_INVALID;
-    const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
-    // header | path records | traversal-stack overflow of the scene's BVH (per persistent lane)
-    const size_t lanes = (size_t)std::max(c->grid_plain, c->grid_sur) * 256;
-    *bytes = kWsHeader + align256((size_t)(per * (uint64_t)o->spp_count) * sizeof(float)) +
-             lanes * overflow_entries(c, o) * sizeof(int);
+    *bytes = ws_layout(c, o, nl).total;
     return GR_OK;
 }
 
@@ -382,24 +416,46 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.bsdf_mode = o->bsdf_mode;
     if (o->bsdf_mode != GR_BSDF_PLAIN) grw::surrogate_fill(c->sur, a.sur);
     char* base = static_cast<char*>(ws);
+    const WsLayout WL = ws_layout(c, o, nl);
+    const uint64_t total = a.n_paths;
     a.counter = reinterpret_cast<unsigned long long*>(base);
+    a.sq_count = reinterpret_cast<unsigned long long*>(base + 128);
     a.stats = reinterpret_cast<unsigned long long*>(base + 256);
-    a.records = reinterpret_cast<float*>(base + kWsHeader);
+    a.records = reinterpret_cast<float*>(base + WL.records);
     a.lds_cap = lds_cap_for(o);
     a.ovf_n = overflow_entries(c, o);
-    a.ovf = a.ovf_n ? reinterpret_cast<int*>(base + kWsHeader + align256((size_t)a.n_paths * sizeof(float)))
-                    : nullptr;
+    a.ovf = a.ovf_n ? reinterpret_cast<int*>(base + WL.ovf) : nullptr;
+    const bool defer = o->bsdf_mode == GR_BSDF_SURROGATE_BF16;
+    a.sq = defer ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
+    float* dense = defer ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
 
     GR_HIP(c, hipSetDevice(c->device));
-    const int grid = o->bsdf_mode == GR_BSDF_SURROGATE_BF16 ? c->grid_sur : c->grid_plain;
+    const int grid = defer ? c->grid_sur : c->grid_plain;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (st)
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));
     GR_HIP(c, hipMemsetAsync(ws, 0, kWsHeader, c->stream));
     if (st) GR_HIP(c, hipEventRecord(ev[0], c->stream));
-    if (a.n_paths > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
+    if (!defer) {
+        a.path_begin = 0;
+        if (total > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
+    } else {
+        // launches of at most WL.chunk paths: trace (queries queued), one batched network
+        // pass over the queue, results added to the path records in a fixed order
+        const int D = o->max_depth;
+        for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
+            const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
+            a.path_begin = p0;
+            a.n_paths = pn;
+            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, pn * (uint64_t)D, c->stream));
+            GR_HIP(c, grw::launch_trace(a, grid, c->stream));
+            GR_HIP(c, grw::launch_sur_batch(c->sur, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
+            GR_HIP(c, grw::launch_sur_merge(dense, D, a.records, p0, pn, c->stream));
+        }
+        a.n_paths = total;
+    }
     if (st) GR_HIP(c, hipEventRecord(ev[1], c->stream));
-    if (a.n_paths > 0)
+    if (total > 0)
         GR_HIP(c, grw::launch_reduce(a.records, image, o->spp_count, (uint32_t)s.height, (uint32_t)s.width,
                                      (uint32_t)nl, c->stream));
     if (st) {

@@ -39,15 +39,17 @@ struct SourceDev {
     float rc_um, power;
 };
 
-// Surrogate (learned p_w) parameters prepared for the matrix cores.
+// Trained domain of the learned p_w (the trace kernel encodes queries; a batched
+// matrix-core kernel evaluates them after the trace).
 struct SurrogateDev {
-    const void* wf;           // packed BF16 weights (mlp_core.hpp layout)
-    const float* bias;        // [4][64]
-    const float* w5;          // [64]
-    const float* b5;          // [1]
     float gmin, gmax, smin, smax;
     int enabled;
 };
+
+// One deferred learned-p_w query, 32 bytes: the 10 network inputs as bfloat16 pairs (the
+// network rounds its inputs to bfloat16 anyway), the contribution scale (already divided by
+// the sample count), log of the lobe peak, and the (path, depth) slot of the result.
+constexpr int kSurQueryBytes = 32;
 
 struct TraceArgs {
     SceneDev scene;
@@ -57,7 +59,8 @@ struct TraceArgs {
     int nl;
     float lambda[kMaxLambda];
     int64_t spp_begin;
-    uint64_t n_paths;          // spp_count * H * W * nl
+    uint64_t path_begin;       // first path index of this launch
+    uint64_t n_paths;          // paths of this launch: [path_begin, path_begin + n_paths)
     uint32_t per_sample;       // H * W * nl
     float inv_spp_norm;
     int max_depth;
@@ -67,6 +70,8 @@ struct TraceArgs {
     uint64_t seed;
     int bsdf_mode;
     SurrogateDev sur;
+    uint4* sq;                       // deferred learned-p_w queries, 2 uint4 each, or null
+    unsigned long long* sq_count;
     float* records;                  // [n_paths]
     int* ovf;                        // traversal stack overflow [ovf_n][grid * 256], or null
     uint32_t ovf_n;                  // overflow entries per lane
@@ -84,6 +89,11 @@ enum {
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
                          uint32_t nl, hipStream_t s);
+// Zero the path dispenser, the query count and n floats of per-(path, depth) results.
+hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count, float* dense, uint64_t n,
+                              hipStream_t s);
+// records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
+hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
 int trace_grid_size(int device, bool sur);
 
 // Batch p_w evaluation (trace.hip).

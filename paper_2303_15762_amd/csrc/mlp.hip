@@ -347,6 +347,56 @@ __global__ __launch_bounds__(256) void sur_eval_kernel(const MlpDev M, SurDomain
     out[i] = v;
 }
 
+// ------------------------------------------------------------------------------------------
+// Deferred queries of a trace: one wave per 64 queries, grid-stride over the count the trace
+// kernel left in device memory (every lane of a wave takes part in the matrix-core pass).
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void bf16_unpair(uint32_t u, float& a, float& b) {
+    a = __uint_as_float(u << 16);
+    b = __uint_as_float(u & 0xFFFF0000u);
+}
+
+__global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const uint4* __restrict__ q,
+                                                        const unsigned long long* __restrict__ count,
+                                                        float* __restrict__ dense, unsigned long long* stats) {
+    __shared__ float stage[4][64 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint64_t n = *count;
+    for (uint64_t base = ((uint64_t)blockIdx.x * 4 + wv) * 64; base < n; base += (uint64_t)gridDim.x * 256) {
+        const uint64_t i = base + lane;
+        float x[MLP_IN] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        float scale = 0.0f, logpeak = 0.0f;
+        uint32_t slot = 0;
+        if (i < n) {
+            const uint4 a = q[2 * i], b = q[2 * i + 1];
+            bf16_unpair(a.x, x[0], x[1]);
+            bf16_unpair(a.y, x[2], x[3]);
+            bf16_unpair(a.z, x[4], x[5]);
+            bf16_unpair(a.w, x[6], x[7]);
+            bf16_unpair(b.x, x[8], x[9]);
+            scale = __uint_as_float(b.y);
+            logpeak = __uint_as_float(b.z);
+            slot = b.w;
+        }
+        const float y = mlp_forward_wave(M, x, stage[wv], nullptr);
+        if (i < n) {
+            float v = scale * __expf(y + logpeak);
+            if (!isfinite(v)) {
+                atomicAdd(stats + ST_NONFINITE, 1ull);
+                v = 0.0f;
+            }
+            dense[slot] = v;
+        }
+    }
+}
+
+hipError_t launch_sur_batch(const SurrogateState& s, const uint4* queries, const unsigned long long* count,
+                            float* dense, unsigned long long* stats, int grid, hipStream_t stream) {
+    const MlpDev M = mlp_dev(s.d_params, s.d_pack);
+    hipLaunchKernelGGL(sur_batch_kernel, dim3(grid), dim3(256), 0, stream, M, queries, count, dense, stats);
+    return hipGetLastError();
+}
+
 void surrogate_free(SurrogateState& s) {
     if (s.d_pack) (void)hipFree(s.d_pack);
     if (s.d_params) (void)hipFree(s.d_params);
@@ -354,11 +404,6 @@ void surrogate_free(SurrogateState& s) {
 }
 
 void surrogate_fill(const SurrogateState& s, SurrogateDev& d) {
-    const char* b = static_cast<const char*>(s.d_pack);
-    d.wf = b;
-    d.bias = reinterpret_cast<const float*>(b + kPackWf + kPackWb);
-    d.w5 = s.d_params + OFF_W5;
-    d.b5 = s.d_params + OFF_B5;
     d.gmin = s.domain[0];
     d.gmax = s.domain[1];
     d.smin = s.domain[2];

@@ -12,6 +12,8 @@
 // Algorithm 1 under the interactive assumption of Sec. "Interactive Rendering".
 #include <float.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "mlp_core.hpp"
 
@@ -258,14 +260,23 @@ __device__ __forceinline__ unsigned long long wave_sum(uint32_t v) {
     return x;
 }
 
-// SUR: instantiate the learned-p_w path (its matrix-core pass raises the register budget, so
-// the plain path is a separate instantiation).
 enum { EV_PATH = 0, EV_SEG, EV_SHADOW, EV_SUR, EV_FALLBACK, EV_EVANESCENT, EV_BACKFACING, EV_NONFINITE, EV_COUNT };
 
-// The plain instantiation asks for 4 waves per SIMD (128 VGPRs): a few path-state values
-// spill to scratch, which costs less than the latency hidden by the fourth wave.
-template <int STACK, bool SUR>
-__global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs A) {
+// bfloat16 pair (a in the low half), rounded to nearest even as the network's input stage does.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+    uint32_t ua = __float_as_uint(a), ub = __float_as_uint(b);
+    ua += 0x7FFFu + ((ua >> 16) & 1u);
+    ub += 0x7FFFu + ((ub >> 16) & 1u);
+    return (ua >> 16) | (ub & 0xFFFF0000u);
+}
+
+// DEFER: rough-surface measurements inside the learned model's domain are not evaluated here;
+// their encoded queries go to a queue that one batched matrix-core kernel evaluates after the
+// trace (its results are added to the path records in a fixed order).
+// Both instantiations ask for 4 waves per SIMD (128 VGPRs): a few path-state values spill to
+// scratch, which costs less than the latency hidden by the fourth wave.
+template <int STACK, bool DEFER>
+__global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -298,12 +309,12 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                 unsigned long long base = 0;
                 if (lane == first) base = atomicAdd(A.counter, (unsigned long long)cnt);
                 base = __shfl(base, first);
-                if (base + cnt >= A.n_paths) exhausted = true;
+                if (base + cnt >= A.n_paths) exhausted = true;   // n_paths: paths of this launch
                 if (!live) {
                     const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-                    const uint64_t my = base + rank;
-                    if (my < A.n_paths) {
+                    const uint64_t my = A.path_begin + base + rank;
+                    if (base + rank < A.n_paths) {
                         // Sourcing (Sec. "Interactive Rendering"): mean position uniform on the
                         // pixel, mean direction the sensor axis, beta^2 = 2 sigma^2, rho = 0,
                         // alpha = 1.
@@ -349,9 +360,6 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
 
         // ---- one segment of every live path ------------------------------------------
         bool finish = false;
-        bool sur_want = false;           // this lane's measurement waits for the network
-        float sur_scale = 0.0f, sur_logpeak = 0.0f;
-        float sur_x[MLP_IN];
         if (live) {
         ev |= 1u << EV_SEG;
         RayT ray;
@@ -470,16 +478,34 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
                             const float kox = -k * dx, koy = -k * dy;
                             const float scale = alpha * L.power * (float)A.nsrc;
                             int e = 0;
-                            if (SUR && m.kind == MAT_ROUGH) {
+                            if (DEFER && m.kind == MAT_ROUGH) {
                                 const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
-                                e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sur_x, sur_logpeak);
+                                float sx[MLP_IN], slp;
+                                e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sx, slp);
                                 if (e == 0) ev |= 1u << EV_FALLBACK;
+                                // append the query (one atomic per wave); every (path, depth)
+                                // appends at most once, so the queue and the result slots are
+                                // sized for the launch's paths x max_depth
+                                const bool want = e == 1;
+                                const unsigned long long qm = __ballot(want);
+                                if (want) {
+                                    ev |= 1u << EV_SUR;
+                                    const int leader = __ffsll((long long)qm) - 1;
+                                    unsigned long long qb = 0;
+                                    if (lane == leader) qb = atomicAdd(A.sq_count, (unsigned long long)__popcll(qm));
+                                    qb = __shfl(qb, leader);
+                                    const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+                                    uint4* q = A.sq + 2 * (qb + r);
+                                    const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
+                                    q[0] = make_uint4(bf16_pair(sx[0], sx[1]), bf16_pair(sx[2], sx[3]),
+                                                      bf16_pair(sx[4], sx[5]), bf16_pair(sx[6], sx[7]));
+                                    q[1] = make_uint4(bf16_pair(sx[8], sx[9]),
+                                                      __float_as_uint(scale * m.refl * A.inv_spp_norm),
+                                                      __float_as_uint(slp), slot);
+                                }
                             }
-                            if (e == 1) {
-                                sur_want = true;
-                                sur_scale = scale * m.refl;
-                                ev |= 1u << EV_SUR;
-                            } else if (e == 0) {
+                            if (e == 0) {
                                 contrib += scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy,
                                                             sxx, syy, sxy, 1.0f, 0.0f);
                             }
@@ -514,20 +540,6 @@ __global__ __launch_bounds__(256, SUR ? 1 : 4) void trace_kernel(const TraceArgs
             }
         }
         }   // live
-        // ---- learned p_w: one matrix-core pass for the whole wave -------------------------
-        if (SUR && __any(sur_want)) {
-            float xin[MLP_IN];
-#pragma unroll
-            for (int f = 0; f < MLP_IN; ++f) xin[f] = sur_want ? sur_x[f] : 0.0f;
-            MlpDev M;
-            M.wf = static_cast<const bf16x8*>(A.sur.wf);
-            M.bias = A.sur.bias;
-            M.w5 = A.sur.w5;
-            M.b5 = A.sur.b5;
-            // the wave's traversal stack is idle here and holds the 64 x 16 input staging
-            const float y = mlp_forward_wave(M, xin, reinterpret_cast<float*>(&lds_stack[wv][0][0]), nullptr);
-            if (sur_want) contrib += sur_scale * __expf(y + sur_logpeak);
-        }
         if (finish) {
             float val = contrib * A.inv_spp_norm;
             if (!isfinite(val)) {
@@ -578,11 +590,11 @@ __global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict_
                       r[12], r[13]);
 }
 
-template <bool SUR>
+template <bool DEFER>
 static int grid_for(int device) {
     int ncu = 0, nb = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, SUR>, 256, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER>, 256, 0) != hipSuccess) return 0;
     return ncu * (nb > 0 ? nb : 1);
 }
 
@@ -591,6 +603,39 @@ int trace_grid_size(int device, bool sur) { return sur ? grid_for<true>(device) 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
     if (a.bsdf_mode == 1) hipLaunchKernelGGL((trace_kernel<kLdsStack, true>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((trace_kernel<kLdsStack, false>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void chunk_reset_kernel(unsigned long long* counter, unsigned long long* sq_count,
+                                                          float* dense, uint64_t n) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) {
+        *counter = 0ull;
+        *sq_count = 0ull;
+    }
+    for (uint64_t i = t; i < n; i += (uint64_t)gridDim.x * blockDim.x) dense[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void sur_merge_kernel(const float* __restrict__ dense, int depth,
+                                                        float* __restrict__ records, uint64_t p0, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int d = 0; d < depth; ++d) s += dense[i * depth + d];
+    records[p0 + i] += s;
+}
+
+hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count, float* dense, uint64_t n,
+                              hipStream_t s) {
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256 + 1, 4096);
+    hipLaunchKernelGGL(chunk_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, counter, sq_count, dense, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(sur_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dense, depth, records,
+                       p0, n);
     return hipGetLastError();
 }
 

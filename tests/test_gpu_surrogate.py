@@ -88,3 +88,15 @@ def test_surrogate_cost_against_closed_form(trained):
     print(f"p_w of {q.shape[0]} rough queries: closed form {t[0]:.3f} ms, surrogate {t[1]:.3f} ms,"
           f" speed-up {t[0] / t[1]:.2f}x")
     assert t[1] > 0 and t[0] > 0
+
+
+def test_surrogate_trace_deterministic(trained):
+    """The queued network evaluations land in per-(path, interaction) slots that are added to
+    the path records in a fixed order: two renders are bitwise identical."""
+    R, S, p, hist, torch = trained
+    wl = W.mid_terrain(width=64, height=48, spp=8, n_lambda=8)
+    R.load_workload(wl)
+    a, sa = R.render_workload(wl, bsdf_mode=1)
+    b, sb = R.render_workload(wl, bsdf_mode=1)
+    assert sa["surrogate_evals"] > 0 and sa["surrogate_evals"] == sb["surrogate_evals"]
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
