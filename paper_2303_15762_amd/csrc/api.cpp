@@ -94,7 +94,7 @@ int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_
 
 // The learned-p_w path renders in launches of at most this many paths: each launch queues at
 // most one query per path and interaction (32 B) and owns one result float per slot.
-constexpr uint64_t kSurChunk = 1ull << 22;
+constexpr uint64_t kSurChunk = 1ull << 24;
 
 struct WsLayout {
     size_t records = 0, ovf = 0, queue = 0, dense = 0, total = 0;
