@@ -190,6 +190,10 @@ int gr_workspace_paths(const gr_ctx* ctx, void* workspace, float** paths_dev);
  *   workspace : device, >= gr_workspace_size bytes.
  *   image     : device float [n_lambda][height][width]; contributions are ADDED to it.
  *   stats     : optional; when given the call synchronises the stream and fills it.
+ * Surrogate modes: in-domain rough-surface measurements are queued by the trace kernel and
+ * evaluated by one batched matrix-core pass per launch of at most 16M paths (the workspace
+ * holds that launch's queue, 32 B per path and interaction, and one float per slot); the
+ * results are added to the path records in a fixed order.
  * Same options and seed give a bitwise identical image. */
 int gr_trace(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_trace_opts* opts,
              void* workspace, size_t workspace_bytes, float* image, gr_stats* stats);
@@ -206,7 +210,10 @@ int gr_bsdf_eval(gr_ctx* ctx, const float* queries, int64_t n, int32_t mode, flo
  * 10 -> 64 -> 64 -> 64 -> 64 -> 1 perceptron with GELU (tanh form).
  * params: device float [13249] laid out W1[10][64], b1[64], W2[64][64], b2, W3, b3, W4, b4,
  * W5[64][1], b5[1] (row-major [fan_in][fan_out]; a layer computes x W + b).  The matrix-core
- * passes round weights and activations to bfloat16 and accumulate in FP32.
+ * passes accumulate in FP32.  GR_BSDF_SURROGATE_BF16 rounds weights and activations to
+ * bfloat16.  GR_BSDF_SURROGATE_FP8 quantizes them to OCP E4M3: weights per layer with scale
+ * max|W| / 448, activations per 64 queries and layer with scale max|a| / 448; the output
+ * layer runs on the vector ALUs in FP32 in both modes.
  *
  * Input encoding of a query (sur_encode in the sources; rough surfaces only): the tangential
  * transfer in lobe widths sqrt(2 g) / l (g = (q_z s)^2), the incident tangential direction,
@@ -223,7 +230,7 @@ int gr_surrogate_samples(gr_ctx* ctx, int64_t n, uint64_t seed, const float* dom
                          float* y_out, float* q_out);
 /* Device workspace for gr_mlp_forward / gr_mlp_backward on n rows. */
 int gr_mlp_workspace_size(int64_t n, size_t* bytes);
-/* y [n] = network(x [n][10]); dtype GR_BSDF_SURROGATE_BF16. */
+/* y [n] = network(x [n][10]); dtype GR_BSDF_SURROGATE_BF16 or GR_BSDF_SURROGATE_FP8. */
 int gr_mlp_forward(gr_ctx* ctx, const float* params, const float* x, int64_t n, int32_t dtype,
                    void* workspace, float* y);
 /* Gradient of the mean squared error (1/n) sum (network(x_i) - target_i)^2 into grad (device
@@ -234,8 +241,8 @@ int gr_mlp_backward(gr_ctx* ctx, const float* params, const float* x, const floa
  * moments (start at zero); step t >= 1. */
 int gr_adam_step(gr_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t t,
                  float lr, float beta1, float beta2, float eps);
-/* Install a trained network for GR_BSDF_SURROGATE_BF16 (copied and packed on the device;
- * allocates on first use). */
+/* Install a trained network for both surrogate modes (copied and packed on the device in
+ * bfloat16 and in E4M3; allocates on first use). */
 int gr_set_surrogate(gr_ctx* ctx, const float* params, const float* domain);
 
 /* Coherent measurement of mutually coherent emitters (Sec. "Linearity of Generalized Rays",

@@ -81,3 +81,46 @@ def adam_step(p, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1.0 - b1 ** t)
     vh = v / (1.0 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------------------------------------------------
+# OCP FP8 E4M3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; largest finite 448,
+# smallest subnormal 2^-9) and the quantized forward pass of the FP8 surrogate mode.
+# ------------------------------------------------------------------------------------------
+E4M3_MAX = 448.0
+
+
+def e4m3_round(v):
+    """Round to the nearest E4M3 value, ties to even; |v| <= 448 is expected (clamped)."""
+    v = np.clip(np.asarray(v, np.float64), -E4M3_MAX, E4M3_MAX)
+    a = np.abs(v)
+    # spacing: 2^-9 below the smallest normal 2^-6, else 2^(floor(log2 a) - 3)
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -6)))
+    step = 2.0 ** (e - 3)
+    return np.sign(v) * np.round(a / step) * step     # np.round: half to even
+
+
+def _scale(amax):
+    return (amax / E4M3_MAX) if amax > 1e-30 else 0.0
+
+
+def forward_e4m3(Ws, bs, X, block=64):
+    """Forward pass with the FP8 mode's quantization: each hidden layer's weights scaled by
+    max|W| / 448 and rounded to E4M3; each layer's input activations, per block of `block`
+    rows, scaled by their max |a| / 448 and rounded to E4M3; products and sums exact (FP64),
+    then multiplied back by both scales; the output layer unquantized."""
+    X = np.asarray(X, np.float64)
+    out = np.zeros(X.shape[0])
+    wq, ws = [], []
+    for W in Ws[:-1]:
+        s = _scale(np.abs(W).max())
+        ws.append(s)
+        wq.append(e4m3_round(W / s) if s > 0 else np.zeros_like(W))
+    for r0 in range(0, X.shape[0], block):
+        a = X[r0:r0 + block]
+        for l in range(len(Ws) - 1):
+            s = _scale(np.abs(a).max())
+            aq = e4m3_round(a / s) if s > 0 else np.zeros_like(a)
+            a = gelu((aq @ wq[l]) * (ws[l] * s) + bs[l])
+        out[r0:r0 + block] = (a @ Ws[-1] + bs[-1])[:, 0]
+    return out

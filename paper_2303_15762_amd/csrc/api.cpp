@@ -349,7 +349,6 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
         return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
-    if (o->bsdf_mode == GR_BSDF_SURROGATE_FP8) return fail(c, GR_E_UNSUPPORTED, "trace: FP8 surrogate in the tracer");
     if (o->bsdf_mode != GR_BSDF_PLAIN && (c->sensor.width * (int64_t)c->sensor.height < 1))
         return fail(c, GR_E_INVALID, "trace: sensor");
     size_t need = 0;
@@ -425,7 +424,8 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.lds_cap = lds_cap_for(o);
     a.ovf_n = overflow_entries(c, o);
     a.ovf = a.ovf_n ? reinterpret_cast<int*>(base + WL.ovf) : nullptr;
-    const bool defer = o->bsdf_mode == GR_BSDF_SURROGATE_BF16;
+    const bool defer = o->bsdf_mode != GR_BSDF_PLAIN;
+    const bool fp8 = o->bsdf_mode == GR_BSDF_SURROGATE_FP8;
     a.sq = defer ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
     float* dense = defer ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
 
@@ -449,7 +449,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
             a.n_paths = pn;
             GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, pn * (uint64_t)D, c->stream));
             GR_HIP(c, grw::launch_trace(a, grid, c->stream));
-            GR_HIP(c, grw::launch_sur_batch(c->sur, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
+            GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
             GR_HIP(c, grw::launch_sur_merge(dense, D, a.records, p0, pn, c->stream));
         }
         a.n_paths = total;
@@ -488,13 +488,14 @@ int gr_bsdf_eval(gr_ctx* c, const float* q, int64_t n, int32_t mode, float* out)
     if (n < 0 || (n > 0 && (!q || !out))) return fail(c, GR_E_INVALID, "bsdf_eval: arguments");
     if (mode != GR_BSDF_PLAIN) {
         if (!c->sur.ready) return fail(c, GR_E_INVALID, "bsdf_eval: surrogate mode without gr_set_surrogate");
-        if (mode == GR_BSDF_SURROGATE_FP8) return fail(c, GR_E_UNSUPPORTED, "bsdf_eval: FP8");
+        if (mode != GR_BSDF_SURROGATE_BF16 && mode != GR_BSDF_SURROGATE_FP8)
+            return fail(c, GR_E_INVALID, "bsdf_eval: mode %d", mode);
     }
     GR_HIP(c, hipSetDevice(c->device));
     if (mode == GR_BSDF_PLAIN) {
         GR_HIP(c, grw::launch_bsdf_eval(q, n, out, c->stream));
     } else {
-        GR_HIP(c, grw::launch_bsdf_eval_surrogate(c->sur, q, n, out, c->stream));
+        GR_HIP(c, grw::launch_bsdf_eval_surrogate(c->sur, mode == GR_BSDF_SURROGATE_FP8, q, n, out, c->stream));
     }
     return GR_OK;
 }
@@ -531,10 +532,11 @@ int gr_mlp_workspace_size(int64_t n, size_t* bytes) {
 int gr_mlp_forward(gr_ctx* c, const float* params, const float* x, int64_t n, int32_t dtype, void* ws, float* y) {
     if (!c) return GR_E_INVALID;
     if (!params || !ws || n < 0 || (n > 0 && (!x || !y))) return fail(c, GR_E_INVALID, "mlp_forward: arguments");
-    if (dtype != GR_BSDF_SURROGATE_BF16) return fail(c, GR_E_UNSUPPORTED, "mlp_forward: only BF16 operands");
+    if (dtype != GR_BSDF_SURROGATE_BF16 && dtype != GR_BSDF_SURROGATE_FP8)
+        return fail(c, GR_E_INVALID, "mlp_forward: dtype %d", dtype);
     if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) return fail(c, GR_E_INVALID, "mlp_forward: workspace alignment");
     GR_HIP(c, hipSetDevice(c->device));
-    GR_HIP(c, grw::mlp_forward(params, x, n, ws, y, c->stream));
+    GR_HIP(c, grw::mlp_forward(params, x, n, dtype == GR_BSDF_SURROGATE_FP8, ws, y, c->stream));
     return GR_OK;
 }
 

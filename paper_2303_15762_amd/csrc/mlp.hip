@@ -3,6 +3,7 @@
 // deterministic gradient reduction, Adam, and the surrogate p_w evaluator.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -57,6 +58,54 @@ constexpr size_t kPackWf = (size_t)FWD_FRAGS * 64 * 16;
 constexpr size_t kPackWb = (size_t)BWD_FRAGS * 64 * 16;
 constexpr size_t kPackBias = 4 * 64 * 4;
 constexpr size_t kPackBytes = kPackWf + kPackWb + kPackBias;
+// E4M3 forward fragments and the four per-layer weight scales.
+constexpr size_t kPack8Wf = (size_t)FWD_FRAGS * 64 * 8;
+constexpr size_t kPack8Bytes = kPack8Wf + 256;
+
+// One wave per layer: the layer's weight scale max|W| / 448, then its forward fragments in
+// E4M3 (the bfloat16 fragments' order and operand layout).
+__global__ __launch_bounds__(64) void pack8_kernel(const float* __restrict__ P, long* __restrict__ wf8,
+                                                   float* __restrict__ wscale) {
+    const int layer = blockIdx.x, lane = threadIdx.x;
+    const int g = lane >> 4, c = lane & 15;
+    const int fan_in = layer == 0 ? MLP_IN : MLP_H;
+    float am = 0.0f;
+    for (int i = lane; i < fan_in * MLP_H; i += 64) am = fmaxf(am, fabsf(P[w_off(layer) + i]));
+    float sw, inv;
+    e4m3_scale(wave_absmax(am), sw, inv);
+    if (lane == 0) wscale[layer] = sw;
+    const int nkb = layer == 0 ? 1 : 2;
+    for (int mt = 0; mt < 4; ++mt)
+        for (int kb = 0; kb < nkb; ++kb) {
+            const int out = 16 * mt + c;
+            float v[8];
+            for (int j = 0; j < 8; ++j) {
+                const int in = 32 * kb + kperm(8 * g + j);
+                v[j] = clamp448(in < fan_in ? P[w_off(layer) + in * MLP_H + out] * inv : 0.0f);
+            }
+            wf8[fwd_frag(layer, mt, kb) * 64 + lane] = e4m3x8(v);
+        }
+}
+
+static hipError_t pack8(const float* params, void* buf, hipStream_t s) {
+    char* b = static_cast<char*>(buf);
+    hipLaunchKernelGGL(pack8_kernel, dim3(4), dim3(64), 0, s, params, reinterpret_cast<long*>(b),
+                       reinterpret_cast<float*>(b + kPack8Wf));
+    return hipGetLastError();
+}
+
+// pack: the bfloat16 pack (for the hidden biases); pack8: the E4M3 pack
+static MlpDev8 mlp_dev8(const float* params, const void* pack, const void* pack8buf) {
+    const char* b = static_cast<const char*>(pack);
+    const char* b8 = static_cast<const char*>(pack8buf);
+    MlpDev8 M;
+    M.wf = reinterpret_cast<const long*>(b8);
+    M.wscale = reinterpret_cast<const float*>(b8 + kPack8Wf);
+    M.bias = reinterpret_cast<const float*>(b + kPackWf + kPackWb);
+    M.w5 = params + OFF_W5;
+    M.b5 = params + OFF_B5;
+    return M;
+}
 
 static hipError_t pack(const float* params, void* ws, hipStream_t s) {
     char* b = static_cast<char*>(ws);
@@ -87,6 +136,17 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const MlpDev M, const 
     float xi[MLP_IN];
     for (int f = 0; f < MLP_IN; ++f) xi[f] = row < n ? x[row * MLP_IN + f] : 0.0f;
     const float o = mlp_forward_wave(M, xi, stage[wv], nullptr);
+    if (row < n) y[row] = o;
+}
+
+__global__ __launch_bounds__(256) void mlp_forward8_kernel(const MlpDev8 M, const float* __restrict__ x, int64_t n,
+                                                           float* __restrict__ y) {
+    __shared__ float stage[4][64 * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t row = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
+    float xi[MLP_IN];
+    for (int f = 0; f < MLP_IN; ++f) xi[f] = row < n ? x[row * MLP_IN + f] : 0.0f;
+    const float o = mlp_forward_wave_fp8(M, xi, stage[wv]);
     if (row < n) y[row] = o;
 }
 
@@ -327,8 +387,9 @@ __global__ __launch_bounds__(256) void samples_kernel(int64_t n, uint64_t seed, 
 // Surrogate p_w for a batch of queries (gr_bsdf_eval rows); out-of-domain rows use the closed
 // form.  One wave per 64 queries: every lane takes part in the matrix-core pass.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void sur_eval_kernel(const MlpDev M, SurDomain D, const float* __restrict__ q,
-                                                       int64_t n, float* __restrict__ out) {
+template <bool FP8>
+__global__ __launch_bounds__(256) void sur_eval_kernel(const MlpDev M, const MlpDev8 M8, SurDomain D,
+                                                       const float* __restrict__ q, int64_t n, float* __restrict__ out) {
     __shared__ float stage[4][64 * 16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t i = ((int64_t)blockIdx.x * 4 + wv) * 64 + lane;
@@ -338,7 +399,7 @@ __global__ __launch_bounds__(256) void sur_eval_kernel(const MlpDev M, SurDomain
     const float* r = q + (i < n ? i : 0) * 14;
     if (i < n && (int)r[0] == MAT_ROUGH)
         e = sur_encode(D, r[4], r[5], r[6], r[7], r[8], r[9], r[10], r[11], r[1], r[2], x, logpeak);
-    const float y = mlp_forward_wave(M, x, stage[wv], nullptr);
+    const float y = FP8 ? mlp_forward_wave_fp8(M8, x, stage[wv]) : mlp_forward_wave(M, x, stage[wv], nullptr);
     if (i >= n) return;
     float v;
     if (e == 1) v = r[3] * __expf(y + logpeak);
@@ -356,7 +417,8 @@ __device__ __forceinline__ void bf16_unpair(uint32_t u, float& a, float& b) {
     b = __uint_as_float(u & 0xFFFF0000u);
 }
 
-__global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const uint4* __restrict__ q,
+template <bool FP8>
+__global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const MlpDev8 M8, const uint4* __restrict__ q,
                                                         const unsigned long long* __restrict__ count,
                                                         float* __restrict__ dense, unsigned long long* stats) {
     __shared__ float stage[4][64 * 16];
@@ -378,7 +440,7 @@ __global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const ui
             logpeak = __uint_as_float(b.z);
             slot = b.w;
         }
-        const float y = mlp_forward_wave(M, x, stage[wv], nullptr);
+        const float y = FP8 ? mlp_forward_wave_fp8(M8, x, stage[wv]) : mlp_forward_wave(M, x, stage[wv], nullptr);
         if (i < n) {
             float v = scale * __expf(y + logpeak);
             if (!isfinite(v)) {
@@ -390,14 +452,19 @@ __global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const ui
     }
 }
 
-hipError_t launch_sur_batch(const SurrogateState& s, const uint4* queries, const unsigned long long* count,
+hipError_t launch_sur_batch(const SurrogateState& s, bool fp8, const uint4* queries, const unsigned long long* count,
                             float* dense, unsigned long long* stats, int grid, hipStream_t stream) {
     const MlpDev M = mlp_dev(s.d_params, s.d_pack);
-    hipLaunchKernelGGL(sur_batch_kernel, dim3(grid), dim3(256), 0, stream, M, queries, count, dense, stats);
+    const MlpDev8 M8 = mlp_dev8(s.d_params, s.d_pack, s.d_pack8);
+    if (fp8)
+        hipLaunchKernelGGL(sur_batch_kernel<true>, dim3(grid), dim3(256), 0, stream, M, M8, queries, count, dense, stats);
+    else
+        hipLaunchKernelGGL(sur_batch_kernel<false>, dim3(grid), dim3(256), 0, stream, M, M8, queries, count, dense, stats);
     return hipGetLastError();
 }
 
 void surrogate_free(SurrogateState& s) {
+    if (s.d_pack8) (void)hipFree(s.d_pack8);
     if (s.d_pack) (void)hipFree(s.d_pack);
     if (s.d_params) (void)hipFree(s.d_params);
     s = SurrogateState();
@@ -411,27 +478,36 @@ void surrogate_fill(const SurrogateState& s, SurrogateDev& d) {
     d.enabled = s.ready ? 1 : 0;
 }
 
-hipError_t launch_bsdf_eval_surrogate(const SurrogateState& s, const float* q, int64_t n, float* out,
+hipError_t launch_bsdf_eval_surrogate(const SurrogateState& s, bool fp8, const float* q, int64_t n, float* out,
                                       hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const MlpDev M = mlp_dev(s.d_params, s.d_pack);
+    const MlpDev8 M8 = mlp_dev8(s.d_params, s.d_pack, s.d_pack8);
     const SurDomain D{s.domain[0], s.domain[1], s.domain[2], s.domain[3]};
     const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(sur_eval_kernel, dim3(blocks), dim3(256), 0, stream, M, D, q, n, out);
+    if (fp8) hipLaunchKernelGGL(sur_eval_kernel<true>, dim3(blocks), dim3(256), 0, stream, M, M8, D, q, n, out);
+    else hipLaunchKernelGGL(sur_eval_kernel<false>, dim3(blocks), dim3(256), 0, stream, M, M8, D, q, n, out);
     return hipGetLastError();
 }
 
 // Host entry points used by the C ABI (api.cpp).
 size_t mlp_workspace_bytes(int64_t n) {
     const int64_t waves = (n + 63) / 64;
-    return kPackBytes + (size_t)waves * (16384 + MLP_NPARAM + 1) * sizeof(float) + 256;
+    return kPackBytes + std::max(kPack8Bytes, (size_t)waves * (16384 + MLP_NPARAM + 1) * sizeof(float)) + 256;
 }
 
-hipError_t mlp_forward(const float* params, const float* x, int64_t n, void* ws, float* y, hipStream_t s) {
+hipError_t mlp_forward(const float* params, const float* x, int64_t n, bool fp8, void* ws, float* y, hipStream_t s) {
     hipError_t e = pack(params, ws, s);
     if (e != hipSuccess || n <= 0) return e;
-    const MlpDev M = mlp_dev(params, ws);
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, x, n, y);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (fp8) {
+        void* p8 = static_cast<char*>(ws) + kPackBytes;
+        e = pack8(params, p8, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(mlp_forward8_kernel, dim3(blocks), dim3(256), 0, s, mlp_dev8(params, ws, p8), x, n, y);
+    } else {
+        hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks), dim3(256), 0, s, mlp_dev(params, ws), x, n, y);
+    }
     return hipGetLastError();
 }
 
@@ -479,11 +555,14 @@ hipError_t surrogate_samples(int64_t n, uint64_t seed, const float* domain, floa
 hipError_t surrogate_set(SurrogateState& st, const float* params, const float* domain, hipStream_t s) {
     if (!st.d_pack) {
         if (hipMalloc(&st.d_pack, kPackBytes) != hipSuccess) return hipErrorOutOfMemory;
+        if (hipMalloc(&st.d_pack8, kPack8Bytes) != hipSuccess) return hipErrorOutOfMemory;
         if (hipMalloc(&st.d_params, MLP_NPARAM * sizeof(float)) != hipSuccess) return hipErrorOutOfMemory;
     }
     hipError_t e = hipMemcpyAsync(st.d_params, params, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
     e = pack(st.d_params, st.d_pack, s);
+    if (e != hipSuccess) return e;
+    e = pack8(st.d_params, st.d_pack8, s);
     if (e != hipSuccess) return e;
     for (int i = 0; i < 4; ++i) st.domain[i] = domain[i];
     st.ready = true;

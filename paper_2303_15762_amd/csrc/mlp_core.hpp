@@ -182,6 +182,159 @@ __device__ inline float mlp_forward_wave(const MlpDev& M, const float* x, float*
 }
 
 // ------------------------------------------------------------------------------------------
+// FP8 (OCP E4M3) forward pass.  Weights are quantized per layer with scale max|W| / 448;
+// activations are quantized per wave and layer with scale max|a| / 448 over the wave's 64
+// queries.  The E4M3 16x16x32 matrix-core product has the bfloat16 one's operand layout (8
+// values per lane, value j in byte j); its FP32 result is multiplied by the two scales.
+// ------------------------------------------------------------------------------------------
+struct MlpDev8 {
+    const long* wf;        // [FWD_FRAGS][64] forward A fragments, E4M3
+    const float* wscale;   // [4] per-layer weight scales
+    const float* bias;     // [4][64]
+    const float* w5;       // [64]
+    const float* b5;       // [1]
+};
+
+constexpr float kE4M3Max = 448.0f;
+
+// Four floats (already scaled into [-448, 448]) to E4M3, round to nearest even.
+__device__ __forceinline__ uint32_t e4m3x4(float a, float b, float c, float d) {
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (uint32_t)w;
+}
+
+__device__ __forceinline__ long e4m3x8(const float (&v)[8]) {
+    const uint32_t lo = e4m3x4(v[0], v[1], v[2], v[3]), hi = e4m3x4(v[4], v[5], v[6], v[7]);
+    return (long)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float wave_absmax(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+
+// scale (amax / 448) and its reciprocal; an all-zero tile quantizes to zeros
+__device__ __forceinline__ void e4m3_scale(float amax, float& s, float& inv) {
+    if (amax > 1e-30f) {
+        s = amax * (1.0f / kE4M3Max);
+        inv = kE4M3Max / amax;
+    } else {
+        s = 0.0f;
+        inv = 0.0f;
+    }
+}
+
+__device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -kE4M3Max), kE4M3Max); }
+
+__device__ __forceinline__ long input_frag8(const float* stage, int nb, int lane, float inv) {
+    const int g = lane >> 4, c = lane & 15;
+    const float* row = stage + (16 * nb + c) * 16;
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int f = kperm(8 * g + j);
+        v[j] = clamp448((f < MLP_IN ? row[f] : 0.0f) * inv);
+    }
+    return e4m3x8(v);
+}
+
+__device__ __forceinline__ long act_frag8(const f32x4 (&h)[4][4], int kb, int nb, float inv) {
+    float v[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        v[j] = clamp448(h[2 * kb][nb][j] * inv);
+        v[4 + j] = clamp448(h[2 * kb + 1][nb][j] * inv);
+    }
+    return e4m3x8(v);
+}
+
+__device__ inline float mlp_forward_wave_fp8(const MlpDev8& M, const float* x, float* stage) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    float am = 0.0f;
+#pragma unroll
+    for (int f = 0; f < MLP_IN; ++f) am = fmaxf(am, fabsf(x[f]));
+    float s_act, inv_act;
+    e4m3_scale(wave_absmax(am), s_act, inv_act);
+#pragma unroll
+    for (int f = 0; f < 16; ++f) stage[lane * 16 + f] = f < MLP_IN ? x[f] : 0.0f;
+    wave_sync_lds();
+    f32x4 h[4][4];
+    {
+        long bin[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) bin[nb] = input_frag8(stage, nb, lane, inv_act);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const long a = M.wf[fwd_frag(0, mt, 0) * 64 + lane];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) {
+                const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+                h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bin[nb], zero, 0, 0, 0);
+            }
+        }
+    }
+    wave_sync_lds();   // stage is free again for the caller
+#pragma unroll
+    for (int layer = 0; layer < 4; ++layer) {
+        if (layer > 0) {
+            am = 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) am = fmaxf(am, fabsf(h[mt][nb][i]));
+            e4m3_scale(wave_absmax(am), s_act, inv_act);
+            long b[2][4];
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) b[kb][nb] = act_frag8(h, kb, nb, inv_act);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const long a0 = M.wf[fwd_frag(layer, mt, 0) * 64 + lane];
+                const long a1 = M.wf[fwd_frag(layer, mt, 1) * 64 + lane];
+#pragma unroll
+                for (int nb = 0; nb < 4; ++nb) {
+                    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+                    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b[0][nb], zero, 0, 0, 0);
+                    h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b[1][nb], acc, 0, 0, 0);
+                }
+            }
+        }
+        // dequantize, bias, activation; the layer's output features of this lane are 16 mt + 4 g + i
+        const float deq = M.wscale[layer] * s_act;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            float bb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bb[i] = M.bias[layer * 64 + 16 * mt + 4 * g + i];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) h[mt][nb][i] = gelu_f(h[mt][nb][i] * deq + bb[i]);
+        }
+    }
+    float part[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        float s = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s += M.w5[16 * mt + 4 * g + i] * h[mt][nb][i];
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        part[nb] = s;
+    }
+    const float o = g == 0 ? part[0] : (g == 1 ? part[1] : (g == 2 ? part[2] : part[3]));
+    return o + M.b5[0];
+}
+
+// ------------------------------------------------------------------------------------------
 // Input encoding of a rough-surface query for the learned model.
 //
 // The network sees the outgoing tangential wavevector relative to the incident one in units of

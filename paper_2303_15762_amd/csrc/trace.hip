@@ -601,7 +601,7 @@ static int grid_for(int device) {
 int trace_grid_size(int device, bool sur) { return sur ? grid_for<true>(device) : grid_for<false>(device); }
 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.bsdf_mode == 1) hipLaunchKernelGGL((trace_kernel<kLdsStack, true>), dim3(grid), dim3(256), 0, s, a);
+    if (a.bsdf_mode != 0) hipLaunchKernelGGL((trace_kernel<kLdsStack, true>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((trace_kernel<kLdsStack, false>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }

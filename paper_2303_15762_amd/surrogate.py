@@ -78,11 +78,12 @@ class Surrogate:
                     "gr_surrogate_samples")
         return x, y, q
 
-    def forward(self, params, x):
+    def forward(self, params, x, dtype=L.GR_BSDF_SURROGATE_BF16):
+        """dtype: GR_BSDF_SURROGATE_BF16 or GR_BSDF_SURROGATE_FP8 (E4M3) matrix-core operands."""
         n = x.shape[0]
         y = self.torch.empty(n, dtype=self.torch.float32, device=self.R.dev)
         ws = self.workspace(n)
-        self._check(self.lib.gr_mlp_forward(self.R.h, _fp(params), _fp(x), int(n), L.GR_BSDF_SURROGATE_BF16,
+        self._check(self.lib.gr_mlp_forward(self.R.h, _fp(params), _fp(x), int(n), int(dtype),
                                             C.c_void_p(ws.data_ptr()), _fp(y)), "gr_mlp_forward")
         return y
 

@@ -67,6 +67,29 @@ def test_forward_matches_oracle(env):
         assert np.corrcoef(y, ref[:, 0])[0, 1] > 0.9999
 
 
+def test_forward_fp8_matches_e4m3_oracle(env):
+    """FP8 mode: weights per layer and activations per 64 rows quantized to E4M3 (scale max / 448),
+    FP32 accumulation.  The oracle's quantized forward pass in FP64 is the reference; a value
+    that sits on an E4M3 rounding boundary can round the other way from FP32 inputs, so the
+    bound is that of the BF16 path."""
+    R, S, torch = env
+    from paper_2303_15762_amd import GR_BSDF_SURROGATE_FP8
+    from paper_2303_15762_amd.surrogate import unflatten
+    p = _params(11)
+    rng = np.random.default_rng(12)
+    for n in (64, 1000, 4099):
+        x = rng.uniform(-1, 1, (n, 10)).astype(np.float32)
+        y = S.forward(torch.tensor(p, device=R.dev), torch.tensor(x, device=R.dev),
+                      dtype=GR_BSDF_SURROGATE_FP8).cpu().numpy()
+        Ws, bs = unflatten(p)
+        ref8 = omlp.forward_e4m3(Ws, bs, x.astype(np.float64))
+        ref, _, _ = omlp.forward(Ws, bs, x.astype(np.float64))
+        e8, e = rel_l2(y, ref8), rel_l2(y, ref[:, 0])
+        print("fp8 forward n", n, "rel L2 vs E4M3 oracle", e8, "vs unquantized FP64", e)
+        assert e8 <= 2e-2
+        assert np.corrcoef(y, ref8)[0, 1] > 0.9999
+
+
 def test_backward_matches_oracle(env):
     R, S, torch = env
     from paper_2303_15762_amd.surrogate import unflatten

@@ -100,3 +100,36 @@ def test_surrogate_trace_deterministic(trained):
     b, sb = R.render_workload(wl, bsdf_mode=1)
     assert sa["surrogate_evals"] > 0 and sa["surrogate_evals"] == sb["surrogate_evals"]
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_fp8_surrogate_against_bf16_and_oracle(trained):
+    """The same trained network with E4M3 operands: held-out p_w and the terrain image, both
+    against the FP64 closed form / oracle, next to the BF16 operands (the precision comparison
+    of the learned path)."""
+    R, S, p, hist, torch = trained
+    _, _, q = S.samples(200000, seed=79, with_queries=True)
+    qn = q.cpu().numpy().astype(np.float64)
+    ref = oracle.pw_batch(qn)
+    k = qn[:, 4]
+    ci = np.sqrt(1 - (qn[:, 5] ** 2 + qn[:, 6] ** 2) / k ** 2)
+    co = np.sqrt(1 - (qn[:, 7] ** 2 + qn[:, 8] ** 2) / k ** 2)
+    g = (k * (ci + co) * qn[:, 1]) ** 2
+    peak = qn[:, 2] ** 2 / (4 * np.pi * g)
+    big = ref > 1e-2 * peak
+    stats = {}
+    for mode in (1, 2):
+        got = R.bsdf_eval(q, mode=mode).cpu().numpy().astype(np.float64)
+        rel = np.abs(got[big] - ref[big]) / ref[big]
+        stats[mode] = (np.median(rel), np.quantile(rel, 0.9), (np.abs(got - ref) / peak).max())
+        print("p_w mode", mode, "median rel", stats[mode][0], "p90", stats[mode][1], "abs/peak max", stats[mode][2])
+    assert stats[2][0] < 5e-2 and stats[2][2] < 0.2
+    wl = W.mid_terrain(width=41, height=29, spp=16, n_lambda=8)
+    R.load_workload(wl)
+    o, _ = oracle.render(wl)
+    errs = {}
+    for mode in (1, 2):
+        img, st = R.render_workload(wl, bsdf_mode=mode)
+        errs[mode] = rel_l2(img.cpu().numpy(), o)
+        print("image mode", mode, "rel L2", errs[mode], "surrogate evals", st["surrogate_evals"])
+        assert st["surrogate_evals"] > 0
+    assert errs[2] <= 1e-2

@@ -636,3 +636,57 @@ def test_rough_continuation_sampling_moments():
         ms.append(int(round((d * ell / rr) ** 2 / 2)))
     hist = np.bincount(ms, minlength=30)[:30] / len(us)
     np.testing.assert_allclose(hist, poisson.pmf(np.arange(30), g), atol=1.0 / len(us) + 1e-12)
+
+
+def test_e4m3_rounding_against_format_definition():
+    """OCP FP8 E4M3: 1 sign, 4 exponent bits (bias 7), 3 mantissa bits, code 0x7F / 0xFF NaN.
+    Every finite code (decoded from that definition) rounds to itself; every midpoint of two
+    neighbours rounds to the one with an even mantissa; values beyond 448 clamp."""
+    from oracle import mlp as omlp
+    vals = []
+    for c in range(256):
+        if c & 0x7F == 0x7F:
+            continue
+        s = -1.0 if c & 0x80 else 1.0
+        e, m = (c >> 3) & 15, c & 7
+        v = s * (2.0 ** -6 * m / 8.0 if e == 0 else 2.0 ** (e - 7) * (1.0 + m / 8.0))
+        vals.append((v, m))
+    pos = sorted({(v, m) for v, m in vals if v >= 0})
+    v = np.array([p[0] for p in pos])
+    assert len(pos) == 127 and v[-1] == 448.0 and v[1] == 2.0 ** -9
+    np.testing.assert_array_equal(omlp.e4m3_round(v), v)
+    np.testing.assert_array_equal(omlp.e4m3_round(-v), -v)
+    mids = 0.5 * (v[1:] + v[:-1])
+    even = np.array([pos[i][0] if pos[i][1] % 2 == 0 else pos[i + 1][0] for i in range(len(pos) - 1)])
+    np.testing.assert_array_equal(omlp.e4m3_round(mids), even)
+    # just off the midpoints: the nearer neighbour
+    np.testing.assert_array_equal(omlp.e4m3_round(mids * (1 - 1e-9)), v[:-1])
+    np.testing.assert_array_equal(omlp.e4m3_round(mids * (1 + 1e-9)), v[1:])
+    assert omlp.e4m3_round(1e6) == 448.0 and omlp.e4m3_round(-500.0) == -448.0
+
+
+def test_e4m3_forward_reduces_to_exact_network():
+    """The quantized forward pass is the FP64 network when quantization is exact: every
+    weight and input an E4M3 value and each tensor's (and each 64-row block's) max 448, so
+    both scales are 1.  A one-hidden-layer network makes the hidden layer's input the raw
+    input; a second, deeper case checks that quantization changes outputs by no more than
+    E4M3's relative spacing allows."""
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(3)
+    grid = np.array([0.25, 0.5, 1.0, 2.0, -0.5, -1.0, 0.0, 0.75])
+    W1 = rng.choice(grid, size=(10, 64))
+    W1[0, 0] = 448.0
+    W2 = rng.normal(size=(64, 1))
+    X = rng.choice(grid, size=(256, 10))
+    X[::64, 0] = 448.0
+    bs = [rng.normal(size=64), np.zeros(1)]
+    ref, _, _ = omlp.forward([W1, W2], bs, X)
+    np.testing.assert_allclose(omlp.forward_e4m3([W1, W2], bs, X), ref[:, 0], rtol=1e-12, atol=1e-12)
+    # full network, random weights: bounded quantization error, and not zero
+    Ws = [rng.normal(0, np.sqrt(2.0 / a), size=(a, b)) for a, b in zip(omlp.SIZES[:-1], omlp.SIZES[1:])]
+    bz = [rng.normal(0, 0.05, size=b) for b in omlp.SIZES[1:]]
+    X = rng.uniform(-1, 1, size=(512, 10))
+    ref, _, _ = omlp.forward(Ws, bz, X)
+    got = omlp.forward_e4m3(Ws, bz, X)
+    err = np.linalg.norm(got - ref[:, 0]) / np.linalg.norm(ref[:, 0])
+    assert 1e-4 < err < 0.1
