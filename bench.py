@@ -19,6 +19,10 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+# Dense matrix-core peaks of the MI355X and the network's multiply-add work per query:
+# 2 x (10 x 64 + 3 x 64 x 64 + 64) flops.
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0}
+MLP_FLOPS = 2 * (10 * 64 + 3 * 64 * 64 + 64)
 # Vector ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one wave64
 # instruction occupies a 16-lane SIMD for 4 cycles; FMA counted as one op, no packed math).
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
@@ -96,7 +100,8 @@ def cpu_baseline(wl, target_s=15.0):
 
 def surrogate_leg(R, wl, o_plain, img, st_plain, args):
     """Train the learned p_w (outside the timed region), then time the same workload with the
-    surrogate path.  Its image is compared with the plain-path image of this GPU."""
+    surrogate path, with bfloat16 and with E4M3 matrix-core operands.  Each image is compared
+    with the plain-path image of this GPU."""
     import torch
     from paper_2303_15762_amd.surrogate import Surrogate
     S = Surrogate(R)
@@ -105,26 +110,48 @@ def surrogate_leg(R, wl, o_plain, img, st_plain, args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     S.install(p)
-    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
-               rr_enable=wl.rr_enable, rr_p=wl.rr_p, bsdf_mode=1)
     plain = img.clone()
-    img_s = torch.zeros_like(img)
-    _, st = R.trace(wl.lambdas_um, o, image=img_s, stats=True)
-    err = float((img_s - plain).norm() / plain.norm())
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(R.stream)
-    for _ in range(args.steps):
-        R.trace(wl.lambdas_um, o, image=img_s, stats=False)
-    e1.record(R.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    return {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
-            "ms_per_step": round(ms, 3), "rel_l2_vs_plain_gpu_image": err,
-            "surrogate_evals_per_step": st["surrogate_evals"], "fallbacks_per_step": st["fallbacks"],
-            "train_s": round(t_train, 2), "train_steps": hist["step"][-1],
-            "val_mse_log_pw": hist["val_loss"][-1]}
+    legs = {}
+    for name, mode in (("bf16", 1), ("fp8", 2)):
+        o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+                   rr_enable=wl.rr_enable, rr_p=wl.rr_p, bsdf_mode=mode)
+        img_s = torch.zeros_like(img)
+        _, st = R.trace(wl.lambdas_um, o, image=img_s, stats=True)
+        err = float((img_s - plain).norm() / plain.norm())
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(R.stream)
+        for _ in range(args.steps):
+            R.trace(wl.lambdas_um, o, image=img_s, stats=False)
+        e1.record(R.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        legs[name] = {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 3),
+                      "rel_l2_vs_plain_gpu_image": err, "surrogate_evals_per_step": st["surrogate_evals"]}
+    # the network alone on the matrix cores: 4M encoded queries, both operand types
+    x, _, _ = S.samples(1 << 22, seed=77)
+    mfma = {}
+    for name, dtype, peak in (("bf16", 1, MFMA_PEAK_TFLOPS["bf16"]), ("fp8", 2, MFMA_PEAK_TFLOPS["fp8"])):
+        S.forward(p, x, dtype=dtype)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(R.stream)
+        for _ in range(5):
+            S.forward(p, x, dtype=dtype)
+        e1.record(R.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        tf = x.shape[0] * MLP_FLOPS / (ms * 1e-3) / 1e12
+        mfma[name] = {"bound": "mfma", "achieved": round(tf, 1), "peak": peak, "unit": "TFLOP/s",
+                      "frac": round(tf / peak, 4), "rows": int(x.shape[0]), "ms": round(ms, 4)}
+    legs["bf16"]["roofline"] = mfma["bf16"]
+    legs["fp8"]["roofline"] = mfma["fp8"]
+    out = dict(legs["bf16"])
+    out.update({"unit": "Mpath-segments/s", "fallbacks_per_step": st["fallbacks"], "train_s": round(t_train, 2),
+                "train_steps": hist["step"][-1], "val_mse_log_pw": hist["val_loss"][-1], "fp8": legs["fp8"]})
+    return out
 
 
 def main():

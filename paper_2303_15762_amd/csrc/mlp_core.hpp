@@ -44,24 +44,22 @@ __host__ __device__ inline int bwd_frag(int layer, int mt, int kb) {   // layer 
 }
 
 // GELU, tanh form: 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))), and its derivative.
+// tanh(y) = 1 - 2 / (exp(2y) + 1), with the hardware exponential and reciprocal (1 ulp each).
+__device__ __forceinline__ float tanh_fast(float y) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * y) + 1.0f);
+}
 __device__ __forceinline__ float gelu_f(float x) {
     const float y = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * y) + 1.0f);
-    return 0.5f * x * (1.0f + t);
+    return 0.5f * x * (1.0f + tanh_fast(y));
 }
 __device__ __forceinline__ float gelu_grad_f(float x) {
     const float y = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * y) + 1.0f);
+    const float t = tanh_fast(y);
     return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * x * x);
 }
 
-// Round-to-nearest-even float -> bfloat16.
-__device__ __forceinline__ __bf16 to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    const uint16_t h = (uint16_t)(u >> 16);
-    return __builtin_bit_cast(__bf16, h);
-}
+// Round-to-nearest-even float -> bfloat16 (v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ __bf16 to_bf16(float f) { return (__bf16)f; }
 
 struct MlpDev {
     const bf16x8* wf;    // [FWD_FRAGS][64] forward A fragments

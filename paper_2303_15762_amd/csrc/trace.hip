@@ -157,21 +157,33 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // ovf[i * ostride + lane], ovf being the wave's slice of the overflow region, which the caller
 // sizes for the tree: at most 3 entries per inner node on the current root path.
 // Returns the triangle (leaf order) or -1.
+// Traversal loop structure (Aila and Laine, "Understanding the efficiency of ray traversal on
+// GPUs", HPG 2009: while-while with postponed leaves): each lane descends inner nodes until it
+// has found a leaf, which it parks while it keeps descending; the wave leaves the node loop once
+// every lane still in it holds a leaf, and then the lanes test their leaves together.  Node
+// and triangle code thus run on fuller waves than when every iteration does either one.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
                                         bool any, int skip, int* stk, int cap, int* ovf, size_t ostride,
                                         uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv) {
+    constexpr int kDone = 0x7FFFFFFF;   // nothing left to visit (never a node index)
     int best = -1;
     int best_orig = 0x7FFFFFFF;
     float best_t = tmax;
     int sp = 0;
-    int cur = 0;
+    int cur = 0;    // next inner node (>= 0) or leaf (< 0) to visit, or kDone
+    int leaf = 0;   // a parked leaf (< 0), or 0
+    auto pop = [&]() -> int {
+        if (sp == 0) return kDone;
+        --sp;
+        return sp < cap ? stk[sp * 64] : ovf[(size_t)(sp - cap) * ostride + __lane_id()];
+    };
     // slab distances as (lo - o) / d = lo * inv - o * inv: one FMA per plane (the node boxes
     // are widened by more than the extra rounding of o * inv)
     const float ix = r.inv.x, iy = r.inv.y, iz = r.inv.z;
     const float oix = r.o.x * ix, oiy = r.o.y * iy, oiz = r.o.z * iz;
-    while (true) {
-        if (cur >= 0) {
+    while (cur != kDone) {
+        while (cur >= 0 && cur != kDone) {
             ++n_nodes;
             const float4* N = S.nodes + (size_t)cur * 8;
             const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
@@ -215,13 +227,16 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                     ++sp;
                 }
             }
-            if (key[0] != 0xFFFFFFFFu) {
-                cur = child_of(ch, key[0]);
-                continue;
+            cur = key[0] != 0xFFFFFFFFu ? child_of(ch, key[0]) : pop();
+            if (cur < 0 && leaf == 0) {   // park the leaf and keep descending
+                leaf = cur;
+                cur = pop();
             }
-        } else {
-            const int first = cur & 0x0FFFFFFF;
-            const int cnt = ((cur >> 28) & 7) + 1;
+            if (!__any(leaf == 0)) break;
+        }
+        while (leaf < 0) {
+            const int first = leaf & 0x0FFFFFFF;
+            const int cnt = ((leaf >> 28) & 7) + 1;
             for (int i = 0; i < cnt; ++i) {
                 const float4* T = S.tris + (size_t)(first + i) * 3;
                 const float4 a = T[0], b = T[1], cc = T[2];
@@ -242,10 +257,12 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                     }
                 }
             }
+            leaf = 0;
+            if (cur < 0) {   // the next node is a leaf too: test it in this loop
+                leaf = cur;
+                cur = pop();
+            }
         }
-        if (sp == 0) break;
-        --sp;
-        cur = sp < cap ? stk[sp * 64] : ovf[(size_t)(sp - cap) * ostride + __lane_id()];
     }
     tmax = best_t;
     return best;
