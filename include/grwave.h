@@ -92,7 +92,7 @@ typedef struct {
     float power;
 } gr_source;
 
-enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2 };
+enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2, GR_TRACE_WAVEFRONT = 4 };
 
 /* Trace options.
  *   spp_begin, spp_count : sample indices [spp_begin, spp_begin + spp_count) of every pixel and
@@ -110,7 +110,10 @@ enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2 };
  *                          only 4 BVH traversal-stack entries per lane in LDS and the rest in
  *                          the workspace (normally 32 stay in LDS and only BVHs deeper than 9
  *                          levels overflow); the image is identical, the render slower.  It
- *                          exists to exercise the overflow path.  Other bits are invalid. */
+ *                          exists to exercise the overflow path.  GR_TRACE_WAVEFRONT renders
+ *                          with the wavefront kernels (per-bounce queues in the workspace)
+ *                          instead of the persistent path kernel; the image is the same up to
+ *                          the rounding of a few shortened paths.  Other bits are invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;

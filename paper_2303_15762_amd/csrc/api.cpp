@@ -42,6 +42,8 @@ struct gr_ctx {
     int grid_plain = 0;              // persistent grids (blocks), set at scene upload
     int grid_sur = 0;
     int grid_batch = 0;              // blocks of the batched network pass
+    int grid_wf = 0;                 // blocks of the wavefront traversal kernels
+    int grid_work = 0;               // blocks of the grid-stride wavefront kernels
     grw::SurrogateState sur;
 };
 
@@ -95,11 +97,76 @@ int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_
 // The learned-p_w path renders in launches of at most this many paths: each launch queues at
 // most one query per path and interaction (32 B) and owns one result float per slot.
 constexpr uint64_t kSurChunk = 1ull << 24;
+// The wavefront kernels keep per-path state of a launch of at most this many paths.
+constexpr uint64_t kWfChunk = 1ull << 23;
 
 struct WsLayout {
-    size_t records = 0, ovf = 0, queue = 0, dense = 0, total = 0;
+    size_t records = 0, ovf = 0, wf = 0, queue = 0, dense = 0, total = 0;
     uint64_t chunk = 0;
+    size_t wf_bytes = 0;
 };
+
+bool wavefront_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_WAVEFRONT) != 0; }
+
+// Per-path wavefront arrays in this order, each padded to 256 B (element sizes in bytes).
+constexpr int kWfArrays = 27;
+constexpr int kWfElem[kWfArrays] = {8, 8, 8,                       // ox oy oz
+                                    4, 4, 4, 4, 4, 4, 4,           // dx dy dz beta2 rho alpha contrib
+                                    4, 4, 4, 4, 4,                 // prev hit ht hu hv
+                                    4, 4,                          // list0 list1
+                                    4, 8, 8, 8, 4, 4, 4, 4,        // s_path s_px s_py s_pz s_dx s_dy s_dz s_tmax
+                                    4, 4};                         // s_skip s_mat
+// plus s_q ([kShadowQ][n] floats) and s_vis (bytes)
+
+size_t wf_bytes(uint64_t n) {
+    size_t b = 0;
+    for (int i = 0; i < kWfArrays; ++i) b += align256((size_t)n * kWfElem[i]);
+    b += align256((size_t)n * grw::kShadowQ * sizeof(float));
+    b += align256((size_t)n);
+    return b;
+}
+
+grw::WfArgs wf_args(char* base, uint64_t n) {
+    grw::WfArgs w{};
+    w.n = n;
+    char* p = base;
+    void* arr[kWfArrays];
+    for (int i = 0; i < kWfArrays; ++i) {
+        arr[i] = p;
+        p += align256((size_t)n * kWfElem[i]);
+    }
+    w.ox = (double*)arr[0];
+    w.oy = (double*)arr[1];
+    w.oz = (double*)arr[2];
+    w.dx = (float*)arr[3];
+    w.dy = (float*)arr[4];
+    w.dz = (float*)arr[5];
+    w.beta2 = (float*)arr[6];
+    w.rho = (float*)arr[7];
+    w.alpha = (float*)arr[8];
+    w.contrib = (float*)arr[9];
+    w.prev = (int*)arr[10];
+    w.hit = (int*)arr[11];
+    w.ht = (float*)arr[12];
+    w.hu = (float*)arr[13];
+    w.hv = (float*)arr[14];
+    w.list[0] = (uint32_t*)arr[15];
+    w.list[1] = (uint32_t*)arr[16];
+    w.s_path = (uint32_t*)arr[17];
+    w.s_px = (double*)arr[18];
+    w.s_py = (double*)arr[19];
+    w.s_pz = (double*)arr[20];
+    w.s_dx = (float*)arr[21];
+    w.s_dy = (float*)arr[22];
+    w.s_dz = (float*)arr[23];
+    w.s_tmax = (float*)arr[24];
+    w.s_skip = (int*)arr[25];
+    w.s_mat = (int*)arr[26];
+    w.s_q = (float*)p;
+    p += align256((size_t)n * grw::kShadowQ * sizeof(float));
+    w.s_vis = (uint8_t*)p;
+    return w;
+}
 
 // Traversal-stack entries per lane that do not fit the LDS part.
 uint32_t overflow_entries(const gr_ctx* c, const gr_trace_opts* o) {
@@ -235,6 +302,12 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
         c->grid_batch = 4 * std::max(ncu, 1);
+        c->grid_work = 8 * std::max(ncu, 1);
+    }
+    c->grid_wf = grw::wavefront_trav_grid(c->device);
+    if (c->grid_wf <= 0) {
+        free_scene(c);
+        return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
     if (c->grid_plain <= 0 || c->grid_sur <= 0) {
         free_scene(c);
@@ -304,14 +377,16 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     WsLayout L;
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
     const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
-    const size_t lanes = (size_t)std::max(c->grid_plain, c->grid_sur) * 256;
+    const size_t lanes = (size_t)std::max(std::max(c->grid_plain, c->grid_sur), c->grid_wf) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
-    L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
+    L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
+    L.chunk = std::min<uint64_t>(n, wavefront_of(o) ? kWfChunk : kSurChunk);
+    L.wf_bytes = wavefront_of(o) ? wf_bytes(L.chunk) : 0;
+    L.queue = L.wf + L.wf_bytes;
     L.dense = L.queue;
     L.total = L.queue;
     if (o->bsdf_mode != GR_BSDF_PLAIN) {
-        L.chunk = std::min<uint64_t>(n, kSurChunk);
         const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
         L.dense = L.queue + align256((size_t)slots * grw::kSurQueryBytes);
         L.total = L.dense + align256((size_t)slots * sizeof(float));
@@ -345,7 +420,8 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (o->max_depth < 1 || o->max_depth > 64) return fail(c, GR_E_INVALID, "trace: max_depth %d", o->max_depth);
     if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
     if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
-    if (o->flags & ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK)) return fail(c, GR_E_INVALID, "trace: flags");
+    if (o->flags & ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_WAVEFRONT))
+        return fail(c, GR_E_INVALID, "trace: flags");
     if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
         return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
@@ -436,7 +512,28 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));
     GR_HIP(c, hipMemsetAsync(ws, 0, kWsHeader, c->stream));
     if (st) GR_HIP(c, hipEventRecord(ev[0], c->stream));
-    if (!defer) {
+    if (wavefront_of(o)) {
+        // launches of at most WL.chunk paths through the wavefront kernels (state, queues and
+        // shadow records in the workspace); with the learned p_w each launch's queued queries
+        // are evaluated and merged before the next launch reuses the queue
+        const int D = o->max_depth;
+        const grw::WfArgs w0 = wf_args(base + WL.wf, WL.chunk);
+        for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
+            const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
+            grw::WfArgs w = w0;
+            w.n = pn;
+            w.cnt = reinterpret_cast<unsigned int*>(base + 192);
+            a.path_begin = p0;
+            a.n_paths = pn;
+            if (defer) GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, pn * (uint64_t)D, c->stream));
+            GR_HIP(c, grw::launch_wavefront(a, w, c->grid_wf, c->grid_work, c->stream));
+            if (defer) {
+                GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
+                GR_HIP(c, grw::launch_sur_merge(dense, D, a.records, p0, pn, c->stream));
+            }
+        }
+        a.n_paths = total;
+    } else if (!defer) {
         a.path_begin = 0;
         if (total > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
     } else {
