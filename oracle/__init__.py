@@ -56,7 +56,7 @@ class OrOpts(C.Structure):
     _fields_ = [("spp_begin", C.c_int64), ("spp_count", C.c_int64), ("spp_norm", C.c_double),
                 ("max_depth", C.c_int32), ("rr_enable", C.c_int32),
                 ("rr_threshold24", C.c_uint32), ("rr_p", C.c_double), ("seed", C.c_uint64),
-                ("use_bvh", C.c_int32), ("n_threads", C.c_int32)]
+                ("use_bvh", C.c_int32), ("n_threads", C.c_int32), ("hero", C.c_int32)]
 
 
 class OrCoherent(C.Structure):
@@ -87,6 +87,7 @@ def lib():
             L.or_pw_batch.argtypes = [dp, C.c_int64, dp]
             L.or_sample.argtypes = [C.c_int] + [C.c_double] * 12 + [dp]
             L.or_sample.restype = C.c_int
+            L.or_hero_step_batch.argtypes = [C.c_int] + [C.c_double] * 10 + [dp, C.c_int64, dp]
             L.or_scene_create.argtypes = [dp, C.c_int64, dp, C.POINTER(C.c_int32), C.c_int64,
                                           C.POINTER(C.c_int32), C.POINTER(OrMaterial), C.c_int32]
             L.or_scene_create.restype = C.c_void_p
@@ -172,6 +173,18 @@ def sample_continuation(kind, h, L, k, kit, ci, u, g=(1.0, 0.0), refl=1.0):
     return (out[0], out[1], out[2]) if ok else None
 
 
+def hero_step(kind, h, L, kh, kc, ui, ci, U, g=(1.0, 0.0), refl=1.0):
+    """Hero-wavelength continuation step for uniforms U [n, 3]: the hero's sample at
+    wavenumber kh from incident tangential direction ui, and a companion's ratios at kc.
+    Returns [n, 5]: (kox, koy, hero weight, f_c / p_h, p_c / p_h); NaN rows end the path."""
+    U = np.ascontiguousarray(U, np.float64).reshape(-1, 3)
+    out = np.empty((U.shape[0], 5))
+    lib().or_hero_step_batch(int(kind), float(h), float(L), float(refl), float(kh), float(kc),
+                             float(ui[0]), float(ui[1]), float(ci), float(g[0]), float(g[1]),
+                             _dp(U), U.shape[0], _dp(out))
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 # Scenes and rendering
 # ------------------------------------------------------------------------------------------
@@ -244,10 +257,12 @@ def rr_threshold24(p: float) -> int:
 
 
 def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=None,
-           use_bvh=True, n_threads=0, keep_paths=False, lambdas=None):
+           use_bvh=True, n_threads=0, keep_paths=False, lambdas=None, hero=False):
     """Render a workload (or a pixel subset of it).  Returns (image, stats[, paths]).
 
-    image: [n_lambda, H, W] when pixels is None, else [n_lambda, n_pixels]."""
+    image: [n_lambda, H, W] when pixels is None, else [n_lambda, n_pixels].
+    hero: one path per (pixel, sample, rotation group of four wavelengths), sampled at a hero
+    wavelength drawn from its group (n_lambda must be a multiple of 4)."""
     L = lib()
     oscene = OracleScene(wl.scene) if oscene is None else oscene
     lam = np.ascontiguousarray(wl.lambdas_um if lambdas is None else lambdas, np.float64)
@@ -257,7 +272,7 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
     op = OrOpts(spp_begin=spp_begin, spp_count=spp_count, spp_norm=spp_norm,
                 max_depth=wl.max_depth, rr_enable=int(wl.rr_enable),
                 rr_threshold24=rr_threshold24(wl.rr_p), rr_p=float(np.float32(wl.rr_p)),
-                seed=wl.seed, use_bvh=int(use_bvh), n_threads=n_threads)
+                seed=wl.seed, use_bvh=int(use_bvh), n_threads=n_threads, hero=int(hero))
     sen = _sensor_struct(wl.sensor)
     srcs = _sources_struct(wl.sources)
     if pixels is None:

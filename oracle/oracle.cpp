@@ -135,6 +135,7 @@ typedef struct {
     uint64_t seed;
     int32_t use_bvh;            // 0: brute-force closest hit
     int32_t n_threads;
+    int32_t hero;               // 1: hero-wavelength paths over rotation groups (nl % 4 == 0)
 } or_opts;
 
 }  // extern "C"
@@ -224,10 +225,13 @@ double pw_eval(const Mat& m, double k, double kix, double kiy, double kox, doubl
 // Sec. "Interaction Kernels" (grating orders, rough-surface Monte Carlo) with the incident
 // wave taken along the generalized ray's own travel direction (time reversal = wavevector
 // reversal; the kernels used here are reciprocal).  Returns false when the path ends.
+// comp (optional) receives the sampled component: the grating order j, the rough surface's
+// Poisson term n (0 = the specular delta), 0 for a smooth surface.
 bool sample_finf(const Mat& m, double k, double kix, double kiy, double ci, double u0, double u1,
                  double u2, double gx, double gy, double& kox, double& koy, double& weight,
-                 int& evanescent) {
+                 int& evanescent, int* comp = nullptr) {
     evanescent = 0;
+    if (comp) *comp = 0;
     if (m.kind == 0) {
         kox = kix; koy = kiy; weight = m.refl;
         return true;
@@ -258,6 +262,7 @@ bool sample_finf(const Mat& m, double k, double kix, double kiy, double ci, doub
         kox = kix - pick * K * gx;
         koy = kiy - pick * K * gy;
         weight = m.refl * W;
+        if (comp) *comp = pick;
         return true;
     }
     // rough: term n ~ Poisson(g) at the specular normal transfer, then kappa ~ N(0, 2n/l^2 I)
@@ -272,6 +277,7 @@ bool sample_finf(const Mat& m, double k, double kix, double kiy, double ci, doub
             if (u0 < c) { n = i; break; }
         }
     }
+    if (comp) *comp = n;
     double z1, z2;
     box_muller(u1, u2, z1, z2);
     double sd = std::sqrt(2.0 * n) / m.L;
@@ -280,6 +286,91 @@ bool sample_finf(const Mat& m, double k, double kix, double kiy, double ci, doub
     if ((kox * kox + koy * koy) >= k * k) { evanescent = 1; return false; }
     weight = m.refl;
     return true;
+}
+
+// ------------------------------------------------------------------------------------------
+// Hero-wavelength spectral sampling (Sec. "Interactive Rendering", implementation details: the
+// hero wavelength drives the path, and paths without dispersive delta segments carry up to
+// three more wavelengths).  The companions here are the other members of a rotation group of
+// the wavelength grid, and the four estimates are combined by the one-sample balance heuristic
+// over the four choices of hero (Wilkie, Nawaz, Droske, Weidlich, Hanika, "Hero wavelength
+// spectral sampling", EGSR 2014): with f_i the path's contribution and p_i its sampling
+// density at wavelength i, member i's estimate is 4 f_i / sum_k p_k.
+//
+// One continuation step, companion at wavenumber kc against the hero's kh.  Densities are over
+// the outgoing tangential direction u_o = k_o,t / k for a continuous lobe; a delta component
+// is compared by its probability.
+//   smooth : one delta at the mirror direction for every wavelength: p = 1, f = refl.
+//   grating: order j leaves at u_o = u_i - j K g / k, a delta that moves with the wavelength
+//            (dispersive) unless j = 0, so a companion reaches the hero's direction only
+//            through order 0, with probability J_0(m_0)^2 / W and value refl J_0(m_0)^2.
+//   rough  : term 0 is the specular delta, probability e^-g; terms n >= 1 spread
+//            kappa = k (u_o - u_i) as N(0, 2n/l^2 I), i.e. over u_o the density
+//            k^2 sum_{n>=1} Poisson(n; g) N(k du; 0, 2n/l^2 I); f = refl p.
+// ------------------------------------------------------------------------------------------
+
+// Order weights of a grating at wavenumber k: W = sum of J_j(m_j)^2 over the propagating
+// orders (the normalisation of order sampling) and w0 = J_0(m_0)^2.
+void grating_weights(const Mat& m, double k, double kix, double kiy, double ci, double gx, double gy,
+                     double& W, double& w0) {
+    double K = 2.0 * kPi / m.L;
+    int J = (int)std::ceil(2.0 * k / K) + 2;
+    W = 0.0;
+    w0 = 0.0;
+    for (int j = -J; j <= J; ++j) {
+        double ox = kix - j * K * gx, oy = kiy - j * K * gy;
+        double no = (ox * ox + oy * oy) / (k * k);
+        if (no >= 1.0) continue;
+        double bj = besselj(j, k * m.h * (ci + std::sqrt(1.0 - no)));
+        W += bj * bj;
+        if (j == 0) w0 = bj * bj;
+    }
+}
+
+// Continuous part (terms n >= 1) of the rough surface's sampling density over u_o, at squared
+// direction change du2 = |u_o - u_i|^2.
+double rough_lobe_density(const Mat& m, double k, double ci, double du2) {
+    double g = 4.0 * k * k * ci * ci * m.h * m.h;
+    if (g <= 0.0) return 0.0;
+    int M = (int)std::ceil(g + 20.0 * std::sqrt(g) + 40.0);
+    double lg = std::log(g), s = 0.0;
+    for (int n = 1; n <= M; ++n) {
+        double w = std::exp(-g + n * lg - std::lgamma((double)n + 1.0));
+        double var = 2.0 * n / (m.L * m.L);
+        s += w * std::exp(-0.5 * k * k * du2 / var) / (2.0 * kPi * var);
+    }
+    return k * k * s;
+}
+
+// f_c / p_h and p_c / p_h of a companion for the direction the hero sampled through component
+// comp (as returned by sample_finf).  (ux, uy): incident tangential direction; (dux, duy):
+// u_o - u_i.
+void finf_companion(const Mat& m, double kh, double kc, double ux, double uy, double ci, double dux,
+                    double duy, int comp, double gx, double gy, double& f_ph, double& p_ph) {
+    if (m.kind == 0) {
+        f_ph = m.refl;
+        p_ph = 1.0;
+        return;
+    }
+    if (m.kind == 2) {
+        if (comp != 0) { f_ph = 0.0; p_ph = 0.0; return; }
+        double Wh, w0h, Wc, w0c;
+        grating_weights(m, kh, kh * ux, kh * uy, ci, gx, gy, Wh, w0h);
+        grating_weights(m, kc, kc * ux, kc * uy, ci, gx, gy, Wc, w0c);
+        double ph = w0h / Wh;                     // > 0: the hero drew order 0
+        f_ph = m.refl * w0c / ph;
+        p_ph = (Wc > 0.0 ? w0c / Wc : 0.0) / ph;
+        return;
+    }
+    if (comp == 0) {
+        double gh = 4.0 * kh * kh * ci * ci * m.h * m.h, gc = 4.0 * kc * kc * ci * ci * m.h * m.h;
+        p_ph = std::exp(gh - gc);
+        f_ph = m.refl * p_ph;
+        return;
+    }
+    double du2 = dux * dux + duy * duy;
+    p_ph = rough_lobe_density(m, kc, ci, du2) / rough_lobe_density(m, kh, ci, du2);
+    f_ph = m.refl * p_ph;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -453,6 +544,90 @@ void make_frame(const Mat& m, V3 n, V3 d, V3& xa, V3& ya) {
     ya = cross(n, xa);
 }
 
+// Geometry of an interaction: hit point, geometric and shading normals (both facing the
+// incoming ray), cosine of incidence, tangent frame and the travel direction in that frame.
+struct Vertex {
+    V3 P, ng, ns, xa, ya;
+    double ci, dx, dy;
+    const Mat* m;
+};
+
+// Returns false when the shading normal faces away from the incoming ray.
+bool make_vertex(const SceneO& S, V3 o, V3 d, const Hit& h, Vertex& v) {
+    v.P = o + h.t * d;
+    const Tri& T = S.tris[h.tri];
+    V3 ng = unit(cross(T.p1 - T.p0, T.p2 - T.p0));
+    V3 ns = ng;
+    {
+        V3 n0 = S.vn[3 * h.tri], n1 = S.vn[3 * h.tri + 1], n2 = S.vn[3 * h.tri + 2];
+        if (dot(n0, n0) > 0.0 && dot(n1, n1) > 0.0 && dot(n2, n2) > 0.0)
+            ns = unit((1.0 - h.u - h.v) * n0 + h.u * n1 + h.v * n2);
+    }
+    if (dot(d, ng) > 0.0) ng = -1.0 * ng;
+    if (dot(ns, ng) < 0.0) ns = -1.0 * ns;
+    v.ng = ng;
+    v.ns = ns;
+    v.ci = -dot(d, ns);
+    if (v.ci <= 0.0) return false;
+    v.m = &S.mats[S.mat[h.tri]];
+    make_frame(*v.m, ns, d, v.xa, v.ya);
+    v.dx = dot(d, v.xa);
+    v.dy = dot(d, v.ya);
+    return true;
+}
+
+// Footprint of the generalized ray on the surface: intensity variance beta^2/2 across the
+// beam, stretched by 1/cos along the plane of incidence.
+void footprint(const Vertex& v, double beta2, double& sxx, double& syy, double& sxy) {
+    double sr2 = 0.5 * beta2;
+    sxx = sr2 * (1.0 + v.dx * v.dx / (v.ci * v.ci));
+    syy = sr2 * (1.0 + v.dy * v.dy / (v.ci * v.ci));
+    sxy = sr2 * (v.dx * v.dy / (v.ci * v.ci));
+}
+
+// Emitter sampling for next-event estimation from P at wavenumber k.  A plane wave arrives
+// along its direction; a Gaussian-Schell emitter's arrival wavevector is drawn from its
+// ensemble-averaged angular spectrum, a Gaussian of standard deviation 1/r_c per transverse
+// axis, and must reach the emitter's rectangle.  om: travel direction of the arriving light;
+// tmax: distance to the emitter; tt: squared transverse part of om (Gaussian-Schell).
+bool nee_direction(const or_source& L, V3 P, double k, double u1, double u2, V3& om, double& tmax,
+                   double& tt) {
+    tmax = 1e300;
+    tt = 0.0;
+    if (L.kind == 0) {
+        om = unit(ld3(L.dir));
+        return true;
+    }
+    double z1, z2;
+    box_muller(u1, u2, z1, z2);
+    double du = z1 / L.rc_um, dv = z2 / L.rc_um;      // um^-1
+    tt = (du * du + dv * dv) / (k * k);
+    if (tt >= 1.0) return false;
+    V3 ax = unit(ld3(L.dir));
+    V3 eu = ld3(L.eu), ev = ld3(L.ev);
+    double lu = norm(eu), lv = norm(ev);
+    V3 bu = (1.0 / lu) * eu, bv = (1.0 / lv) * ev;
+    om = (du / k) * bu + (dv / k) * bv + std::sqrt(1.0 - tt) * ax;
+    double den = dot(om, ax);
+    double te = dot(ld3(L.pos) - P, ax) / (-den);
+    if (!(te > t_eps(P))) return false;
+    V3 Q = P - te * om;
+    double a = dot(Q - ld3(L.pos), bu) / lu, b = dot(Q - ld3(L.pos), bv) / lv;
+    if (!(std::fabs(a) <= 1.0 && std::fabs(b) <= 1.0)) return false;
+    tmax = te;
+    return true;
+}
+
+// Free-space propagation of the generalized ray over z um (eq. K_free_space_propagation),
+// with zbar = z / |k0| and the pre-update beta, rho.
+void propagate(double z, double k, double& beta2, double& rho) {
+    double zb = z / k;
+    double rho_new = rho + zb * (1.0 + rho * rho) / beta2;
+    double beta2_new = beta2 + zb * (2.0 * rho + zb * (1.0 + rho * rho) / beta2);
+    rho = rho_new;
+    beta2 = beta2_new;
+}
+
 double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
     const SceneO& S = *C.S;
     const or_sensor& sen = *C.sen;
@@ -481,37 +656,12 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
         Hit h;
         if (!trace_ray(S, o, d, t_eps(o), 1e300, op.use_bvh != 0, false, h, prev)) break;
         prev = h.tri;
-        // Free-space propagation of the generalized ray over the hit distance
-        // (eq. K_free_space_propagation), with zbar = z / |k0| and the pre-update beta, rho.
-        double z = h.t * 1e6;
-        double zb = z / k;
-        double rho_new = rho + zb * (1.0 + rho * rho) / beta2;
-        double beta2_new = beta2 + zb * (2.0 * rho + zb * (1.0 + rho * rho) / beta2);
-        rho = rho_new;
-        beta2 = beta2_new;
-        V3 P = o + h.t * d;
-        const Tri& T = S.tris[h.tri];
-        V3 ng = unit(cross(T.p1 - T.p0, T.p2 - T.p0));
-        V3 ns = ng;
-        {
-            V3 n0 = S.vn[3 * h.tri], n1 = S.vn[3 * h.tri + 1], n2 = S.vn[3 * h.tri + 2];
-            if (dot(n0, n0) > 0.0 && dot(n1, n1) > 0.0 && dot(n2, n2) > 0.0)
-                ns = unit((1.0 - h.u - h.v) * n0 + h.u * n1 + h.v * n2);
-        }
-        if (dot(d, ng) > 0.0) ng = -1.0 * ng;
-        if (dot(ns, ng) < 0.0) ns = -1.0 * ns;
-        double ci = -dot(d, ns);
-        if (ci <= 0.0) { st.backfacing++; break; }
-        const Mat& m = S.mats[S.mat[h.tri]];
-        V3 xa, ya;
-        make_frame(m, ns, d, xa, ya);
-        // Footprint of the generalized ray on the surface: intensity variance beta^2/2
-        // across the beam, stretched by 1/cos along the plane of incidence.
-        double sr2 = 0.5 * beta2;
-        double dx = dot(d, xa), dy = dot(d, ya);
-        double sxx = sr2 * (1.0 + dx * dx / (ci * ci));
-        double syy = sr2 * (1.0 + dy * dy / (ci * ci));
-        double sxy = sr2 * (dx * dy / (ci * ci));
+        propagate(h.t * 1e6, k, beta2, rho);
+        Vertex v;
+        if (!make_vertex(S, o, d, h, v)) { st.backfacing++; break; }
+        const Mat& m = *v.m;
+        double sxx, syy, sxy;
+        footprint(v, beta2, sxx, syy, sxy);
         // The frame's x axis is the grating direction, so the grating vector is (1, 0).
         const double gx = 1.0, gy = 0.0;
 
@@ -522,38 +672,15 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
             int si = std::min((int)(unif(rn.v[0]) * C.nsrc), C.nsrc - 1);
             const or_source& L = C.src[si];
             V3 om{0, 0, 0};
-            bool ok = false;
-            double tmax = 1e300;
-            if (L.kind == 0) {
-                om = unit(ld3(L.dir));
-                ok = true;
-            } else {
-                double z1, z2;
-                box_muller(unif(rn.v[1]), unif(rn.v[2]), z1, z2);
-                double du = z1 / L.rc_um, dv = z2 / L.rc_um;      // um^-1
-                double tt = (du * du + dv * dv) / (k * k);
-                if (tt < 1.0) {
-                    V3 ax = unit(ld3(L.dir));
-                    V3 eu = ld3(L.eu), ev = ld3(L.ev);
-                    double lu = norm(eu), lv = norm(ev);
-                    V3 bu = (1.0 / lu) * eu, bv = (1.0 / lv) * ev;
-                    om = (du / k) * bu + (dv / k) * bv + std::sqrt(1.0 - tt) * ax;
-                    double den = dot(om, ax);
-                    double te = dot(ld3(L.pos) - P, ax) / (-den);
-                    if (te > t_eps(P)) {
-                        V3 Q = P - te * om;
-                        double a = dot(Q - ld3(L.pos), bu) / lu, b = dot(Q - ld3(L.pos), bv) / lv;
-                        if (std::fabs(a) <= 1.0 && std::fabs(b) <= 1.0) { ok = true; tmax = te; }
-                    }
-                }
-            }
-            if (ok && dot(om, ng) < 0.0 && dot(om, ns) < 0.0) {
+            double tmax, tt;
+            bool ok = nee_direction(L, v.P, k, unif(rn.v[1]), unif(rn.v[2]), om, tmax, tt);
+            if (ok && dot(om, v.ng) < 0.0 && dot(om, v.ns) < 0.0) {
                 st.shadow++;
                 Hit hs;
-                bool occ = trace_ray(S, P, -1.0 * om, t_eps(P), tmax, op.use_bvh != 0, true, hs, h.tri);
+                bool occ = trace_ray(S, v.P, -1.0 * om, t_eps(v.P), tmax, op.use_bvh != 0, true, hs, h.tri);
                 if (!occ) {
-                    double kix = k * dot(om, xa), kiy = k * dot(om, ya);
-                    double kox = -k * dx, koy = -k * dy;
+                    double kix = k * dot(om, v.xa), kiy = k * dot(om, v.ya);
+                    double kox = -k * v.dx, koy = -k * v.dy;
                     double p = pw_eval(m, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
                     contrib += alpha * L.power * p * (double)C.nsrc;
                 }
@@ -563,9 +690,9 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
 
         // Light-matter interaction: sample the continuation generalized ray.
         U4 rs = draw(pid, depth, STREAM_SCATTER, op.seed);
-        double kix = k * dx, kiy = k * dy, kox, koy, wgt;
+        double kix = k * v.dx, kiy = k * v.dy, kox, koy, wgt;
         int ev;
-        if (!sample_finf(m, k, kix, kiy, ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), gx, gy,
+        if (!sample_finf(m, k, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), gx, gy,
                          kox, koy, wgt, ev)) {
             st.evanescent += ev;
             break;
@@ -576,11 +703,122 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
             alpha /= op.rr_p;
         }
         double kn = std::sqrt(std::max(0.0, 1.0 - (kox * kox + koy * koy) / (k * k)));
-        d = (kox / k) * xa + (koy / k) * ya + kn * ns;
+        d = (kox / k) * v.xa + (koy / k) * v.ya + kn * v.ns;
         d = unit(d);
-        o = P;
+        o = v.P;
     }
     return contrib;
+}
+
+// One hero-wavelength path: the path of trace_path, sampled at the hero wavelength, carrying
+// the four wavelengths of rotation group grp of the grid (indices grp + i G, G = nl / 4; the
+// hero is member r0.w >> 30 of the group).  Path id ((s H + y) W + x) G + grp.  Each member
+// keeps its own beta, rho (the free-space law depends on |k|) and its own footprint; they share
+// the geometric path.  Per member i: T_i = f_i / p_h and R_i = p_i / p_h along the path; next-
+// event estimation at a vertex adds 4 T_i q_i M_i / sum_k R_k q_k, with M_i the member's
+// measurement and q_i the ratio of its emitter-sampling density to the hero's.
+// out[i]: contribution to wavelength grp + i G.
+void trace_path_hero(const Ctx& C, int px, int py, int64_t s, int grp, Stats& st, double out[4]) {
+    const SceneO& S = *C.S;
+    const or_sensor& sen = *C.sen;
+    const or_opts& op = *C.op;
+    const uint64_t W = (uint64_t)sen.width, H = (uint64_t)sen.height;
+    const int G = C.nl / 4;
+    const uint64_t pid = ((((uint64_t)s * H) + (uint64_t)py) * W + (uint64_t)px) * (uint64_t)G +
+                         (uint64_t)grp;
+    double k[4];
+    for (int i = 0; i < 4; ++i) k[i] = 2.0 * kPi / C.lambdas[grp + i * G];
+
+    U4 r0 = draw(pid, 0, STREAM_SOURCE, op.seed);
+    const int hi = (int)(r0.v[3] >> 30);
+    const double kh = k[hi];
+    V3 o = ld3(sen.origin) + ((px + unif(r0.v[0])) * sen.pitch_m) * ld3(sen.axis_u) +
+           ((py + unif(r0.v[1])) * sen.pitch_m) * ld3(sen.axis_v);
+    V3 d = ld3(sen.dir);
+    double sig_um = sen.sigma_m * 1e6;
+    double beta2[4], rho[4], T[4], R[4];
+    for (int i = 0; i < 4; ++i) {
+        beta2[i] = 2.0 * sig_um * sig_um;
+        rho[i] = 0.0;
+        T[i] = 1.0;
+        R[i] = 1.0;
+        out[i] = 0.0;
+    }
+    int prev = -1;
+
+    for (int depth = 0; depth < op.max_depth; ++depth) {
+        st.segments++;
+        Hit h;
+        if (!trace_ray(S, o, d, t_eps(o), 1e300, op.use_bvh != 0, false, h, prev)) break;
+        prev = h.tri;
+        for (int i = 0; i < 4; ++i) propagate(h.t * 1e6, k[i], beta2[i], rho[i]);
+        Vertex v;
+        if (!make_vertex(S, o, d, h, v)) { st.backfacing++; break; }
+        const Mat& m = *v.m;
+        const double gx = 1.0, gy = 0.0;
+
+        U4 rn = draw(pid, depth, STREAM_NEE, op.seed);
+        if (C.nsrc > 0) {
+            int si = std::min((int)(unif(rn.v[0]) * C.nsrc), C.nsrc - 1);
+            const or_source& L = C.src[si];
+            V3 om{0, 0, 0};
+            double tmax, tt;
+            bool ok = nee_direction(L, v.P, kh, unif(rn.v[1]), unif(rn.v[2]), om, tmax, tt);
+            if (ok && dot(om, v.ng) < 0.0 && dot(om, v.ns) < 0.0) {
+                st.shadow++;
+                Hit hs;
+                bool occ = trace_ray(S, v.P, -1.0 * om, t_eps(v.P), tmax, op.use_bvh != 0, true, hs, h.tri);
+                if (!occ) {
+                    // emitter-sampling density of the arrival direction at each member,
+                    // relative to the hero's: the angular spectrum N(k u_t; 0, rc^-2 I) k^2
+                    double q[4], den = 0.0;
+                    for (int i = 0; i < 4; ++i) {
+                        q[i] = L.kind == 0 ? 1.0
+                                           : (k[i] * k[i]) / (kh * kh) *
+                                                 std::exp(-0.5 * (k[i] * k[i] - kh * kh) * tt * L.rc_um * L.rc_um);
+                        den += R[i] * q[i];
+                    }
+                    for (int i = 0; i < 4; ++i) {
+                        if (T[i] == 0.0) continue;
+                        double sxx, syy, sxy;
+                        footprint(v, beta2[i], sxx, syy, sxy);
+                        double p = pw_eval(m, k[i], k[i] * dot(om, v.xa), k[i] * dot(om, v.ya), -k[i] * v.dx,
+                                           -k[i] * v.dy, sxx, syy, sxy, gx, gy);
+                        out[i] += 4.0 * T[i] * q[i] * L.power * p * (double)C.nsrc / den;
+                    }
+                }
+            }
+        }
+        if (depth + 1 >= op.max_depth) break;
+
+        U4 rs = draw(pid, depth, STREAM_SCATTER, op.seed);
+        double kix = kh * v.dx, kiy = kh * v.dy, kox, koy, wgt;
+        int ev, comp;
+        if (!sample_finf(m, kh, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), gx, gy,
+                         kox, koy, wgt, ev, &comp)) {
+            st.evanescent += ev;
+            break;
+        }
+        for (int i = 0; i < 4; ++i) {
+            if (i == hi) {
+                T[i] *= wgt;
+                continue;
+            }
+            double f_ph, p_ph;
+            finf_companion(m, kh, k[i], v.dx, v.dy, v.ci, (kox - kix) / kh, (koy - kiy) / kh, comp, gx, gy,
+                           f_ph, p_ph);
+            T[i] *= f_ph;
+            R[i] *= p_ph;
+        }
+        if (op.rr_enable && depth + 1 >= 2) {
+            if (!((rs.v[3] >> 8) < op.rr_threshold24)) break;
+            for (int i = 0; i < 4; ++i) T[i] /= op.rr_p;
+        }
+        double kn = std::sqrt(std::max(0.0, 1.0 - (kox * kox + koy * koy) / (kh * kh)));
+        d = (kox / kh) * v.xa + (koy / kh) * v.ya + kn * v.ns;
+        d = unit(d);
+        o = v.P;
+    }
 }
 
 }  // namespace
@@ -640,6 +878,32 @@ int or_sample(int kind, double h, double L, double refl, double k, double kix, d
     return ok ? 1 : 0;
 }
 
+// Hero-wavelength continuation step for a batch of uniforms u[n][3]: sample at kh from the
+// incident tangential direction (ux, uy), then the companion ratios at kc.  out[n][5] =
+// (kox, koy, hero weight, f_c / p_h, p_c / p_h), all NaN when the sample ends the path.
+void or_hero_step_batch(int kind, double h, double L, double refl, double kh, double kc, double ux,
+                        double uy, double ci, double gx, double gy, const double* u, int64_t n,
+                        double* out) {
+    Mat m{kind, h, L, refl, {1, 0, 0}};
+    for (int64_t i = 0; i < n; ++i) {
+        double* o = out + 5 * i;
+        double kox, koy, w;
+        int ev, comp;
+        if (!sample_finf(m, kh, kh * ux, kh * uy, ci, u[3 * i], u[3 * i + 1], u[3 * i + 2], gx, gy, kox, koy, w,
+                         ev, &comp)) {
+            for (int j = 0; j < 5; ++j) o[j] = std::nan("");
+            continue;
+        }
+        double f_ph, p_ph;
+        finf_companion(m, kh, kc, ux, uy, ci, kox / kh - ux, koy / kh - uy, comp, gx, gy, f_ph, p_ph);
+        o[0] = kox;
+        o[1] = koy;
+        o[2] = w;
+        o[3] = f_ph;
+        o[4] = p_ph;
+    }
+}
+
 void* or_scene_create(const double* verts, int64_t nv, const double* normals,
                       const int32_t* tris, int64_t nt, const int32_t* tri_mat,
                       const or_material* mats, int32_t nm) {
@@ -697,6 +961,7 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
              const double* lambdas, int32_t nl, const or_opts* op, const int32_t* pixels,
              int64_t npix, double* image, double* paths, uint64_t* stats) {
     if (!s || !sen || !op || nl <= 0 || op->spp_count < 0 || op->max_depth < 0) return -1;
+    if (op->hero && nl % 4 != 0) return -1;
     const SceneO* S = (const SceneO*)s;
     if (!pixels) npix = (int64_t)sen->width * sen->height;
     Ctx C{S, sen, src, nsrc, lambdas, nl, op};
@@ -712,6 +977,23 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
             int px, py;
             if (pixels) { px = pixels[2 * p]; py = pixels[2 * p + 1]; }
             else { px = (int)(p % sen->width); py = (int)(p / sen->width); }
+            if (op->hero) {
+                const int G = nl / 4;
+                for (int g = 0; g < G; ++g) {
+                    double acc[4] = {0, 0, 0, 0};
+                    for (int64_t sl = 0; sl < op->spp_count; ++sl) {
+                        double c[4];
+                        trace_path_hero(C, px, py, op->spp_begin + sl, g, st, c);
+                        for (int i = 0; i < 4; ++i) {
+                            c[i] /= op->spp_norm;
+                            if (paths) paths[(sl * npix + p) * nl + g + i * G] = c[i];
+                            acc[i] += c[i];
+                        }
+                    }
+                    for (int i = 0; i < 4; ++i) image[(int64_t)(g + i * G) * npix + p] = acc[i];
+                }
+                continue;
+            }
             for (int w = 0; w < nl; ++w) {
                 double acc = 0.0;
                 for (int64_t sl = 0; sl < op->spp_count; ++sl) {

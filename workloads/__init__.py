@@ -13,6 +13,7 @@ from .scenes import (  # noqa: F401
     Workload,
     wavelength_bins,
     tiny_grating,
+    parallel_mirror,
     terrain_scene,
     mid_terrain,
     large_scene,

@@ -131,6 +131,26 @@ def tiny_grating(width: int = 32, height: int = 32, spp: int = 8, seed: int = 1)
                     max_depth=1, seed=seed)
 
 
+def parallel_mirror(width: int = 16, height: int = 16, spp: int = 4, n_lambda: int = 8,
+                    seed: int = 5) -> Workload:
+    """1 mm square smooth quad in z=0 under a plane wave travelling along -z, seen at normal
+    incidence by an orthographic sensor 1 cm above it (its axis along -z): every path meets
+    the quad at the same distance and is lit at the mirror direction, so each path of a given
+    wavelength contributes the same value, whatever its random numbers."""
+    half = 0.5e-3
+    verts = np.array([[-half, -half, 0.0], [half, -half, 0.0], [half, half, 0.0],
+                      [-half, half, 0.0]], np.float64)
+    tris = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    scene = Scene(verts=verts, tris=tris, tri_mat=np.zeros(2, np.int32),
+                  materials=[Material(SMOOTH, reflectance=0.9)], normals=None)
+    pitch = 0.5e-3 / width
+    sensor = _ortho_sensor(np.array([0.0, 0.0, 0.01]), np.array([0.0, 0.0, -1.0]),
+                           np.array([0.0, 1.0, 0.0]), width, height, pitch, 20e-6)
+    src = Source(PLANE_WAVE, dir=np.array([0.0, 0.0, -1.0]), power=1.0)
+    return Workload("parallel-mirror", scene, sensor, [src], wavelength_bins(n_lambda), spp=spp,
+                    max_depth=2, seed=seed)
+
+
 # --------------------------------------------------------------------------------------
 # Terrain: value-noise heightfield with per-tile materials
 # --------------------------------------------------------------------------------------
