@@ -155,6 +155,32 @@ def surrogate_leg(R, wl, o_plain, img, st_plain, args):
     return out
 
 
+def hero_leg(R, wl, ms_plain, args):
+    """Hero-wavelength paths (one path per pixel, sample and rotation group of four wavelengths)
+    on the same workload: the same image estimated from a quarter of the paths.  Reported: the
+    frame time, path segments per second, and wavelength-segments per second (each hero segment
+    carries four).  Both estimators are unbiased for the same image (checked by the tests); a
+    single frame's totals are dominated by rare bright paths, so they are not compared here."""
+    import torch
+    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+               rr_enable=wl.rr_enable, rr_p=wl.rr_p, hero=True)
+    img = torch.zeros((len(wl.lambdas_um), wl.sensor.height, wl.sensor.width), device=R.dev)
+    _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(R.stream)
+    for _ in range(args.steps):
+        R.trace(wl.lambdas_um, o, image=img, stats=False)
+    e1.record(R.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    return {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
+            "ms_per_step": round(ms, 3), "paths_per_step": st["paths"], "segments_per_step": st["segments"],
+            "wavelength_segments_per_s_M": round(4 * st["segments"] / (ms * 1e-3) / 1e6, 2),
+            "frame_speedup_vs_one_wavelength_paths": round(ms_plain / ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -163,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
                     help="skip the learned-p_w leg (training takes a few seconds)")
+    ap.add_argument("--no-hero", dest="hero", action="store_false",
+                    help="skip the hero-wavelength leg")
     ap.add_argument("--workload", choices=["mid", "large"], default="mid",
                     help="mid: the 65,536-triangle terrain (the reported line); large: the "
                          "4,194,300-triangle instanced scene at 1920x1080, 64 spp, 16 wavelengths")
@@ -260,6 +288,8 @@ def main():
                    "bvh_depth": info["depth"]},
         "roofline": roofline,
     }
+    if args.hero and len(wl.lambdas_um) % 4 == 0:
+        out["hero"] = hero_leg(R, wl, ms_step, args)
     if args.surrogate:
         out["surrogate"] = surrogate_leg(R, wl, o, img, st, args)
     if not args.no_cpu:

@@ -92,7 +92,7 @@ typedef struct {
     float power;
 } gr_source;
 
-enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2, GR_TRACE_WAVEFRONT = 4 };
+enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2, GR_TRACE_WAVEFRONT = 4, GR_TRACE_HERO = 8 };
 
 /* Trace options.
  *   spp_begin, spp_count : sample indices [spp_begin, spp_begin + spp_count) of every pixel and
@@ -113,7 +113,19 @@ enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2, GR_TRACE_WAVEFRONT
  *                          exists to exercise the overflow path.  GR_TRACE_WAVEFRONT renders
  *                          with the wavefront kernels (per-bounce queues in the workspace)
  *                          instead of the persistent path kernel; the image is the same up to
- *                          the rounding of a few shortened paths.  Other bits are invalid. */
+ *                          the rounding of a few shortened paths.  GR_TRACE_HERO traces
+ *                          hero-wavelength paths (Sec. "Interactive Rendering", implementation
+ *                          details: the hero wavelength drives the path and up to three more
+ *                          wavelengths ride along): the n_lambda wavelengths (a multiple of 4)
+ *                          form G = n_lambda / 4 rotation groups {g, g + G, g + 2G, g + 3G}; one
+ *                          path per (pixel, sample, group) is sampled at a member drawn
+ *                          uniformly (the hero), every member keeps its own beta, rho and
+ *                          footprint, and the members' estimates are combined by the one-sample
+ *                          balance heuristic over the choice of hero (grating orders other than
+ *                          0 are dispersive and carry the hero alone).  A quarter of the paths
+ *                          of the default render, a different estimator of the same image; the
+ *                          records keep their layout.  Closed-form p_w and the persistent
+ *                          kernel only (else GR_E_UNSUPPORTED).  Other bits are invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;

@@ -41,6 +41,7 @@ struct gr_ctx {
     std::vector<gr_source> sources;
     int grid_plain = 0;              // persistent grids (blocks), set at scene upload
     int grid_sur = 0;
+    int grid_hero = 0;
     int grid_batch = 0;              // blocks of the batched network pass
     int grid_wf = 0;                 // blocks of the wavefront traversal kernels
     int grid_work = 0;               // blocks of the grid-stride wavefront kernels
@@ -107,6 +108,7 @@ struct WsLayout {
 };
 
 bool wavefront_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_WAVEFRONT) != 0; }
+bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
 
 // Per-path wavefront arrays in this order, each padded to 256 B (element sizes in bytes).
 constexpr int kWfArrays = 27;
@@ -298,6 +300,7 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     c->build_ms = std::chrono::duration<float, std::milli>(t1 - t0).count();
     c->grid_plain = grw::trace_grid_size(c->device, false);
     c->grid_sur = grw::trace_grid_size(c->device, true);
+    c->grid_hero = grw::trace_grid_size(c->device, false, true);
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
@@ -309,7 +312,7 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
-    if (c->grid_plain <= 0 || c->grid_sur <= 0) {
+    if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0) {
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
@@ -377,7 +380,7 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     WsLayout L;
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
     const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
-    const size_t lanes = (size_t)std::max(std::max(c->grid_plain, c->grid_sur), c->grid_wf) * 256;
+    const size_t lanes = (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_wf}) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
@@ -420,8 +423,13 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (o->max_depth < 1 || o->max_depth > 64) return fail(c, GR_E_INVALID, "trace: max_depth %d", o->max_depth);
     if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
     if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
-    if (o->flags & ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_WAVEFRONT))
+    if (o->flags & ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_WAVEFRONT | GR_TRACE_HERO))
         return fail(c, GR_E_INVALID, "trace: flags");
+    if (hero_of(o)) {
+        if (nl % 4 != 0) return fail(c, GR_E_INVALID, "trace: hero wavelengths need n_lambda %% 4 == 0 (got %d)", nl);
+        if (o->bsdf_mode != GR_BSDF_PLAIN || wavefront_of(o))
+            return fail(c, GR_E_UNSUPPORTED, "trace: hero wavelengths with the closed-form p_w and the persistent kernel only");
+    }
     if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
         return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
@@ -480,8 +488,9 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.nl = nl;
     for (int i = 0; i < nl; ++i) a.lambda[i] = lambda[i];
     a.spp_begin = o->spp_begin;
-    a.n_paths = per * (uint64_t)o->spp_count;
-    a.per_sample = (uint32_t)per;
+    a.hero = hero_of(o) ? 1 : 0;
+    a.per_sample = (uint32_t)(a.hero ? per / 4 : per);   // hero: one path per group of 4 wavelengths
+    a.n_paths = (uint64_t)a.per_sample * (uint64_t)o->spp_count;
     a.inv_spp_norm = (float)(1.0 / (double)o->spp_norm);
     a.max_depth = o->max_depth;
     a.rr_enable = o->rr_enable;
@@ -506,7 +515,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     float* dense = defer ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
 
     GR_HIP(c, hipSetDevice(c->device));
-    const int grid = defer ? c->grid_sur : c->grid_plain;
+    const int grid = defer ? c->grid_sur : (a.hero ? c->grid_hero : c->grid_plain);
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (st)
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));

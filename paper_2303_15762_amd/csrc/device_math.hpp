@@ -282,11 +282,14 @@ __device__ __noinline__ int poisson_inverse(double g, float u0) {
 //            m_j = k A (cos i + cos o_j); weight = reflectance * W (evanescent orders dropped)
 //   rough  : term m ~ Poisson(g), g = (2 k cos i s)^2, then kappa ~ N(0, 2m/l^2 I);
 //            weight = reflectance; an evanescent draw ends the path
-// Returns 0 on success, 1 when the path ends evanescently.
+// Returns 0 on success, 1 when the path ends evanescently.  comp (optional) receives the
+// sampled component: the grating order, the rough surface's Poisson term (0 = the specular
+// delta), 0 for a smooth surface.
 // ------------------------------------------------------------------------------------------
 __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, float ci,
                                   float u0, float u1, float u2, float& kox, float& koy,
-                                  float& weight, float* cache, int cache_n) {
+                                  float& weight, float* cache, int cache_n, int* comp = nullptr) {
+    if (comp) *comp = 0;
     if (m.kind == MAT_SMOOTH) {
         kox = kix;
         koy = kiy;
@@ -346,10 +349,12 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         kox = kix - (float)pick * K;
         koy = kiy;
         weight = m.refl * W;
+        if (comp) *comp = pick;
         return 0;
     }
     // rough: Poisson term by inversion of the CDF in double precision
     const int n = poisson_inverse(4.0 * (double)k2 * (double)ci * (double)ci * (double)m.h * (double)m.h, u0);
+    if (comp) *comp = n;
     float z1, z2;
     box_muller(u1, u2, z1, z2);
     const float sd = sqrtf(2.0f * (float)n) / m.L;
@@ -358,6 +363,65 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
     if (kox * kox + koy * koy >= k2) return 1;
     weight = m.refl;
     return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Hero-wavelength companions.  A path sampled at its hero wavelength also carries the other
+// members of the hero's rotation group of the wavelength grid; the members' estimates are
+// combined by the one-sample balance heuristic over the choice of hero (Wilkie et al., "Hero
+// wavelength spectral sampling", EGSR 2014).  For the direction the hero sampled, a member's
+// value f_c and density p_c are compared with the hero's density p_h over the outgoing
+// tangential direction u_o = k_o,t / k (continuous lobes) or by probability (deltas):
+//   smooth : one non-dispersive delta: p_c / p_h = 1, f_c / p_h = refl
+//   grating: order j != 0 is a delta whose direction moves with the wavelength (dispersive):
+//            no member shares it; order 0 has probability J_0(m_0)^2 / W at every wavelength
+//   rough  : the specular delta has probability exp(-g); the terms n >= 1 form the density
+//            below; f_c / p_h = refl p_c / p_h
+// ------------------------------------------------------------------------------------------
+
+// Order weights of a grating at wavenumber k: W = sum of J_j(m_j)^2 over the propagating
+// orders and w0 = J_0(m_0)^2, with m_j = k A (cos i + cos o_j) as in sample_finf.
+__device__ inline void grating_weights(const DMat& m, float k, float kix, float kiy, float ci, float& W,
+                                       float& w0) {
+    W = 0.0f;
+    w0 = 0.0f;
+    const float k2 = k * k;
+    const float K = kTwoPiF / m.L;
+    const float rem = k2 - kiy * kiy;
+    if (rem <= 0.0f) return;
+    const float r = sqrtf(rem);
+    const int jlo = (int)floorf((kix - r) / K) - 1;
+    const int jhi = min((int)ceilf((kix + r) / K) + 1, jlo + 4096);
+    for (int j = jlo; j <= jhi; ++j) {
+        const float ox = kix - (float)j * K;
+        const float no = (ox * ox + kiy * kiy) / k2;
+        if (no >= 1.0f) continue;
+        const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
+        W += bj * bj;
+        if (j == 0) w0 = bj * bj;
+    }
+}
+
+// Continuous part (terms n >= 1) of a rough surface's continuation density over u_o at
+// squared direction change du2 = |u_o - u_i|^2:
+//   k^2 sum_{n>=1} Poisson(n; g) exp(-k^2 du2 l^2 / (4 n)) l^2 / (4 pi n),  g = (2 k cos i s)^2.
+// Terms outside [g - 6 sqrt(g) - 3, g + 8 sqrt(g) + 8] are skipped (Poisson mass < 1e-9).
+__device__ inline float rough_lobe_density(float k, float ci, float h, float L, float du2) {
+    const float g = 4.0f * k * k * ci * ci * h * h;
+    if (!(g > 1e-12f)) return 0.0f;
+    const float sq = sqrtf(g);
+    const int nlo = max(1, (int)floorf(g - 6.0f * sq - 3.0f));
+    const int nhi = min((int)ceilf(g + 8.0f * sq + 8.0f), nlo + 8191);
+    const float A = 0.25f * k * k * du2 * L * L;
+    const float lp0 = log_poisson(nlo, g, logf(g));
+    float w = 1.0f;   // Poisson(n; g) / Poisson(nlo; g)
+    float s = 0.0f;
+    for (int n = nlo; n <= nhi; ++n) {
+        const float rn = __builtin_amdgcn_rcpf((float)n);
+        s += w * __expf(lp0 - A * rn) * rn;
+        w *= g * __builtin_amdgcn_rcpf((float)(n + 1));
+    }
+    return s * k * k * L * L * (1.0f / (4.0f * kPiF));
 }
 
 }  // namespace grw

@@ -16,12 +16,101 @@
 
 namespace grw {
 
+// Hero-wavelength continuation: the hero (member hs, wavenumber kh) sampled (kox, koy) with
+// weight wgt through component comp from the incident (kix, kiy); every member's value ratio
+// f / p_h multiplies T and its density ratio p / p_h multiplies R.  A common factor of all T
+// and R leaves the balance-heuristic estimates unchanged, so R is renormalised to max 1 (and
+// the specular ratio exp(g_h - g_c) is formed relative to the largest member) to keep both in
+// FP32 range.
+__device__ inline void hero_continuation(const DMat& m, float kh, const float (&mk)[4], int hs, float kix,
+                                         float kiy, float ci, float kox, float koy, float wgt, int comp,
+                                         float (&T)[4], float (&R)[4]) {
+    const float ux = kix / kh, uy = kiy / kh;
+    float rf[4], rp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        rf[i] = 0.0f;
+        rp[i] = 0.0f;
+    }
+    if (m.kind == MAT_SMOOTH) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            rf[i] = m.refl;
+            rp[i] = 1.0f;
+        }
+    } else if (m.kind == MAT_GRATING) {
+        if (comp == 0) {
+            float Wh, w0h;
+            grating_weights(m, kh, kix, kiy, ci, Wh, w0h);
+            const float ph = w0h / Wh;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i == hs) continue;
+                float Wc, w0c;
+                grating_weights(m, mk[i], mk[i] * ux, mk[i] * uy, ci, Wc, w0c);
+                rf[i] = m.refl * w0c / ph;
+                rp[i] = (Wc > 0.0f ? w0c / Wc : 0.0f) / ph;
+            }
+        }
+    } else if (comp == 0) {
+        const float c2h2 = 4.0f * ci * ci * m.h * m.h;
+        const float gh = kh * kh * c2h2;
+        float lr[4], mx = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            lr[i] = gh - mk[i] * mk[i] * c2h2;
+            if (i != hs) mx = fmaxf(mx, lr[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            rp[i] = __expf((i == hs ? 0.0f : lr[i]) - mx);
+            rf[i] = m.refl * rp[i];
+        }
+        wgt *= rp[hs];   // the hero's share of the common factor exp(-mx)
+    } else {
+        const float du2 = ((kox - kix) * (kox - kix) + (koy - kiy) * (koy - kiy)) / (kh * kh);
+        const float dh = rough_lobe_density(kh, ci, m.h, m.L, du2);
+        if (dh > 0.0f) {
+            const float idh = 1.0f / dh;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i == hs) continue;
+                rp[i] = rough_lobe_density(mk[i], ci, m.h, m.L, du2) * idh;
+                rf[i] = m.refl * rp[i];
+            }
+        }
+    }
+    float rmax = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i == hs) {
+            T[i] *= wgt;
+            R[i] *= m.kind == MAT_ROUGH && comp == 0 ? rp[i] : 1.0f;
+        } else {
+            T[i] *= rf[i];
+            R[i] *= rp[i];
+        }
+        rmax = fmaxf(rmax, R[i]);
+    }
+    const float inv = 1.0f / rmax;   // R of the hero > 0
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        T[i] *= inv;
+        R[i] *= inv;
+    }
+}
+
 // DEFER: rough-surface measurements inside the learned model's domain are not evaluated here;
 // their encoded queries go to a queue that one batched matrix-core kernel evaluates after the
 // trace (its results are added to the path records in a fixed order).
-// Both instantiations ask for 4 waves per SIMD (128 VGPRs): a few path-state values spill to
+// HERO: each path carries the four wavelengths of a rotation group of the grid (indices
+// g + i nl/4), sampled at the hero member drawn at sourcing; every member keeps its own beta,
+// rho and footprint, and its estimate is 4 T_i q_i M_i / sum_k R_k q_k (one-sample balance
+// heuristic over the hero choices), with q the members' emitter-sampling densities relative
+// to the hero's and M the measurement.
+// All instantiations ask for 4 waves per SIMD (128 VGPRs): a few path-state values spill to
 // scratch, which costs less than the latency hidden by the fourth wave.
-template <int STACK, bool DEFER>
+template <int STACK, bool DEFER, bool HERO>
 __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
@@ -40,6 +129,12 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     d3 o = d3{0.0, 0.0, 0.0};
     f3 d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
+    // hero-wavelength members: wavenumber, beta^2, rho, T = f / p_h, R = p / p_h, estimate
+    constexpr int NM = HERO ? 4 : 1;
+    float mk[NM], mb2[NM], mrho[NM], mT[NM], mR[NM], macc[NM];
+    int hs = 0;
+#pragma unroll
+    for (int i = 0; i < NM; ++i) mk[i] = mb2[i] = mrho[i] = mT[i] = mR[i] = macc[i] = 0.0f;
     // traversal work per lane; the per-path events are flagged per lane (one bit each) and
     // counted per wave with ballots, which keeps the counts in scalar registers
     uint32_t c_nodes = 0, c_tris = 0;
@@ -67,13 +162,24 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         idx = my;
                         const uint64_t sl = my / A.per_sample;
                         const uint32_t rem = (uint32_t)(my - sl * A.per_sample);
-                        const uint32_t w = rem % nl;
-                        const uint32_t pix = rem / nl;
+                        // hero paths: w is the rotation group, G = nl / 4 groups
+                        const uint32_t nw = HERO ? (nl >> 2) : nl;
+                        const uint32_t w = rem % nw;
+                        const uint32_t pix = rem / nw;
                         const uint32_t x = pix % Wd, y = pix / Wd;
                         const uint64_t s_abs = (uint64_t)A.spp_begin + sl;
-                        pid = ((s_abs * Hd + y) * Wd + x) * nl + w;
-                        k = kTwoPiF / A.lambda[w];
+                        pid = ((s_abs * Hd + y) * Wd + x) * nw + w;
                         const uint4 r0 = draw(pid, 0, STREAM_SOURCE, A.seed);
+                        if constexpr (HERO) {
+                            hs = (int)(r0.w >> 30);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                mk[i] = kTwoPiF / A.lambda[w + i * nw];
+                                if (i == hs) k = mk[i];
+                            }
+                        } else {
+                            k = kTwoPiF / A.lambda[w];
+                        }
                         const double fx = ((double)x + (double)unif(r0.x)) * (double)sen.pitch;
                         const double fy = ((double)y + (double)unif(r0.y)) * (double)sen.pitch;
                         o = d3{sen.o[0] + fx * sen.u[0] + fy * sen.v[0], sen.o[1] + fx * sen.u[1] + fy * sen.v[1],
@@ -86,6 +192,21 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         // distances; the free-space law composes, so the skipped stretch is
                         // propagated here
                         const float tadv = scene_entry(A.scene, o, d);
+                        if constexpr (HERO) {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                mb2[i] = beta2;
+                                mrho[i] = 0.0f;
+                                mT[i] = 1.0f;
+                                mR[i] = 1.0f;
+                                macc[i] = 0.0f;
+                                if (tadv > 0.0f) {
+                                    const float zb = tadv * 1e6f / mk[i];
+                                    mrho[i] = zb / beta2;
+                                    mb2[i] = beta2 + zb * zb / beta2;
+                                }
+                            }
+                        }
                         if (tadv > 0.0f) {
                             o = add_scaled(o, tadv, d);
                             const float zb = tadv * 1e6f / k;
@@ -122,11 +243,22 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
             refine_hit(o, d, v0, v1, v2, thit, bu, bv, t64);
             // Free-space propagation of the generalized ray (eq. K_free_space_propagation)
             // over the hit distance, zbar = z / |k0|, pre-update beta and rho on the right.
-            const float zb = thit * 1e6f / k;
-            const float orr = 1.0f + rho * rho;
-            const float rho_n = rho + zb * orr / beta2;
-            beta2 = beta2 + zb * (2.0f * rho + zb * orr / beta2);
-            rho = rho_n;
+            if constexpr (HERO) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float zb = thit * 1e6f / mk[i];
+                    const float orr = 1.0f + mrho[i] * mrho[i];
+                    const float rho_n = mrho[i] + zb * orr / mb2[i];
+                    mb2[i] = mb2[i] + zb * (2.0f * mrho[i] + zb * orr / mb2[i]);
+                    mrho[i] = rho_n;
+                }
+            } else {
+                const float zb = thit * 1e6f / k;
+                const float orr = 1.0f + rho * rho;
+                const float rho_n = rho + zb * orr / beta2;
+                beta2 = beta2 + zb * (2.0f * rho + zb * orr / beta2);
+                rho = rho_n;
+            }
             const d3 P = d3{o.x + t64 * d.x, o.y + t64 * d.y, o.z + t64 * d.z};
             prev = __float_as_int(v0.w);
             const DMat m = A.scene.mats[__float_as_int(v1.w)];
@@ -188,7 +320,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     const SourceDev& L = A.src[si];
                     f3 om = mk3(0, 0, 0);
                     bool ok = false;
-                    float tmax_s = FLT_MAX;
+                    float tmax_s = FLT_MAX, tt_s = 0.0f;
                     const float tminP = 1e-7f * (1.0f + maxabs3(to_f3(P)));
                     if (L.kind == 0) {
                         om = ld3(L.dir);
@@ -198,6 +330,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         box_muller(unif(rn.y), unif(rn.z), z1, z2);
                         const float du = z1 / L.rc_um, dv = z2 / L.rc_um;
                         const float tt = (du * du + dv * dv) / (k * k);
+                        tt_s = tt;
                         if (tt < 1.0f) {
                             const f3 ax = ld3(L.dir), eu = ld3(L.bu), ev = ld3(L.bv);
                             om = (du / k) * eu + (dv / k) * ev + sqrtf(1.0f - tt) * ax;
@@ -219,7 +352,30 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         ray_setup(sray, P, -1.0f * om);
                         float tm = tmax_s, su, sv;
                         const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, su, sv);
-                        if (occ < 0) {
+                        if (HERO && occ < 0) {
+                            // members: emitter-sampling density of om relative to the hero's
+                            // (Gaussian angular spectrum N(k u_t; 0, rc^-2 I) k^2), then the
+                            // balance-heuristic estimate of each
+                            float q[NM], den = 0.0f;
+#pragma unroll
+                            for (int i = 0; i < NM; ++i) {
+                                q[i] = L.kind == 0 ? 1.0f
+                                                   : mk[i] * mk[i] / (k * k) *
+                                                         __expf(-0.5f * (mk[i] * mk[i] - k * k) * tt_s * L.rc_um * L.rc_um);
+                                den += mR[i] * q[i];
+                            }
+                            const float cx = dot3(om, xa), cy = dot3(om, ya);
+                            const float scale = 4.0f * L.power * (float)A.nsrc / den;
+#pragma unroll
+                            for (int i = 0; i < NM; ++i) {
+                                if (mT[i] == 0.0f) continue;
+                                const float sr = 0.5f * mb2[i];
+                                const float p = pw_plain(m.kind, m.h, m.L, m.refl, mk[i], mk[i] * cx, mk[i] * cy,
+                                                         -mk[i] * dx, -mk[i] * dy, sr * (1.0f + dx * dx * ic2),
+                                                         sr * (1.0f + dy * dy * ic2), sr * (dx * dy * ic2), 1.0f, 0.0f);
+                                macc[i] += scale * mT[i] * q[i] * p;
+                            }
+                        } else if (occ < 0) {
                             const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
                             const float kox = -k * dx, koy = -k * dy;
                             const float scale = alpha * L.power * (float)A.nsrc;
@@ -265,15 +421,27 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     // Light-matter interaction: sample the continuation generalized ray.
                     const uint4 rs = draw(pid, (uint32_t)depth, STREAM_SCATTER, A.seed);
                     float kox, koy, wgt;
+                    int comp = 0;
                     if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
-                                    reinterpret_cast<float*>(stk), STACK)) {
+                                    reinterpret_cast<float*>(stk), STACK, HERO ? &comp : nullptr)) {
                         ev |= 1u << EV_EVANESCENT;
                         finish = true;
                     } else {
-                        alpha *= wgt;
+                        if constexpr (HERO) {
+                            hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp, mT, mR);
+                        } else {
+                            alpha *= wgt;
+                        }
                         if (A.rr_enable && depth + 1 >= 2) {
-                            if ((rs.w >> 8) < A.rr_thr) alpha *= A.inv_rr_p;
-                            else finish = true;
+                            if ((rs.w >> 8) < A.rr_thr) {
+                                alpha *= A.inv_rr_p;
+                                if constexpr (HERO) {
+#pragma unroll
+                                    for (int i = 0; i < NM; ++i) mT[i] *= A.inv_rr_p;
+                                }
+                            } else {
+                                finish = true;
+                            }
                         }
                         if (!finish) {
                             const float kn = sqrtf(fmaxf(0.0f, 1.0f - (kox * kox + koy * koy) / (k * k)));
@@ -287,12 +455,27 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         }
         }   // live
         if (finish) {
-            float val = contrib * A.inv_spp_norm;
-            if (!isfinite(val)) {
-                ev |= 1u << EV_NONFINITE;
-                val = 0.0f;
+            if constexpr (HERO) {
+                // record of (sample, pixel, wavelength g + i G): (idx / G) nl + g + i G
+                const uint32_t G = nl >> 2;
+                const uint64_t rb = (idx / G) * nl + idx % G;
+#pragma unroll
+                for (int i = 0; i < NM; ++i) {
+                    float val = macc[i] * A.inv_spp_norm;
+                    if (!isfinite(val)) {
+                        ev |= 1u << EV_NONFINITE;
+                        val = 0.0f;
+                    }
+                    A.records[rb + (uint64_t)i * G] = val;
+                }
+            } else {
+                float val = contrib * A.inv_spp_norm;
+                if (!isfinite(val)) {
+                    ev |= 1u << EV_NONFINITE;
+                    val = 0.0f;
+                }
+                A.records[idx] = val;
             }
-            A.records[idx] = val;
             live = false;
         }
 #pragma unroll
@@ -336,19 +519,24 @@ __global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict_
                       r[12], r[13]);
 }
 
-template <bool DEFER>
+template <bool DEFER, bool HERO>
 static int grid_for(int device) {
     int ncu = 0, nb = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER>, 256, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER, HERO>, 256, 0) != hipSuccess)
+        return 0;
     return ncu * (nb > 0 ? nb : 1);
 }
 
-int trace_grid_size(int device, bool sur) { return sur ? grid_for<true>(device) : grid_for<false>(device); }
+int trace_grid_size(int device, bool sur, bool hero) {
+    if (hero) return grid_for<false, true>(device);
+    return sur ? grid_for<true, false>(device) : grid_for<false, false>(device);
+}
 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.bsdf_mode != 0) hipLaunchKernelGGL((trace_kernel<kLdsStack, true>), dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((trace_kernel<kLdsStack, false>), dim3(grid), dim3(256), 0, s, a);
+    if (a.hero) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (a.bsdf_mode != 0) hipLaunchKernelGGL((trace_kernel<kLdsStack, true, false>), dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,126 @@
+"""GPU parity of hero-wavelength paths (GR_TRACE_HERO) against the oracle's hero paths, through
+the C ABI.  Both sides draw the same Philox streams (path id ((s H + y) W + x) G + g for group
+g of G = n_lambda / 4, hero = member (source draw word 3) >> 30), so images are compared
+element by element at the plain path's bound, rel. L2 <= 1e-3.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2303_15762_amd._lib import GrError
+from workloads import scenes as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL_IMAGE = 1e-3
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2303_15762_amd import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def test_hero_parallel_mirror_closed_form(R):
+    wl = W.parallel_mirror()
+    R.load_workload(wl)
+    img, st = R.render_workload(wl, hero=True)
+    g = img.cpu().numpy().astype(np.float64)
+    assert st["paths"] == 16 * 16 * 4 * 2 and st["nonfinite"] == 0
+    sig = wl.sensor.sigma_m * 1e6
+    b0 = 2.0 * sig * sig
+    for w, lam in enumerate(wl.lambdas_um):
+        k = 2.0 * math.pi / lam
+        ref = 0.9 * (b0 + (1e4 / k) ** 2 / b0) / math.pi
+        np.testing.assert_allclose(g[w], ref, rtol=2e-5)
+
+
+def test_hero_terrain_small_ragged_matches_oracle(R):
+    """The mid workload's scene, samples, 8 wavelengths (2 rotation groups) and depth on a
+    41 x 29 sensor; per-path records are compared too."""
+    wl = W.mid_terrain(width=41, height=29, spp=16, n_lambda=8)
+    R.load_workload(wl)
+    img, st = R.render_workload(wl, hero=True, keep_paths=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost, op = oracle.render(wl, hero=True, keep_paths=True)
+    e = rel_l2(g, o)
+    print("hero terrain 41x29: rel L2", e, st, ost)
+    assert st["paths"] == 41 * 29 * 16 * 2
+    assert st["nonfinite"] == 0
+    assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    assert e <= RTOL_IMAGE
+    # records: [s, y, x, lambda] on the GPU, [s, pixel, lambda] in the oracle
+    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+                  keep_paths=True, hero=True)
+    rec = R.path_records(opts, 8).cpu().numpy().astype(np.float64).reshape(16, 41 * 29, 8)
+    er = rel_l2(rec, op)
+    print("hero terrain 41x29 records: rel L2", er)
+    assert er <= RTOL_IMAGE
+
+
+def test_hero_terrain_full_size_sampled_pixels(R):
+    """The mid workload at its full size with hero paths; the oracle computes sampled pixels.
+    The oracle is given the scene, sensor and sources rounded to the float32 values the library
+    receives: a hero path carries four estimates, so a single grazing path whose value moves by
+    the input rounding (one path at 1.4 %) weighs more in the image than with one wavelength
+    per path."""
+    wl = W.as_float32_inputs(W.mid_terrain())
+    R.load_workload(wl)
+    img, st = R.render_workload(wl, hero=True)
+    g = img.cpu().numpy().astype(np.float64)
+    assert st["paths"] == 512 * 512 * 16 * 2 and st["nonfinite"] == 0
+    rng = np.random.default_rng(4)
+    lit = np.argwhere(g.sum(0) > 0)
+    pick_lit = lit[rng.choice(len(lit), size=min(400, len(lit)), replace=False)]
+    pick_any = np.stack([rng.integers(0, 512, 200), rng.integers(0, 512, 200)], 1)
+    pix_yx = np.concatenate([pick_lit, pick_any])
+    pix = np.stack([pix_yx[:, 1], pix_yx[:, 0]], 1)
+    o, _ = oracle.render(wl, pixels=pix, hero=True)
+    e = rel_l2(g[:, pix_yx[:, 0], pix_yx[:, 1]], o)
+    print("hero terrain full: rel L2 on", len(pix), "pixels:", e, st)
+    assert e <= RTOL_IMAGE
+
+
+def test_hero_and_per_wavelength_images_agree_statistically(R):
+    """Both estimate the same image: per-wavelength totals of the full-size hero image and the
+    default image agree within the spread of per-sample totals."""
+    wl = W.mid_terrain()
+    R.load_workload(wl)
+    keep = dict(keep_paths=True)
+    _, _ = R.render_workload(wl, **keep)
+    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed, keep_paths=True)
+    a = R.path_records(o, 8).double().sum(dim=(1, 2)).cpu().numpy()        # [s, lambda]
+    _, _ = R.render_workload(wl, hero=True, **keep)
+    b = R.path_records(o, 8).double().sum(dim=(1, 2)).cpu().numpy()
+    s = a.shape[0]
+    se = np.sqrt(s * (a.var(0, ddof=1) + b.var(0, ddof=1)))
+    z = (b.sum(0) - a.sum(0)) / se
+    print("hero vs default totals, z per wavelength:", np.round(z, 2))
+    assert np.all(np.abs(z) < 5.0)
+
+
+def test_hero_rejected_where_unsupported(R):
+    wl = W.mid_terrain(width=8, height=8, spp=1, n_lambda=3)
+    R.load_workload(wl)
+    with pytest.raises(GrError):
+        R.render_workload(wl, hero=True)                   # 3 wavelengths: not groups of 4
+    wl = W.mid_terrain(width=8, height=8, spp=1, n_lambda=4)
+    R.load_workload(wl)
+    o = R.opts(spp_count=1, max_depth=2, seed=1, hero=True, wavefront=True)
+    with pytest.raises(GrError):
+        R.trace(wl.lambdas_um, o)
+    img, st = R.render_workload(wl, hero=True)             # one group of 4: fine
+    assert st["paths"] == 8 * 8

@@ -3,7 +3,8 @@
 sensor, 64 samples, 16 wavelengths, depth <= 6 with Russian roulette, three partially coherent
 emitters.  Its BVH is 15 levels deep, so the traversal stack overflows the LDS part into the
 workspace.  The GPU image is compared with the FP64 oracle on sampled pixels, which the oracle
-computes one by one: rel. L2 <= 1e-3 with the closed-form p_w and <= 1e-2 with the learned p_w.
+computes one by one: rel. L2 <= 1e-3 with the closed-form p_w (one wavelength per path, and
+hero-wavelength paths) and <= 1e-2 with the learned p_w.
 """
 
 import time
@@ -57,6 +58,21 @@ def test_large_full_size_sampled_pixels(large):
     o, ost = oracle.render(wl, pixels=pix, n_threads=0)
     e = rel_l2(g[:, pix_yx[:, 0], pix_yx[:, 1]], o)
     print("large plain: rel L2 on", len(pix), "pixels:", e, ost)
+    assert e <= 1e-3
+
+
+def test_large_hero_sampled_pixels(large):
+    """Hero-wavelength paths: 16 wavelengths in 4 rotation groups, a quarter of the paths."""
+    R, wl, torch = large
+    img, st = R.render_workload(wl, hero=True)
+    g = img.cpu().numpy()
+    print("large hero:", st)
+    assert st["paths"] == 1920 * 1080 * 64 * 4
+    assert st["nonfinite"] == 0
+    pix_yx, pix = _pixels(g, 800, 200, 2)
+    o, _ = oracle.render(wl, pixels=pix, n_threads=0, hero=True)
+    e = rel_l2(g[:, pix_yx[:, 0], pix_yx[:, 1]], o)
+    print("large hero: rel L2 on", len(pix), "pixels:", e)
     assert e <= 1e-3
 
 
