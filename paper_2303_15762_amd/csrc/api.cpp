@@ -448,6 +448,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.scene.tnorm = static_cast<const float4*>(c->d_tnorm);
     a.scene.mats = static_cast<const grw::DMat*>(c->d_mats);
     a.scene.n_tris = c->n_tris;
+    a.scene.node_bytes = (uint32_t)(c->n_nodes * 128);
     for (int i = 0; i < 3; ++i) {
         a.scene.lo[i] = c->lo[i] - 1e-3f;
         a.scene.hi[i] = c->hi[i] + 1e-3f;

@@ -20,6 +20,7 @@ struct SceneDev {
     const DMat* mats;
     int64_t n_tris;
     float lo[3], hi[3];      // bounds of all vertices widened by 1 mm
+    uint32_t node_bytes;     // size of the node array (bounds of its buffer loads)
 };
 
 struct SensorDev {

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    int* stk = &lds_stack[wv][0][lane];
+    lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
     // this wave's slice of the traversal-stack overflow (uniform; the lane adds its id)
     const size_t ostride = (size_t)gridDim.x * 256;
     int* ovf = A.ovf ? A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     float kox, koy, wgt;
                     int comp = 0;
                     if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
-                                    reinterpret_cast<float*>(stk), STACK, HERO ? &comp : nullptr)) {
+                                    (float*)(int*)stk, STACK, HERO ? &comp : nullptr)) {
                         ev |= 1u << EV_EVANESCENT;
                         finish = true;
                     } else {

@@ -12,6 +12,10 @@
 
 namespace grw {
 
+// A pointer into LDS typed as such, so that LDS accesses stay LDS instructions (a generic
+// pointer lets the compiler merge an LDS and a global access into one flat access).
+typedef __attribute__((address_space(3))) int lds_int;
+
 // Path positions are kept in double precision: at metre-scale coordinates one float ulp is
 // 0.06 um, and steep shading-normal gradients turn such offsets into direction errors that
 // grow along the path.  A ray carries its origin as the nearest float o plus the float
@@ -157,7 +161,7 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // and triangle code thus run on fuller waves than when every iteration does either one.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
-                                        bool any, int skip, int* stk, int cap, int* ovf, size_t ostride,
+                                        bool any, int skip, lds_int* stk, int cap, int* ovf, size_t ostride,
                                         uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv) {
     constexpr int kDone = 0x7FFFFFFF;   // nothing left to visit (never a node index)
     int best = -1;
@@ -166,43 +170,74 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
     int sp = 0;
     int cur = 0;    // next inner node (>= 0) or leaf (< 0) to visit, or kDone
     int leaf = 0;   // a parked leaf (< 0), or 0
+    // the LDS entry is always read (in range) and replaced by the overflow entry when the
+    // stack is that deep, so the common pop stays an LDS read
     auto pop = [&]() -> int {
         if (sp == 0) return kDone;
         --sp;
-        return sp < cap ? stk[sp * 64] : ovf[(size_t)(sp - cap) * ostride + __lane_id()];
+        int v = stk[min(sp, cap - 1) * 64];
+        if (sp >= cap) v = ovf[(size_t)(sp - cap) * ostride + __lane_id()];
+        return v;
     };
     // slab distances as (lo - o) / d = lo * inv - o * inv: one FMA per plane (the node boxes
     // are widened by more than the extra rounding of o * inv)
     const float ix = r.inv.x, iy = r.inv.y, iz = r.inv.z;
     const float oix = r.o.x * ix, oiy = r.o.y * iy, oiz = r.o.z * iz;
+    // The ray's direction signs fix which plane of each slab it meets first: the near planes
+    // are the low ones along positive directions.  Each lane fetches its near and far planes by
+    // byte offset within the 128-byte node (lo x at 0, hi x at 16, lo y 32, hi y 48, lo z 64,
+    // hi z 80, children 96), so the slab test needs no min/max per plane.  Buffer loads take
+    // the per-lane offsets (reads past the node array return zero instead of faulting).
+    const __amdgpu_buffer_rsrc_t nb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float4*>(S.nodes), (short)0, (int)S.node_bytes, 0x00020000);
+    const int sx = ix < 0.0f ? 16 : 0, sy = iy < 0.0f ? 48 : 32, sz = iz < 0.0f ? 80 : 64;
+    typedef float v4f_t __attribute__((ext_vector_type(4)));
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
     while (cur != kDone) {
         while (cur >= 0 && cur != kDone) {
             ++n_nodes;
-            const float4* N = S.nodes + (size_t)cur * 8;
-            const float4 lx = N[0], hx = N[1], ly = N[2], hy = N[3], lz = N[4], hz = N[5];
-            const int4 ch = *reinterpret_cast<const int4*>(N + 6);
-            const float lxa[4] = {lx.x, lx.y, lx.z, lx.w}, hxa[4] = {hx.x, hx.y, hx.z, hx.w};
-            const float lya[4] = {ly.x, ly.y, ly.z, ly.w}, hya[4] = {hy.x, hy.y, hy.z, hy.w};
-            const float lza[4] = {lz.x, lz.y, lz.z, lz.w}, hza[4] = {hz.x, hz.y, hz.z, hz.w};
+            const int base = cur << 7;
+            const int onx = base + sx, ony = base + sy, onz = base + sz;
+            const v4f_t nx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx, 0, 0);
+            const v4f_t fx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx ^ 16, 0, 0);
+            const v4f_t ny = __builtin_amdgcn_raw_buffer_load_b128(nb, ony, 0, 0);
+            const v4f_t fy = __builtin_amdgcn_raw_buffer_load_b128(nb, ony ^ 16, 0, 0);
+            const v4f_t nz = __builtin_amdgcn_raw_buffer_load_b128(nb, onz, 0, 0);
+            const v4f_t fz = __builtin_amdgcn_raw_buffer_load_b128(nb, onz ^ 16, 0, 0);
+            const v4i_t chv = __builtin_bit_cast(v4i_t, __builtin_amdgcn_raw_buffer_load_b128(nb, base + 96, 0, 0));
+            const int4 ch = make_int4(chv.x, chv.y, chv.z, chv.w);
+            const float lxa[4] = {nx.x, nx.y, nx.z, nx.w}, hxa[4] = {fx.x, fx.y, fx.z, fx.w};
+            const float lya[4] = {ny.x, ny.y, ny.z, ny.w}, hya[4] = {fy.x, fy.y, fy.z, fy.w};
+            const float lza[4] = {nz.x, nz.y, nz.z, nz.w}, hza[4] = {fz.x, fz.y, fz.z, fz.w};
             // key = entry distance with the slot in its two low bits (distances are positive, so
             // their bit patterns order like the values); a miss keys as 0xFFFFFFFF.  Empty slots
-            // hold boxes at +inf and always miss.
+            // hold boxes at +inf and always miss.  The interval ends are taken as signed integers:
+            // the entry is at least tmin > 0, and positive floats order like their bit patterns
+            // while any negative float is a negative integer, so the hit decision and the entry
+            // distance equal the float ones (no NaN arises: the inverse direction is finite).
             uint32_t key[4];
+            int chd[4] = {ch.x, ch.y, ch.z, ch.w};
+            const int itmin = __float_as_int(tmin), ibest = __float_as_int(best_t);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
+                // lxa..: near planes, hxa..: far planes (see above)
                 const float t0x = fmaf(lxa[i], ix, -oix), t1x = fmaf(hxa[i], ix, -oix);
                 const float t0y = fmaf(lya[i], iy, -oiy), t1y = fmaf(hya[i], iy, -oiy);
                 const float t0z = fmaf(lza[i], iz, -oiz), t1z = fmaf(hza[i], iz, -oiz);
-                const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
-                const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), best_t));
-                key[i] = tn <= tf ? ((__float_as_uint(tn) & ~3u) | (uint32_t)i) : 0xFFFFFFFFu;
+                const int tn = max(max(__float_as_int(t0x), __float_as_int(t0y)), max(__float_as_int(t0z), itmin));
+                const int tf = min(min(__float_as_int(t1x), __float_as_int(t1y)), min(__float_as_int(t1z), ibest));
+                key[i] = tn <= tf ? (((uint32_t)tn & ~3u) | (uint32_t)i) : 0xFFFFFFFFu;
             }
-            // ascending sorting network on the keys
-#define GRW_CSWAP(i, j)                               \
-    {                                                 \
-        const uint32_t lo_ = min(key[i], key[j]);     \
-        key[j] = max(key[i], key[j]);                 \
-        key[i] = lo_;                                 \
+            // ascending sorting network on the keys, the child codes carried along
+#define GRW_CSWAP(i, j)                                 \
+    {                                                   \
+        const bool sw_ = key[j] < key[i];               \
+        const uint32_t lo_ = sw_ ? key[j] : key[i];     \
+        key[j] = sw_ ? key[i] : key[j];                 \
+        key[i] = lo_;                                   \
+        const int cl_ = sw_ ? chd[j] : chd[i];          \
+        chd[j] = sw_ ? chd[i] : chd[j];                 \
+        chd[i] = cl_;                                   \
     }
             GRW_CSWAP(0, 1)
             GRW_CSWAP(2, 3)
@@ -214,13 +249,13 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
 #pragma unroll
             for (int i = 3; i >= 1; --i) {
                 if (key[i] != 0xFFFFFFFFu) {
-                    const int v = child_of(ch, key[i]);
+                    const int v = chd[i];
                     if (sp < cap) stk[sp * 64] = v;
                     else ovf[(size_t)(sp - cap) * ostride + __lane_id()] = v;
                     ++sp;
                 }
             }
-            cur = key[0] != 0xFFFFFFFFu ? child_of(ch, key[0]) : pop();
+            cur = key[0] != 0xFFFFFFFFu ? chd[0] : pop();
             if (cur < 0 && leaf == 0) {   // park the leaf and keep descending
                 leaf = cur;
                 cur = pop();
