@@ -93,12 +93,21 @@ __device__ __forceinline__ float gauss2(float x, float y, float a, float b, floa
 // about 14 terms there, far fewer for large n.
 __device__ __forceinline__ float bessel_jn_series(int n, float x) {
     const float hx = 0.5f * x;
+    // J_n(x) < (x/2)^n / n!: an order below 1e-10 weighs < 1e-20, far under one float ulp of
+    // any sum of weights or lobe values it enters
     float p = 1.0f;
-    for (int i = 1; i <= n; ++i) {
-        p *= hx * __builtin_amdgcn_rcpf((float)i);
-        // J_n(x) < (x/2)^n / n!: an order below 1e-10 weighs < 1e-20, far under one float ulp
-        // of any sum of weights or lobe values it enters
+    if (n <= 4) {
+        for (int i = 1; i <= n; ++i) p *= hx * __builtin_amdgcn_rcpf((float)i);
         if (p < 1e-10f) return 0.0f;
+    } else {
+        // (x/2)^n / n! = exp(n log(x/2) - log n!), log n! by Stirling's series (its first
+        // omitted term, 1 / (1260 n^5), is below 3e-7 for n >= 5)
+        const float nf = (float)n;
+        const float rn = __builtin_amdgcn_rcpf(nf);
+        const float lf = (nf + 0.5f) * __logf(nf) - nf + 0.91893853f + rn * (1.0f / 12.0f - rn * rn * (1.0f / 360.0f));
+        const float e = nf * __logf(hx) - lf;
+        if (!(e > -23.0258509f)) return 0.0f;   // log(1e-10); also x = 0
+        p = __expf(e);
     }
     const float q = -hx * hx;
     float t = 1.0f, s = 1.0f, kf = 0.0f, nk = (float)n;
@@ -297,6 +306,7 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         return 0;
     }
     const float k2 = k * k;
+    const float ik2 = 1.0f / k2;
     if (m.kind == MAT_GRATING) {
         // grating vector = frame x axis; propagating orders: (kix - jK)^2 + kiy^2 < k^2.
         // cache: this lane's idle scratch (stride 64 floats) holding the order weights
@@ -317,7 +327,7 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
             bool found = false;
             for (int j = jlo; j <= jhi; ++j) {
                 const float ox = kix - (float)j * K;
-                const float no = (ox * ox + kiy * kiy) / k2;
+                const float no = (ox * ox + kiy * kiy) * ik2;
                 if (no >= 1.0f) continue;
                 float w;
                 if (pass == 1 && cached) {
@@ -386,6 +396,7 @@ __device__ inline void grating_weights(const DMat& m, float k, float kix, float 
     W = 0.0f;
     w0 = 0.0f;
     const float k2 = k * k;
+    const float ik2 = 1.0f / k2;
     const float K = kTwoPiF / m.L;
     const float rem = k2 - kiy * kiy;
     if (rem <= 0.0f) return;
@@ -394,7 +405,7 @@ __device__ inline void grating_weights(const DMat& m, float k, float kix, float 
     const int jhi = min((int)ceilf((kix + r) / K) + 1, jlo + 4096);
     for (int j = jlo; j <= jhi; ++j) {
         const float ox = kix - (float)j * K;
-        const float no = (ox * ox + kiy * kiy) / k2;
+        const float no = (ox * ox + kiy * kiy) * ik2;
         if (no >= 1.0f) continue;
         const float bj = bessel_jn(abs(j), k * m.h * (ci + sqrtf(1.0f - no)));
         W += bj * bj;
