@@ -228,34 +228,50 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 const int tf = min(min(__float_as_int(t1x), __float_as_int(t1y)), min(__float_as_int(t1z), ibest));
                 key[i] = tn <= tf ? (((uint32_t)tn & ~3u) | (uint32_t)i) : 0xFFFFFFFFu;
             }
-            // ascending sorting network on the keys, the child codes carried along
-#define GRW_CSWAP(i, j)                                 \
-    {                                                   \
-        const bool sw_ = key[j] < key[i];               \
-        const uint32_t lo_ = sw_ ? key[j] : key[i];     \
-        key[j] = sw_ ? key[i] : key[j];                 \
-        key[i] = lo_;                                   \
-        const int cl_ = sw_ ? chd[j] : chd[i];          \
-        chd[j] = sw_ ? chd[i] : chd[j];                 \
-        chd[i] = cl_;                                   \
-    }
-            GRW_CSWAP(0, 1)
-            GRW_CSWAP(2, 3)
-            GRW_CSWAP(0, 2)
-            GRW_CSWAP(1, 3)
-            GRW_CSWAP(1, 2)
-#undef GRW_CSWAP
-            // push the farther hits (farthest first), descend into the nearest
+            auto push = [&](int v) {
+                if (sp < cap) stk[sp * 64] = v;
+                else ovf[(size_t)(sp - cap) * ostride + __lane_id()] = v;
+                ++sp;
+            };
+            if (any) {
+                // any hit ends the query, so the order of the visits only changes the work:
+                // descend into the lowest hit slot and push the other hits, unsorted
+                bool have = false;
+                int nxt = 0;
 #pragma unroll
-            for (int i = 3; i >= 1; --i) {
-                if (key[i] != 0xFFFFFFFFu) {
-                    const int v = chd[i];
-                    if (sp < cap) stk[sp * 64] = v;
-                    else ovf[(size_t)(sp - cap) * ostride + __lane_id()] = v;
-                    ++sp;
+                for (int i = 3; i >= 0; --i) {
+                    if (key[i] != 0xFFFFFFFFu) {
+                        if (have) push(nxt);
+                        nxt = chd[i];
+                        have = true;
+                    }
                 }
+                cur = have ? nxt : pop();
+            } else {
+                // ascending sorting network on the keys, the child codes carried along
+#define GRW_CSWAP(i, j)                                 \
+        {                                                   \
+            const bool sw_ = key[j] < key[i];               \
+            const uint32_t lo_ = sw_ ? key[j] : key[i];     \
+            key[j] = sw_ ? key[i] : key[j];                 \
+            key[i] = lo_;                                   \
+            const int cl_ = sw_ ? chd[j] : chd[i];          \
+            chd[j] = sw_ ? chd[i] : chd[j];                 \
+            chd[i] = cl_;                                   \
+        }
+                GRW_CSWAP(0, 1)
+                GRW_CSWAP(2, 3)
+                GRW_CSWAP(0, 2)
+                GRW_CSWAP(1, 3)
+                GRW_CSWAP(1, 2)
+#undef GRW_CSWAP
+                // push the farther hits (farthest first), descend into the nearest
+#pragma unroll
+                for (int i = 3; i >= 1; --i) {
+                    if (key[i] != 0xFFFFFFFFu) push(chd[i]);
+                }
+                cur = key[0] != 0xFFFFFFFFu ? chd[0] : pop();
             }
-            cur = key[0] != 0xFFFFFFFFu ? chd[0] : pop();
             if (cur < 0 && leaf == 0) {   // park the leaf and keep descending
                 leaf = cur;
                 cur = pop();
