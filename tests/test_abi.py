@@ -89,6 +89,20 @@ def test_trace_rejects_before_device_use(ctx):
     bad = (C.c_float * 1)(-1.0)
     o.bsdf_mode = 0
     assert lib.gr_trace(h, bad, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
+    # flags: unknown bits, and hero-wavelength paths outside what they support
+    o.flags = 16
+    assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
+    o.flags = L.GR_TRACE_HERO
+    assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
+    assert b"n_lambda" in lib.gr_last_error(h)
+    lam4 = (C.c_float * 4)(0.45, 0.5, 0.55, 0.6)
+    o.flags = L.GR_TRACE_HERO | L.GR_TRACE_WAVEFRONT
+    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
+    o.flags = L.GR_TRACE_HERO
+    o.bsdf_mode = 1
+    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
+    o.bsdf_mode = 0
+    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
 
 
 def test_scene_validation(ctx):
