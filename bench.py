@@ -85,18 +85,23 @@ def cpu_baseline(wl, target_s=15.0):
     rng = np.random.default_rng(123)
     threads = os.cpu_count() or 1
 
-    def run(npx):
+    def run(npx, nt):
         pix = np.stack([rng.integers(0, wl.sensor.width, npx), rng.integers(0, wl.sensor.height, npx)], 1)
         t0 = time.perf_counter()
-        _, st = oracle.render(wl, osc, pixels=pix, n_threads=threads)
+        _, st = oracle.render(wl, osc, pixels=pix, n_threads=nt)
         return time.perf_counter() - t0, st["segments"]
 
-    dt, seg = run(64)
+    dt, seg = run(64, threads)
     npx = int(max(64, min(wl.sensor.width * wl.sensor.height, 64 * target_s / max(dt, 1e-3))))
-    dt, seg = run(npx)
+    dt, seg = run(npx, threads)
+    # one thread on a smaller sample (about 3 s)
+    npx1 = max(16, int(npx * 3.0 / max(target_s * threads, 1e-3)))
+    dt1, seg1 = run(npx1, 1)
     return {"value": seg / dt / 1e6, "unit": "Mpath-segments/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": seg1 / dt1 / 1e6,
             "sample": f"{npx} random pixels x {wl.spp} samples x {len(wl.lambdas_um)} wavelengths of the "
-                      f"same workload ({seg} segments, {dt:.1f} s, FP64 C++ oracle, {threads} threads)"}
+                      f"same workload ({seg} segments, {dt:.1f} s, FP64 C++ oracle, {threads} threads); "
+                      f"single thread: {npx1} pixels ({seg1} segments, {dt1:.1f} s)"}
 
 
 def surrogate_leg(R, wl, o_plain, img, st_plain, args):
@@ -181,6 +186,39 @@ def hero_leg(R, wl, ms_plain, args):
             "frame_speedup_vs_one_wavelength_paths": round(ms_plain / ms, 3)}
 
 
+# Coherent measurement: vector operations of one (sample, slit node) evaluation in the FP64
+# mode, the way the kernel writes them: distance (1 FMA + a square root of ~6), phase (1),
+# amplitude (4 multiplies, a division of ~8, a square root of ~6), sincos with its range
+# reduction (~40), the large-argument correction (a division of ~8), complex product and
+# accumulation (8).  FP64 vector operations issue at the FP32 rate on this chip (78.6 TFLOP/s
+# counts an FMA as two).
+COHERENT_NODE_OPS = 85
+
+
+def coherent_leg(R, args):
+    """The precision-stress measurement (double slit, z = 1 m, 0.55 um, 1024 x 64 sensor, 64
+    samples, 16 Gauss-Legendre nodes per slit) in its three phase modes."""
+    from workloads import coherent_case
+    case = coherent_case("slits", z_m=1.0, lambda_um=0.55)
+    nodes = 16
+    out = {"workload": "double slit b = 10 um, d = 50 um, z = 1 m, 0.55 um, 1024x64 sensor, 64 spp, "
+                       "2 x 16 Gauss-Legendre nodes"}
+    evals = case.width * case.height * case.spp * 2 * nodes
+    for name, mode in (("fp32", 0), ("fp64", 1), ("two_float", 2)):
+        R.coherent(case, phase_mode=mode, nodes_per_slit=nodes)
+        ms = []
+        for _ in range(max(1, args.steps)):
+            _, t = R.coherent(case, phase_mode=mode, nodes_per_slit=nodes, timing=True)
+            ms.append(t)
+        m = float(np.median(ms))
+        out[name] = {"ms": round(m, 3), "node_evals_per_s_G": round(evals / (m * 1e-3) / 1e9, 2)}
+    ach = evals * COHERENT_NODE_OPS / (out["fp64"]["ms"] * 1e-3) / 1e9
+    out["fp64"]["roofline"] = {"bound": "alu", "achieved": round(ach, 1), "peak": round(VALU_PEAK_GOPS, 1),
+                               "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4),
+                               "ops_per_node_eval": COHERENT_NODE_OPS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +229,8 @@ def main():
                     help="skip the learned-p_w leg (training takes a few seconds)")
     ap.add_argument("--no-hero", dest="hero", action="store_false",
                     help="skip the hero-wavelength leg")
+    ap.add_argument("--no-coherent", dest="coherent", action="store_false",
+                    help="skip the coherent-measurement leg")
     ap.add_argument("--workload", choices=["mid", "large"], default="mid",
                     help="mid: the 65,536-triangle terrain (the reported line); large: the "
                          "4,194,300-triangle instanced scene at 1920x1080, 64 spp, 16 wavelengths")
@@ -267,7 +307,8 @@ def main():
                 "unit": "Gop/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": traffic,
                 "kernel": "trace_kernel", "kernel_ms": round(k_ms, 3), "algorithmic_ops": int(aops),
                 "requested_bytes": int(abytes),
-                "requested_gbs": round(abytes / (k_ms * 1e-3) / 1e9, 1), "hbm_peak_gbs": HBM_PEAK_GBS}
+                "requested_gbs": round(abytes / (k_ms * 1e-3) / 1e9, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
+                "traffic_bytes_per_segment": (round(traffic / segments, 1) if traffic else None)}
 
     out = {
         "metric": "Mpath-segments/s, plain vs NN-surrogate BSDF, at <=1% rel. L2 image error",
@@ -290,6 +331,8 @@ def main():
     }
     if args.hero and len(wl.lambdas_um) % 4 == 0:
         out["hero"] = hero_leg(R, wl, ms_step, args)
+    if args.coherent and args.workload == "mid":
+        out["coherent"] = coherent_leg(R, args)
     if args.surrogate:
         out["surrogate"] = surrogate_leg(R, wl, o, img, st, args)
     if not args.no_cpu:
