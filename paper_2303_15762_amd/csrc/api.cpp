@@ -100,6 +100,9 @@ int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_
 // numbers are 32-bit: 2^26 paths x 64 interactions at most).  Each launch ends in a tail where
 // waves wait for their slowest path, so launches are made as large as the memory allows.
 constexpr uint64_t kSurChunk = 1ull << 26;
+// ... and at most this many (path, interaction) slots per launch (16 GB of queued queries),
+// which bounds deep paths.
+constexpr uint64_t kSurSlots = 1ull << 29;
 // The wavefront kernels keep per-path state of a launch of at most this many paths.
 constexpr uint64_t kWfChunk = 1ull << 23;
 
@@ -386,7 +389,8 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
-    L.chunk = std::min<uint64_t>(n, wavefront_of(o) ? kWfChunk : kSurChunk);
+    const uint64_t sur_chunk = std::min<uint64_t>(kSurChunk, kSurSlots / (uint64_t)std::max(o->max_depth, 1));
+    L.chunk = std::min<uint64_t>(n, wavefront_of(o) ? kWfChunk : sur_chunk);
     L.wf_bytes = wavefront_of(o) ? wf_bytes(L.chunk) : 0;
     L.queue = L.wf + L.wf_bytes;
     L.dense = L.queue;
