@@ -102,6 +102,31 @@ def test_surrogate_trace_deterministic(trained):
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
+def test_surrogate_deep_paths_in_bounded_launches(trained):
+    """Up to 64 interactions per path: a launch holds at most 2^29 (path, interaction) query
+    slots, i.e. 2^23 paths here, so the 10.5M-path frame runs in two launches.  The image
+    equals the sum of two renders over sample ranges that each fit one launch, and matches
+    the oracle on sampled pixels."""
+    import dataclasses
+    R, S, p, hist, torch = trained
+    wl = dataclasses.replace(W.mid_terrain(width=512, height=512, spp=5, n_lambda=8), max_depth=64)
+    R.load_workload(wl)
+    img, st = R.render_workload(wl, bsdf_mode=1)
+    assert st["paths"] == 512 * 512 * 5 * 8 and st["nonfinite"] == 0 and st["surrogate_evals"] > 0
+    a, _ = R.render_workload(wl, bsdf_mode=1, spp_begin=0, spp_count=3)
+    b, _ = R.render_workload(wl, bsdf_mode=1, spp_begin=3, spp_count=2)
+    g = img.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose((a + b).cpu().numpy(), g, rtol=1e-5, atol=1e-9 * np.abs(g).max())
+    rng = np.random.default_rng(21)
+    lit = np.argwhere(g.sum(0) > 0)
+    pix_yx = lit[rng.choice(len(lit), size=min(300, len(lit)), replace=False)]
+    pix = np.stack([pix_yx[:, 1], pix_yx[:, 0]], 1)
+    o, ost = oracle.render(wl, pixels=pix)
+    e = rel_l2(g[:, pix_yx[:, 0], pix_yx[:, 1]], o)
+    print("deep surrogate paths: rel L2 on", len(pix), "pixels:", e, st)
+    assert e <= 1e-2
+
+
 def test_fp8_surrogate_against_bf16_and_oracle(trained):
     """The same trained network with E4M3 operands: held-out p_w and the terrain image, both
     against the FP64 closed form / oracle, next to the BF16 operands (the precision comparison
