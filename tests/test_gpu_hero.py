@@ -71,6 +71,28 @@ def test_hero_terrain_small_ragged_matches_oracle(R):
     assert er <= RTOL_IMAGE
 
 
+def test_hero_two_sources_roulette_depth6(R):
+    """Hero paths with a Gaussian-Schell and a plane-wave source (emitter-sampling ratios q
+    differ per member for the first and are 1 for the second), Russian roulette and up to 6
+    interactions, on float32-rounded oracle inputs."""
+    import dataclasses
+    wl = W.mid_terrain(width=41, height=29, spp=8, n_lambda=8)
+    th = math.radians(40.0)
+    d = np.array([0.3 * math.sin(th), math.sin(th), -math.cos(th)])
+    pw = W.Source(W.PLANE_WAVE, dir=d / np.linalg.norm(d), power=0.7)
+    wl = W.as_float32_inputs(dataclasses.replace(wl, sources=list(wl.sources) + [pw], max_depth=6,
+                                                 rr_enable=True, rr_p=0.8))
+    R.load_workload(wl)
+    img, st = R.render_workload(wl, hero=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, hero=True)
+    e = rel_l2(g, o)
+    print("hero two sources, RR, depth 6: rel L2", e, st, ost)
+    assert o.sum() > 0 and st["nonfinite"] == 0
+    assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    assert e <= RTOL_IMAGE
+
+
 def test_hero_terrain_full_size_sampled_pixels(R):
     """The mid workload at its full size with hero paths; the oracle computes sampled pixels.
     The oracle is given the scene, sensor and sources rounded to the float32 values the library
