@@ -296,11 +296,13 @@ __device__ __noinline__ int poisson_inverse(double g, float u0) {
 //            weight = reflectance; an evanescent draw ends the path
 // Returns 0 on success, 1 when the path ends evanescently.  comp (optional) receives the
 // sampled component: the grating order, the rough surface's Poisson term (0 = the specular
-// delta), 0 for a smooth surface.
+// delta), 0 for a smooth surface; pick_p (optional) the probability of a grating's sampled
+// order, w_j / W.
 // ------------------------------------------------------------------------------------------
 __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, float ci,
                                   float u0, float u1, float u2, float& kox, float& koy,
-                                  float& weight, float* cache, int cache_n, int* comp = nullptr) {
+                                  float& weight, float* cache, int cache_n, int* comp = nullptr,
+                                  float* pick_p = nullptr) {
     if (comp) *comp = 0;
     if (m.kind == MAT_SMOOTH) {
         kox = kix;
@@ -323,7 +325,7 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         const bool cached = jhi - jlo < cache_n;
         // pass 0 sums the weights W, pass 1 inverts the cumulative sum at u0 W (one Bessel
         // evaluation site for both)
-        float W = 0.0f, c = 0.0f, target = 0.0f;
+        float W = 0.0f, c = 0.0f, target = 0.0f, wp = 0.0f;
         int pick = jhi, last = jlo;
 #pragma nounroll
         for (int pass = 0; pass < 2; ++pass) {
@@ -345,6 +347,7 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
                 } else {
                     c += w;
                     last = j;
+                    wp = w;
                     if (target < c) {
                         pick = j;
                         found = true;
@@ -363,6 +366,7 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         koy = kiy;
         weight = m.refl * W;
         if (comp) *comp = pick;
+        if (pick_p) *pick_p = wp / W;
         return 0;
     }
     // rough: Poisson term by inversion of the CDF in double precision
@@ -430,10 +434,14 @@ __device__ inline float rough_lobe_density(float k, float ci, float h, float L, 
     const float lp0 = log_poisson(nlo, g, logf(g));
     float w = 1.0f;   // Poisson(n; g) / Poisson(nlo; g)
     float s = 0.0f;
+    float nf = (float)nlo;
+    float rn = __builtin_amdgcn_rcpf(nf);   // 1 / n, carried to the next term
     for (int n = nlo; n <= nhi; ++n) {
-        const float rn = __builtin_amdgcn_rcpf((float)n);
+        nf += 1.0f;
+        const float rn1 = __builtin_amdgcn_rcpf(nf);
         s += w * __expf(lp0 - A * rn) * rn;
-        w *= g * __builtin_amdgcn_rcpf((float)(n + 1));
+        w *= g * rn1;
+        rn = rn1;
     }
     return s * k * k * L * L * (1.0f / (4.0f * kPiF));
 }

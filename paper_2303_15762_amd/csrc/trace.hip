@@ -16,15 +16,22 @@
 
 namespace grw {
 
+// Member i of a per-member register array.  Loops over the members that call a large function
+// stay rolled, so that the kernel holds one copy of it; a chain of selects keeps the arrays in
+// registers there (an indexed access would move them to scratch memory).
+__device__ __forceinline__ float pick4(const float (&a)[4], int i) {
+    return i == 0 ? a[0] : i == 1 ? a[1] : i == 2 ? a[2] : a[3];
+}
+
 // Hero-wavelength continuation: the hero (member hs, wavenumber kh) sampled (kox, koy) with
-// weight wgt through component comp from the incident (kix, kiy); every member's value ratio
-// f / p_h multiplies T and its density ratio p / p_h multiplies R.  A common factor of all T
-// and R leaves the balance-heuristic estimates unchanged, so R is renormalised to max 1 (and
-// the specular ratio exp(g_h - g_c) is formed relative to the largest member) to keep both in
-// FP32 range.
+// weight wgt through component comp (a grating order with probability ph) from the incident
+// (kix, kiy); every member's value ratio f / p_h multiplies T and its density ratio p / p_h
+// multiplies R.  A common factor of all T and R leaves the balance-heuristic estimates
+// unchanged, so R is renormalised to max 1 (and the specular ratio exp(g_h - g_c) is formed
+// relative to the largest member) to keep both in FP32 range.
 __device__ inline void hero_continuation(const DMat& m, float kh, const float (&mk)[4], int hs, float kix,
                                          float kiy, float ci, float kox, float koy, float wgt, int comp,
-                                         float (&T)[4], float (&R)[4]) {
+                                         float ph, float (&T)[4], float (&R)[4]) {
     const float ux = kix / kh, uy = kiy / kh;
     float rf[4], rp[4];
 #pragma unroll
@@ -39,17 +46,21 @@ __device__ inline void hero_continuation(const DMat& m, float kh, const float (&
             rp[i] = 1.0f;
         }
     } else if (m.kind == MAT_GRATING) {
-        if (comp == 0) {
-            float Wh, w0h;
-            grating_weights(m, kh, kix, kiy, ci, Wh, w0h);
-            const float ph = w0h / Wh;
-#pragma unroll
+        if (comp == 0) {   // ph: the hero's probability of order 0
+#pragma nounroll
             for (int i = 0; i < 4; ++i) {
                 if (i == hs) continue;
+                const float ki = pick4(mk, i);
                 float Wc, w0c;
-                grating_weights(m, mk[i], mk[i] * ux, mk[i] * uy, ci, Wc, w0c);
-                rf[i] = m.refl * w0c / ph;
-                rp[i] = (Wc > 0.0f ? w0c / Wc : 0.0f) / ph;
+                grating_weights(m, ki, ki * ux, ki * uy, ci, Wc, w0c);
+                const float f = m.refl * w0c / ph, p = (Wc > 0.0f ? w0c / Wc : 0.0f) / ph;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j == i) {
+                        rf[j] = f;
+                        rp[j] = p;
+                    }
+                }
             }
         }
     } else if (comp == 0) {
@@ -69,13 +80,22 @@ __device__ inline void hero_continuation(const DMat& m, float kh, const float (&
         wgt *= rp[hs];   // the hero's share of the common factor exp(-mx)
     } else {
         const float du2 = ((kox - kix) * (kox - kix) + (koy - kiy) * (koy - kiy)) / (kh * kh);
-        const float dh = rough_lobe_density(kh, ci, m.h, m.L, du2);
+        float dn[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // lobe densities; mk[hs] is kh
+#pragma nounroll
+        for (int i = 0; i < 4; ++i) {
+            const float di = rough_lobe_density(pick4(mk, i), ci, m.h, m.L, du2);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j == i) dn[j] = di;
+            }
+        }
+        const float dh = pick4(dn, hs);
         if (dh > 0.0f) {
             const float idh = 1.0f / dh;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (i == hs) continue;
-                rp[i] = rough_lobe_density(mk[i], ci, m.h, m.L, du2) * idh;
+                rp[i] = dn[i] * idh;
                 rf[i] = m.refl * rp[i];
             }
         }
@@ -352,13 +372,15 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         ray_setup(sray, P, -1.0f * om);
                         float tm = tmax_s, su, sv;
                         const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, su, sv);
-                        if (HERO && occ < 0) {
+                        if (occ >= 0) {
+                            // occluded
+                        } else if constexpr (HERO) {
                             // members: emitter-sampling density of om relative to the hero's
                             // (Gaussian angular spectrum N(k u_t; 0, rc^-2 I) k^2), then the
                             // balance-heuristic estimate of each
-                            float q[NM], den = 0.0f;
+                            float q[4], den = 0.0f;
 #pragma unroll
-                            for (int i = 0; i < NM; ++i) {
+                            for (int i = 0; i < 4; ++i) {
                                 q[i] = L.kind == 0 ? 1.0f
                                                    : mk[i] * mk[i] / (k * k) *
                                                          __expf(-0.5f * (mk[i] * mk[i] - k * k) * tt_s * L.rc_um * L.rc_um);
@@ -366,16 +388,23 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                             const float cx = dot3(om, xa), cy = dot3(om, ya);
                             const float scale = 4.0f * L.power * (float)A.nsrc / den;
+                            // one p_w call site for the four members (a rolled loop; the
+                            // member's registers are picked by selects)
+#pragma nounroll
+                            for (int i = 0; i < 4; ++i) {
+                                const float Ti = pick4(mT, i);
+                                if (Ti == 0.0f) continue;
+                                const float ki = pick4(mk, i), sr = 0.5f * pick4(mb2, i);
+                                const float p = pw_plain(m.kind, m.h, m.L, m.refl, ki, ki * cx, ki * cy, -ki * dx,
+                                                         -ki * dy, sr * (1.0f + dx * dx * ic2), sr * (1.0f + dy * dy * ic2),
+                                                         sr * (dx * dy * ic2), 1.0f, 0.0f);
+                                const float add = scale * Ti * pick4(q, i) * p;
 #pragma unroll
-                            for (int i = 0; i < NM; ++i) {
-                                if (mT[i] == 0.0f) continue;
-                                const float sr = 0.5f * mb2[i];
-                                const float p = pw_plain(m.kind, m.h, m.L, m.refl, mk[i], mk[i] * cx, mk[i] * cy,
-                                                         -mk[i] * dx, -mk[i] * dy, sr * (1.0f + dx * dx * ic2),
-                                                         sr * (1.0f + dy * dy * ic2), sr * (dx * dy * ic2), 1.0f, 0.0f);
-                                macc[i] += scale * mT[i] * q[i] * p;
+                                for (int j = 0; j < 4; ++j) {
+                                    if (j == i) macc[j] += add;
+                                }
                             }
-                        } else if (occ < 0) {
+                        } else {
                             const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
                             const float kox = -k * dx, koy = -k * dy;
                             const float scale = alpha * L.power * (float)A.nsrc;
@@ -422,13 +451,14 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     const uint4 rs = draw(pid, (uint32_t)depth, STREAM_SCATTER, A.seed);
                     float kox, koy, wgt;
                     int comp = 0;
+                    float ph = 0.0f;
                     if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
-                                    (float*)(int*)stk, STACK, HERO ? &comp : nullptr)) {
+                                    (float*)(int*)stk, STACK, HERO ? &comp : nullptr, HERO ? &ph : nullptr)) {
                         ev |= 1u << EV_EVANESCENT;
                         finish = true;
                     } else {
                         if constexpr (HERO) {
-                            hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp, mT, mR);
+                            hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp, ph, mT, mR);
                         } else {
                             alpha *= wgt;
                         }
