@@ -56,7 +56,8 @@ class OrOpts(C.Structure):
     _fields_ = [("spp_begin", C.c_int64), ("spp_count", C.c_int64), ("spp_norm", C.c_double),
                 ("max_depth", C.c_int32), ("rr_enable", C.c_int32),
                 ("rr_threshold24", C.c_uint32), ("rr_p", C.c_double), ("seed", C.c_uint64),
-                ("use_bvh", C.c_int32), ("n_threads", C.c_int32), ("hero", C.c_int32)]
+                ("use_bvh", C.c_int32), ("n_threads", C.c_int32), ("hero", C.c_int32),
+                ("aniso", C.c_int32)]
 
 
 class OrCoherent(C.Structure):
@@ -105,6 +106,10 @@ def lib():
             L.or_hankel1_re.restype = C.c_double
             L.or_hankel1_im.argtypes = [C.c_double]
             L.or_hankel1_im.restype = C.c_double
+            L.or_transverse_frame.argtypes = [dp, dp, dp]
+            L.or_aniso_free.argtypes = [C.c_double, C.c_double, dp]
+            L.or_aniso_interact.argtypes = [dp, dp, dp, dp]
+            L.or_aniso_footprint.argtypes = [dp, dp, dp, dp, dp, dp]
             _lib = L
     return _lib
 
@@ -185,6 +190,53 @@ def hero_step(kind, h, L, kh, kc, ui, ci, U, g=(1.0, 0.0), refl=1.0):
     return out
 
 
+def _vec3(a):
+    return np.ascontiguousarray(np.asarray(a, np.float64).reshape(3))
+
+
+def transverse_frame(d):
+    """Orthonormal basis (e1, e2) of the plane normal to the unit vector d."""
+    e1, e2 = np.zeros(3), np.zeros(3)
+    lib().or_transverse_frame(_dp(_vec3(d)), _dp(e1), _dp(e2))
+    return e1, e2
+
+
+def _pack(S):
+    S = np.asarray(S, np.float64)
+    return np.ascontiguousarray(np.concatenate([S[:2, :2].ravel(), S[:2, 2:].ravel(), S[2:, 2:].ravel()]))
+
+
+def _unpack(st):
+    S = np.zeros((4, 4))
+    S[:2, :2] = st[0:4].reshape(2, 2)
+    S[:2, 2:] = st[4:8].reshape(2, 2)
+    S[2:, :2] = st[4:8].reshape(2, 2).T
+    S[2:, 2:] = st[8:12].reshape(2, 2)
+    return S
+
+
+def aniso_free(S, z_um, k):
+    """Free-space step of an anisotropic generalized ray.  S: 4x4 second moments
+    [[Srr, Srk], [Srk^T, Skk]] in the transverse frame of its direction."""
+    st = _pack(S)
+    lib().or_aniso_free(float(z_um), float(k), _dp(st))
+    return _unpack(st)
+
+
+def aniso_interact(S, di, do, n):
+    """Interaction map from mean direction di to do at a surface of normal n."""
+    st = _pack(S)
+    lib().or_aniso_interact(_dp(_vec3(di)), _dp(_vec3(do)), _dp(_vec3(n)), _dp(st))
+    return _unpack(st)
+
+
+def aniso_footprint(S, d, n, xa, ya):
+    """(sxx, syy, sxy) footprint covariance on the surface frame (xa, ya)."""
+    out = np.zeros(3)
+    lib().or_aniso_footprint(_dp(_vec3(d)), _dp(_vec3(n)), _dp(_vec3(xa)), _dp(_vec3(ya)), _dp(_pack(S)), _dp(out))
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 # Scenes and rendering
 # ------------------------------------------------------------------------------------------
@@ -257,12 +309,13 @@ def rr_threshold24(p: float) -> int:
 
 
 def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=None,
-           use_bvh=True, n_threads=0, keep_paths=False, lambdas=None, hero=False):
+           use_bvh=True, n_threads=0, keep_paths=False, lambdas=None, hero=False, aniso=False):
     """Render a workload (or a pixel subset of it).  Returns (image, stats[, paths]).
 
     image: [n_lambda, H, W] when pixels is None, else [n_lambda, n_pixels].
     hero: one path per (pixel, sample, rotation group of four wavelengths), sampled at a hero
-    wavelength drawn from its group (n_lambda must be a multiple of 4)."""
+    wavelength drawn from its group (n_lambda must be a multiple of 4).
+    aniso: anisotropic generalized rays (matrix beta, rho; not with hero)."""
     L = lib()
     oscene = OracleScene(wl.scene) if oscene is None else oscene
     lam = np.ascontiguousarray(wl.lambdas_um if lambdas is None else lambdas, np.float64)
@@ -272,7 +325,8 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
     op = OrOpts(spp_begin=spp_begin, spp_count=spp_count, spp_norm=spp_norm,
                 max_depth=wl.max_depth, rr_enable=int(wl.rr_enable),
                 rr_threshold24=rr_threshold24(wl.rr_p), rr_p=float(np.float32(wl.rr_p)),
-                seed=wl.seed, use_bvh=int(use_bvh), n_threads=n_threads, hero=int(hero))
+                seed=wl.seed, use_bvh=int(use_bvh), n_threads=n_threads, hero=int(hero),
+                aniso=int(aniso))
     sen = _sensor_struct(wl.sensor)
     srcs = _sources_struct(wl.sources)
     if pixels is None:

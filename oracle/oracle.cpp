@@ -136,6 +136,7 @@ typedef struct {
     int32_t use_bvh;            // 0: brute-force closest hit
     int32_t n_threads;
     int32_t hero;               // 1: hero-wavelength paths over rotation groups (nl % 4 == 0)
+    int32_t aniso;              // 1: anisotropic generalized rays (matrix beta, rho)
 } or_opts;
 
 }  // extern "C"
@@ -628,6 +629,103 @@ void propagate(double z, double k, double& beta2, double& rho) {
     beta2 = beta2_new;
 }
 
+// ------------------------------------------------------------------------------------------
+// Anisotropic generalized rays (Sec. "Generalized rays" allows beta, rho to be positive-
+// definite matrices; the formulas are in the paper's supplement, which is not available).
+// Reading: the ray's phase-space Gaussian over the two axes transverse to its mean direction,
+// kept as its 4x4 second-moment matrix [[Srr, Srk], [Srk^T, Skk]] in a transverse frame of
+// the mean direction.  The scalar ray is Srr = beta^2 I, Srk = rho I, Skk = (1 + rho^2) /
+// beta^2 I: its free-space law (eq. K_free_space_propagation) is the shear r -> r + zbar k of
+// these moments, and the matrix form below is the same shear.  At an interaction the
+// transverse plane of the incoming mean direction is carried onto the surface along that
+// direction and the surface onto the transverse plane of the outgoing direction; positions
+// map by that 2x2 G and wavevectors by G^-T (tangential wavevector deviations are conserved),
+// a symplectic map, so a pure state stays pure.  A mirror reflection leaves an isotropic ray
+// isotropic; a grating order or rough-surface lobe leaving at another angle stretches the ray
+// along the plane of scattering by cos(o) / cos(i), the anamorphic beam magnification.
+// ------------------------------------------------------------------------------------------
+struct Aniso {
+    double rr[2][2], rk[2][2], kk[2][2];
+};
+
+// Orthonormal basis (e1, e2) of the plane normal to the unit vector d (Duff et al., "Building
+// an Orthonormal Basis, Revisited", JCGT 6(1), 2017).
+void transverse_frame(V3 d, V3& e1, V3& e2) {
+    double sg = d.z >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (sg + d.z), b = d.x * d.y * a;
+    e1 = V3{1.0 + sg * d.x * d.x * a, sg * b, -sg * d.x};
+    e2 = V3{b, sg + d.y * d.y * a, -d.y};
+}
+
+Aniso aniso_isotropic(double beta2) {
+    Aniso A{};
+    for (int i = 0; i < 2; ++i) {
+        A.rr[i][i] = beta2;
+        A.kk[i][i] = 1.0 / beta2;
+    }
+    return A;
+}
+
+// Free space over z um: zbar = z / k, Srr += zbar (Srk + Srk^T) + zbar^2 Skk, Srk += zbar Skk.
+void propagate_aniso(double z, double k, Aniso& A) {
+    double zb = z / k;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) A.rr[i][j] += zb * (A.rk[i][j] + A.rk[j][i]) + zb * zb * A.kk[i][j];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) A.rk[i][j] += zb * A.kk[i][j];
+}
+
+// The surface point reached from transverse offset v along di: v - di (n . v) / (n . di).
+V3 onto_surface(V3 v, V3 di, V3 n) { return v - (dot(n, v) / dot(n, di)) * di; }
+
+// Interaction: incoming mean direction di, outgoing do_, surface normal n.
+void interact_aniso(V3 di, V3 do_, V3 n, Aniso& A) {
+    V3 ei[2], eo[2];
+    transverse_frame(di, ei[0], ei[1]);
+    transverse_frame(do_, eo[0], eo[1]);
+    double G[2][2], Gi[2][2];
+    for (int b = 0; b < 2; ++b) {
+        V3 sp = onto_surface(ei[b], di, n);
+        for (int a = 0; a < 2; ++a) G[a][b] = dot(eo[a], sp);
+    }
+    double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    Gi[0][0] = G[1][1] / det;
+    Gi[0][1] = -G[0][1] / det;
+    Gi[1][0] = -G[1][0] / det;
+    Gi[1][1] = G[0][0] / det;
+    Aniso B{};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    B.rr[i][j] += G[i][a] * A.rr[a][b] * G[j][b];    // G Srr G^T
+                    B.rk[i][j] += G[i][a] * A.rk[a][b] * Gi[b][j];   // G Srk G^-1
+                    B.kk[i][j] += Gi[a][i] * A.kk[a][b] * Gi[b][j];  // G^-T Skk G^-1
+                }
+    A = B;
+}
+
+// Footprint covariance on the surface frame (xa, ya) of a ray arriving along d: the spatial
+// variance Srr / 2 carried onto the surface along d (the scalar footprint() for Srr = beta^2 I).
+void footprint_aniso(V3 d, V3 n, V3 xa, V3 ya, const Aniso& A, double& sxx, double& syy, double& sxy) {
+    V3 e[2];
+    transverse_frame(d, e[0], e[1]);
+    double H[2][2];
+    for (int b = 0; b < 2; ++b) {
+        V3 sp = onto_surface(e[b], d, n);
+        H[0][b] = dot(xa, sp);
+        H[1][b] = dot(ya, sp);
+    }
+    double S[2][2] = {{0, 0}, {0, 0}};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) S[i][j] += 0.5 * H[i][a] * A.rr[a][b] * H[j][b];
+    sxx = S[0][0];
+    syy = S[1][1];
+    sxy = 0.5 * (S[0][1] + S[1][0]);
+}
+
 double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
     const SceneO& S = *C.S;
     const or_sensor& sen = *C.sen;
@@ -647,6 +745,7 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
     double sig_um = sen.sigma_m * 1e6;
     double beta2 = 2.0 * sig_um * sig_um;
     double rho = 0.0;
+    Aniso A = aniso_isotropic(beta2);   // the matrix form, when op.aniso
     double alpha = 1.0;
     double contrib = 0.0;
     int prev = -1;   // triangle the current segment leaves
@@ -656,12 +755,14 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
         Hit h;
         if (!trace_ray(S, o, d, t_eps(o), 1e300, op.use_bvh != 0, false, h, prev)) break;
         prev = h.tri;
-        propagate(h.t * 1e6, k, beta2, rho);
+        if (op.aniso) propagate_aniso(h.t * 1e6, k, A);
+        else propagate(h.t * 1e6, k, beta2, rho);
         Vertex v;
         if (!make_vertex(S, o, d, h, v)) { st.backfacing++; break; }
         const Mat& m = *v.m;
         double sxx, syy, sxy;
-        footprint(v, beta2, sxx, syy, sxy);
+        if (op.aniso) footprint_aniso(d, v.ns, v.xa, v.ya, A, sxx, syy, sxy);
+        else footprint(v, beta2, sxx, syy, sxy);
         // The frame's x axis is the grating direction, so the grating vector is (1, 0).
         const double gx = 1.0, gy = 0.0;
 
@@ -703,8 +804,10 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
             alpha /= op.rr_p;
         }
         double kn = std::sqrt(std::max(0.0, 1.0 - (kox * kox + koy * koy) / (k * k)));
+        V3 din = d;
         d = (kox / k) * v.xa + (koy / k) * v.ya + kn * v.ns;
         d = unit(d);
+        if (op.aniso) interact_aniso(din, d, v.ns, A);
         o = v.P;
     }
     return contrib;
@@ -962,6 +1065,7 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
              int64_t npix, double* image, double* paths, uint64_t* stats) {
     if (!s || !sen || !op || nl <= 0 || op->spp_count < 0 || op->max_depth < 0) return -1;
     if (op->hero && nl % 4 != 0) return -1;
+    if (op->hero && op->aniso) return -1;   // hero paths carry scalar beta, rho
     const SceneO* S = (const SceneO*)s;
     if (!pixels) npix = (int64_t)sen->width * sen->height;
     Ctx C{S, sen, src, nsrc, lambdas, nl, op};
@@ -1115,5 +1219,48 @@ void or_coherent_exact(const or_coherent* c, const int32_t* xpix, int64_t n, con
 
 double or_hankel1_re(double x) { return std::cyl_bessel_j(1.0, x); }
 double or_hankel1_im(double x) { return std::cyl_neumann(1.0, x); }
+
+// Anisotropic generalized-ray steps, for the tests.  st: the 12 moments in row-major order,
+// Srr[2][2], Srk[2][2], Skk[2][2], in the transverse frame of transverse_frame().
+static Aniso aniso_from(const double* st) {
+    Aniso A;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            A.rr[i][j] = st[2 * i + j];
+            A.rk[i][j] = st[4 + 2 * i + j];
+            A.kk[i][j] = st[8 + 2 * i + j];
+        }
+    return A;
+}
+static void aniso_to(const Aniso& A, double* st) {
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            st[2 * i + j] = A.rr[i][j];
+            st[4 + 2 * i + j] = A.rk[i][j];
+            st[8 + 2 * i + j] = A.kk[i][j];
+        }
+}
+void or_transverse_frame(const double* d, double* e1, double* e2) {
+    V3 a, b;
+    transverse_frame(V3{d[0], d[1], d[2]}, a, b);
+    e1[0] = a.x; e1[1] = a.y; e1[2] = a.z;
+    e2[0] = b.x; e2[1] = b.y; e2[2] = b.z;
+}
+void or_aniso_free(double z_um, double k, double* st) {
+    Aniso A = aniso_from(st);
+    propagate_aniso(z_um, k, A);
+    aniso_to(A, st);
+}
+void or_aniso_interact(const double* di, const double* dout, const double* n, double* st) {
+    Aniso A = aniso_from(st);
+    interact_aniso(V3{di[0], di[1], di[2]}, V3{dout[0], dout[1], dout[2]}, V3{n[0], n[1], n[2]}, A);
+    aniso_to(A, st);
+}
+void or_aniso_footprint(const double* d, const double* n, const double* xa, const double* ya,
+                        const double* st, double* out) {
+    Aniso A = aniso_from(st);
+    footprint_aniso(V3{d[0], d[1], d[2]}, V3{n[0], n[1], n[2]}, V3{xa[0], xa[1], xa[2]},
+                    V3{ya[0], ya[1], ya[2]}, A, out[0], out[1], out[2]);
+}
 
 }  // extern "C"
