@@ -92,7 +92,13 @@ typedef struct {
     float power;
 } gr_source;
 
-enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2, GR_TRACE_WAVEFRONT = 4, GR_TRACE_HERO = 8 };
+enum {
+    GR_TRACE_KEEP_PATHS = 1,
+    GR_TRACE_SHORT_LDS_STACK = 2,
+    GR_TRACE_WAVEFRONT = 4,
+    GR_TRACE_HERO = 8,
+    GR_TRACE_ANISO = 16
+};
 
 /* Trace options.
  *   spp_begin, spp_count : sample indices [spp_begin, spp_begin + spp_count) of every pixel and
@@ -125,7 +131,19 @@ enum { GR_TRACE_KEEP_PATHS = 1, GR_TRACE_SHORT_LDS_STACK = 2, GR_TRACE_WAVEFRONT
  *                          0 are dispersive and carry the hero alone).  A quarter of the paths
  *                          of the default render, a different estimator of the same image; the
  *                          records keep their layout.  Closed-form p_w and the persistent
- *                          kernel only (else GR_E_UNSUPPORTED).  Other bits are invalid. */
+ *                          kernel only (else GR_E_UNSUPPORTED).  GR_TRACE_ANISO carries
+ *                          anisotropic generalized rays (Sec. "Generalized rays": beta, rho as
+ *                          positive-definite matrices): the ray's phase-space second moments
+ *                          over its two transverse axes go through the free-space law in matrix
+ *                          form, and every interaction maps them from the incoming to the
+ *                          outgoing transverse plane through the surface (positions by the
+ *                          projection map G, wavevectors by G^-T), so a grating order or rough
+ *                          lobe leaving at another angle than it arrived stretches the ray
+ *                          along the plane of scattering; the footprint at each hit is the
+ *                          ray's spatial moments on the surface.  Without the flag beta, rho
+ *                          stay scalar and interactions leave them unchanged.  Closed-form p_w,
+ *                          one wavelength per path and the persistent kernel only (else
+ *                          GR_E_UNSUPPORTED).  Other bits are invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;

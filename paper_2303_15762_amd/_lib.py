@@ -20,6 +20,7 @@ GR_TRACE_KEEP_PATHS = 1
 GR_TRACE_SHORT_LDS_STACK = 2
 GR_TRACE_WAVEFRONT = 4
 GR_TRACE_HERO = 8
+GR_TRACE_ANISO = 16
 GR_MLP_PARAMS = 13249
 
 

@@ -42,6 +42,7 @@ struct gr_ctx {
     int grid_plain = 0;              // persistent grids (blocks), set at scene upload
     int grid_sur = 0;
     int grid_hero = 0;
+    int grid_aniso = 0;
     int grid_batch = 0;              // blocks of the batched network pass
     int grid_wf = 0;                 // blocks of the wavefront traversal kernels
     int grid_work = 0;               // blocks of the grid-stride wavefront kernels
@@ -114,6 +115,7 @@ struct WsLayout {
 
 bool wavefront_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_WAVEFRONT) != 0; }
 bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
+bool aniso_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_ANISO) != 0; }
 
 // Per-path wavefront arrays in this order, each padded to 256 B (element sizes in bytes).
 constexpr int kWfArrays = 27;
@@ -306,6 +308,7 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     c->grid_plain = grw::trace_grid_size(c->device, false);
     c->grid_sur = grw::trace_grid_size(c->device, true);
     c->grid_hero = grw::trace_grid_size(c->device, false, true);
+    c->grid_aniso = grw::trace_grid_size(c->device, false, false, true);
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
@@ -317,7 +320,7 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
-    if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0) {
+    if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0 || c->grid_aniso <= 0) {
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
@@ -385,7 +388,8 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     WsLayout L;
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
     const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
-    const size_t lanes = (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_wf}) * 256;
+    const size_t lanes =
+        (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso, c->grid_wf}) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
@@ -429,8 +433,12 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (o->max_depth < 1 || o->max_depth > 64) return fail(c, GR_E_INVALID, "trace: max_depth %d", o->max_depth);
     if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
     if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
-    if (o->flags & ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_WAVEFRONT | GR_TRACE_HERO))
+    if (o->flags &
+        ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_WAVEFRONT | GR_TRACE_HERO | GR_TRACE_ANISO))
         return fail(c, GR_E_INVALID, "trace: flags");
+    if (aniso_of(o) && (hero_of(o) || o->bsdf_mode != GR_BSDF_PLAIN || wavefront_of(o)))
+        return fail(c, GR_E_UNSUPPORTED,
+                    "trace: anisotropic rays with the closed-form p_w, one wavelength per path and the persistent kernel only");
     if (hero_of(o)) {
         if (nl % 4 != 0) return fail(c, GR_E_INVALID, "trace: hero wavelengths need n_lambda %% 4 == 0 (got %d)", nl);
         if (o->bsdf_mode != GR_BSDF_PLAIN || wavefront_of(o))
@@ -496,6 +504,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     for (int i = 0; i < nl; ++i) a.lambda[i] = lambda[i];
     a.spp_begin = o->spp_begin;
     a.hero = hero_of(o) ? 1 : 0;
+    a.aniso = aniso_of(o) ? 1 : 0;
     a.per_sample = (uint32_t)(a.hero ? per / 4 : per);   // hero: one path per group of 4 wavelengths
     a.n_paths = (uint64_t)a.per_sample * (uint64_t)o->spp_count;
     a.inv_spp_norm = (float)(1.0 / (double)o->spp_norm);
@@ -522,7 +531,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     float* dense = defer ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
 
     GR_HIP(c, hipSetDevice(c->device));
-    const int grid = defer ? c->grid_sur : (a.hero ? c->grid_hero : c->grid_plain);
+    const int grid = defer ? c->grid_sur : (a.hero ? c->grid_hero : (a.aniso ? c->grid_aniso : c->grid_plain));
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (st)
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));

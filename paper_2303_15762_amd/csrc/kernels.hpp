@@ -64,6 +64,7 @@ struct TraceArgs {
     uint64_t n_paths;          // paths of this launch: [path_begin, path_begin + n_paths)
     uint32_t per_sample;       // paths per sample: H * W * nl, or H * W * nl / 4 with hero
     int hero;                  // 1: hero-wavelength paths over rotation groups of 4 wavelengths
+    int aniso;                 // 1: anisotropic generalized rays (matrix beta, rho)
     float inv_spp_norm;
     int max_depth;
     int rr_enable;
@@ -124,7 +125,7 @@ hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* s
                               hipStream_t s);
 // records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
 hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
-int trace_grid_size(int device, bool sur, bool hero = false);
+int trace_grid_size(int device, bool sur, bool hero = false, bool aniso = false);
 
 // Batch p_w evaluation (trace.hip).
 hipError_t launch_bsdf_eval(const float* q, int64_t n, float* out, hipStream_t s);

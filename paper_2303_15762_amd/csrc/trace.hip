@@ -130,7 +130,110 @@ __device__ inline void hero_continuation(const DMat& m, float kh, const float (&
 // to the hero's and M the measurement.
 // All instantiations ask for 4 waves per SIMD (128 VGPRs): a few path-state values spill to
 // scratch, which costs less than the latency hidden by the fourth wave.
-template <int STACK, bool DEFER, bool HERO>
+// ------------------------------------------------------------------------------------------
+// Anisotropic generalized rays (Sec. "Generalized rays": beta, rho may be positive-definite
+// matrices).  The ray's phase-space Gaussian over the two axes transverse to its mean direction
+// is kept as its second moments Srr (symmetric), Srk, Skk (symmetric) in the transverse frame
+// of the direction; the scalar ray is Srr = beta^2 I, Srk = rho I, Skk = (1 + rho^2) / beta^2 I,
+// and free space (eq. K_free_space_propagation) is the shear r -> r + zbar k of these moments.
+// An interaction carries the incoming transverse plane onto the surface along the incoming
+// direction and the surface onto the outgoing transverse plane: positions map by that 2x2 G,
+// wavevectors by G^-T (tangential wavevector deviations are conserved).
+// ------------------------------------------------------------------------------------------
+struct AnisoRay {
+    float rr[3];   // Srr: xx, xy, yy
+    float rk[4];   // Srk: xx, xy, yx, yy
+    float kk[3];   // Skk: xx, xy, yy
+};
+
+// Orthonormal basis of the plane normal to the unit vector d (Duff et al., "Building an
+// Orthonormal Basis, Revisited", JCGT 6(1), 2017).
+__device__ __forceinline__ void transverse_frame(const f3& d, f3& e1, f3& e2) {
+    const float sg = d.z >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (sg + d.z), b = d.x * d.y * a;
+    e1 = mk3(1.0f + sg * d.x * d.x * a, sg * b, -sg * d.x);
+    e2 = mk3(b, sg + d.y * d.y * a, -d.y);
+}
+
+__device__ __forceinline__ void aniso_iso(AnisoRay& R, float beta2) {
+    R.rr[0] = R.rr[2] = beta2;
+    R.rr[1] = 0.0f;
+    R.rk[0] = R.rk[1] = R.rk[2] = R.rk[3] = 0.0f;
+    R.kk[0] = R.kk[2] = 1.0f / beta2;
+    R.kk[1] = 0.0f;
+}
+
+// Free space over zbar = z / k: Srr += zbar (Srk + Srk^T) + zbar^2 Skk, Srk += zbar Skk.
+__device__ __forceinline__ void aniso_free(AnisoRay& R, float zb) {
+    const float z2 = zb * zb;
+    R.rr[0] += zb * (2.0f * R.rk[0]) + z2 * R.kk[0];
+    R.rr[1] += zb * (R.rk[1] + R.rk[2]) + z2 * R.kk[1];
+    R.rr[2] += zb * (2.0f * R.rk[3]) + z2 * R.kk[2];
+    R.rk[0] += zb * R.kk[0];
+    R.rk[1] += zb * R.kk[1];
+    R.rk[2] += zb * R.kk[1];
+    R.rk[3] += zb * R.kk[2];
+}
+
+// The 2x2 map from the transverse frame of di onto the surface (normal n) along di, expressed
+// in the basis (t0, t1) (the outgoing transverse frame, or the surface's tangent frame).
+__device__ __forceinline__ void onto_surface_map(const f3& di, const f3& n, const f3& t0, const f3& t1,
+                                                 float (&G)[2][2]) {
+    f3 e[2];
+    transverse_frame(di, e[0], e[1]);
+    const float ind = 1.0f / dot3(n, di);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const f3 sp = e[b] - (dot3(n, e[b]) * ind) * di;
+        G[0][b] = dot3(t0, sp);
+        G[1][b] = dot3(t1, sp);
+    }
+}
+
+__device__ inline void aniso_interact(AnisoRay& R, const f3& di, const f3& dout, const f3& n) {
+    f3 eo0, eo1;
+    transverse_frame(dout, eo0, eo1);
+    float G[2][2];
+    onto_surface_map(di, n, eo0, eo1, G);
+    const float idet = 1.0f / (G[0][0] * G[1][1] - G[0][1] * G[1][0]);
+    const float Gi[2][2] = {{G[1][1] * idet, -G[0][1] * idet}, {-G[1][0] * idet, G[0][0] * idet}};
+    const float rr[2][2] = {{R.rr[0], R.rr[1]}, {R.rr[1], R.rr[2]}};
+    const float rk[2][2] = {{R.rk[0], R.rk[1]}, {R.rk[2], R.rk[3]}};
+    const float kk[2][2] = {{R.kk[0], R.kk[1]}, {R.kk[1], R.kk[2]}};
+    float grr[2][2], grk[2][2], gkk[2][2];   // G Srr, G Srk, Gi^T Skk
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            grr[i][j] = G[i][0] * rr[0][j] + G[i][1] * rr[1][j];
+            grk[i][j] = G[i][0] * rk[0][j] + G[i][1] * rk[1][j];
+            gkk[i][j] = Gi[0][i] * kk[0][j] + Gi[1][i] * kk[1][j];
+        }
+    R.rr[0] = grr[0][0] * G[0][0] + grr[0][1] * G[0][1];
+    R.rr[1] = grr[0][0] * G[1][0] + grr[0][1] * G[1][1];
+    R.rr[2] = grr[1][0] * G[1][0] + grr[1][1] * G[1][1];
+    R.rk[0] = grk[0][0] * Gi[0][0] + grk[0][1] * Gi[1][0];
+    R.rk[1] = grk[0][0] * Gi[0][1] + grk[0][1] * Gi[1][1];
+    R.rk[2] = grk[1][0] * Gi[0][0] + grk[1][1] * Gi[1][0];
+    R.rk[3] = grk[1][0] * Gi[0][1] + grk[1][1] * Gi[1][1];
+    R.kk[0] = gkk[0][0] * Gi[0][0] + gkk[0][1] * Gi[1][0];
+    R.kk[1] = gkk[0][0] * Gi[0][1] + gkk[0][1] * Gi[1][1];
+    R.kk[2] = gkk[1][0] * Gi[0][1] + gkk[1][1] * Gi[1][1];
+}
+
+// Footprint covariance in the surface frame (xa, ya): Srr / 2 carried onto the surface along d.
+__device__ __forceinline__ void aniso_footprint(const AnisoRay& R, const f3& d, const f3& n, const f3& xa,
+                                                const f3& ya, float& sxx, float& syy, float& sxy) {
+    float H[2][2];
+    onto_surface_map(d, n, xa, ya, H);
+    const float h0[2] = {H[0][0] * R.rr[0] + H[0][1] * R.rr[1], H[0][0] * R.rr[1] + H[0][1] * R.rr[2]};
+    const float h1[2] = {H[1][0] * R.rr[0] + H[1][1] * R.rr[1], H[1][0] * R.rr[1] + H[1][1] * R.rr[2]};
+    sxx = 0.5f * (h0[0] * H[0][0] + h0[1] * H[0][1]);
+    sxy = 0.5f * (h0[0] * H[1][0] + h0[1] * H[1][1]);
+    syy = 0.5f * (h1[0] * H[1][0] + h1[1] * H[1][1]);
+}
+
+template <int STACK, bool DEFER, bool HERO, bool ANISO = false>
 __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
@@ -149,6 +252,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     d3 o = d3{0.0, 0.0, 0.0};
     f3 d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
+    AnisoRay ar;   // ANISO: the ray's second moments (beta2, rho unused)
+    if constexpr (ANISO) aniso_iso(ar, 1.0f);
     // hero-wavelength members: wavenumber, beta^2, rho, T = f / p_h, R = p / p_h, estimate
     constexpr int NM = HERO ? 4 : 1;
     float mk[NM], mb2[NM], mrho[NM], mT[NM], mR[NM], macc[NM];
@@ -227,11 +332,16 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                                 }
                             }
                         }
+                        if constexpr (ANISO) aniso_iso(ar, beta2);
                         if (tadv > 0.0f) {
                             o = add_scaled(o, tadv, d);
                             const float zb = tadv * 1e6f / k;
-                            rho = zb / beta2;
-                            beta2 = beta2 + zb * zb / beta2;
+                            if constexpr (ANISO) {
+                                aniso_free(ar, zb);
+                            } else {
+                                rho = zb / beta2;
+                                beta2 = beta2 + zb * zb / beta2;
+                            }
                         }
                         alpha = 1.0f;
                         contrib = 0.0f;
@@ -272,6 +382,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     mb2[i] = mb2[i] + zb * (2.0f * mrho[i] + zb * orr / mb2[i]);
                     mrho[i] = rho_n;
                 }
+            } else if constexpr (ANISO) {
+                aniso_free(ar, thit * 1e6f / k);
             } else {
                 const float zb = thit * 1e6f / k;
                 const float orr = 1.0f + rho * rho;
@@ -329,9 +441,14 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 const float sr2 = 0.5f * beta2;
                 const float dx = dot3(d, xa), dy = dot3(d, ya);
                 const float ic2 = 1.0f / (ci * ci);
-                const float sxx = sr2 * (1.0f + dx * dx * ic2);
-                const float syy = sr2 * (1.0f + dy * dy * ic2);
-                const float sxy = sr2 * (dx * dy * ic2);
+                float sxx, syy, sxy;
+                if constexpr (ANISO) {
+                    aniso_footprint(ar, d, ns, xa, ya, sxx, syy, sxy);
+                } else {
+                    sxx = sr2 * (1.0f + dx * dx * ic2);
+                    syy = sr2 * (1.0f + dy * dy * ic2);
+                    sxy = sr2 * (dx * dy * ic2);
+                }
 
                 // Measurement by next-event estimation (eq. measurement_operator).
                 if (A.nsrc > 0) {
@@ -475,7 +592,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         }
                         if (!finish) {
                             const float kn = sqrtf(fmaxf(0.0f, 1.0f - (kox * kox + koy * koy) / (k * k)));
+                            const f3 din = d;
                             d = normalize3((kox / k) * xa + (koy / k) * ya + kn * ns);
+                            if constexpr (ANISO) aniso_interact(ar, din, d, ns);
                             o = P;
                             ++depth;
                         }
@@ -549,22 +668,25 @@ __global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict_
                       r[12], r[13]);
 }
 
-template <bool DEFER, bool HERO>
+template <bool DEFER, bool HERO, bool ANISO = false>
 static int grid_for(int device) {
     int ncu = 0, nb = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER, HERO>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER, HERO, ANISO>, 256, 0) !=
+        hipSuccess)
         return 0;
     return ncu * (nb > 0 ? nb : 1);
 }
 
-int trace_grid_size(int device, bool sur, bool hero) {
+int trace_grid_size(int device, bool sur, bool hero, bool aniso) {
+    if (aniso) return grid_for<false, false, true>(device);
     if (hero) return grid_for<false, true>(device);
     return sur ? grid_for<true, false>(device) : grid_for<false, false>(device);
 }
 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.hero) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, true>), dim3(grid), dim3(256), 0, s, a);
+    if (a.aniso) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (a.hero) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.bsdf_mode != 0) hipLaunchKernelGGL((trace_kernel<kLdsStack, true, false>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -131,7 +131,7 @@ class Renderer:
     # -- trace -----------------------------------------------------------------------------
     def opts(self, spp_begin=0, spp_count=1, spp_norm=None, max_depth=1, bsdf_mode=0,
              rr_enable=False, rr_p=0.8, seed=0, keep_paths=False,
-             short_lds_stack=False, wavefront=None, hero=False) -> L.GrTraceOpts:
+             short_lds_stack=False, wavefront=None, hero=False, aniso=False) -> L.GrTraceOpts:
         o = L.GrTraceOpts()
         o.spp_begin = int(spp_begin)
         o.spp_count = int(spp_count)
@@ -144,7 +144,7 @@ class Renderer:
         wf = self.wavefront if wavefront is None else wavefront
         o.flags = (L.GR_TRACE_KEEP_PATHS if keep_paths else 0) | \
             (L.GR_TRACE_SHORT_LDS_STACK if short_lds_stack else 0) | (L.GR_TRACE_WAVEFRONT if wf else 0) | \
-            (L.GR_TRACE_HERO if hero else 0)
+            (L.GR_TRACE_HERO if hero else 0) | (L.GR_TRACE_ANISO if aniso else 0)
         return o
 
     def workspace(self, opts: L.GrTraceOpts, n_lambda: int):
@@ -184,11 +184,11 @@ class Renderer:
             opts.spp_count, self.sensor.height, self.sensor.width, n_lambda)
 
     def render_workload(self, wl, spp_begin=0, spp_count=None, bsdf_mode=0, stats=True,
-                        keep_paths=False, hero=False):
+                        keep_paths=False, hero=False, aniso=False):
         spp_count = wl.spp if spp_count is None else spp_count
         o = self.opts(spp_begin=spp_begin, spp_count=spp_count, spp_norm=wl.spp,
                       max_depth=wl.max_depth, bsdf_mode=bsdf_mode, rr_enable=wl.rr_enable,
-                      rr_p=wl.rr_p, seed=wl.seed, keep_paths=keep_paths, hero=hero)
+                      rr_p=wl.rr_p, seed=wl.seed, keep_paths=keep_paths, hero=hero, aniso=aniso)
         return self.trace(wl.lambdas_um, o, stats=stats)
 
     # -- scattering kernels ---------------------------------------------------------------

@@ -89,9 +89,17 @@ def test_trace_rejects_before_device_use(ctx):
     bad = (C.c_float * 1)(-1.0)
     o.bsdf_mode = 0
     assert lib.gr_trace(h, bad, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
-    # flags: unknown bits, and hero-wavelength paths outside what they support
-    o.flags = 16
+    # flags: unknown bits, and hero-wavelength paths or anisotropic rays outside what they support
+    o.flags = 32
     assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
+    for extra, mode in ((L.GR_TRACE_WAVEFRONT, 0), (0, 1), (0, 2)):
+        o.flags = L.GR_TRACE_ANISO | extra
+        o.bsdf_mode = mode
+        assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
+        assert b"anisotropic" in lib.gr_last_error(h)
+    o.bsdf_mode = 0
+    o.flags = L.GR_TRACE_ANISO
+    assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
     o.flags = L.GR_TRACE_HERO
     assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
     assert b"n_lambda" in lib.gr_last_error(h)
@@ -103,6 +111,8 @@ def test_trace_rejects_before_device_use(ctx):
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
     o.bsdf_mode = 0
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
+    o.flags = L.GR_TRACE_HERO | L.GR_TRACE_ANISO
+    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
 
 
 def test_scene_validation(ctx):

@@ -12,7 +12,10 @@ with something other than itself:
   cos(o) / cos(i) along the plane of scattering and unchanged across it;
 - the projected-area ratio |n.o| / |n.i| for any direction change;
 - the scalar footprint (variance beta^2 / 2 stretched by 1 / cos along the plane of incidence);
-- on an all-smooth scene the anisotropic render equals the scalar one.
+- on an all-smooth scene the anisotropic render equals the scalar one;
+- a grating relayed by a mirror: the image ratio between anisotropic and scalar rays is the
+  square root of the ratio of the in-plane beam variances on the mirror, from the Gaussian-beam
+  law per axis with the grating's anamorphic magnification in between.
 """
 
 import math
@@ -21,7 +24,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import parallel_mirror
+from workloads import grating_relay, parallel_mirror
 
 
 def iso(beta2, rho=0.0):
@@ -181,3 +184,34 @@ def test_anisotropic_rays_are_rejected_with_hero_paths():
     wl = parallel_mirror()
     with pytest.raises(RuntimeError):
         oracle.render(wl, aniso=True, hero=True)
+
+
+def relay_ratio(height_m):
+    """Closed form of the anisotropic / scalar image ratio of grating_relay: paths leave the
+    sensor (beta0^2 = 2 sigma^2, rho = 0) at normal incidence, travel L1 to the grating, leave
+    it in the -1 order at angle o (in-plane magnification m = cos(o)), travel D = H / cos(o) to
+    the mirror, where p_w at the specular direction is proportional to sqrt(det S_fp).  The
+    axis across the plane of scattering follows the scalar law in both cases."""
+    lam, sig, L1 = 0.55, 20.0, 1e4
+    k = 2.0 * math.pi / lam
+    b0 = 2.0 * sig * sig
+    so = lam / 1.0
+    co = math.sqrt(1.0 - so * so)
+    z1, z2 = L1 / k, height_m * 1e6 / co / k
+    b1, r1, a = b0 + z1 * z1 / b0, z1 / b0, 1.0 / b0
+    m = co
+    along = m * m * b1 + 2.0 * z2 * r1 + z2 * z2 * a / (m * m)
+    scalar = b0 + (z1 + z2) ** 2 / b0
+    return math.sqrt(along / scalar)
+
+
+@pytest.mark.parametrize("height_m", [2e-3, 5e-3])
+def test_grating_relay_image_ratio_is_the_footprint_ratio(height_m):
+    wl = grating_relay(height_m=height_m)
+    a, st_a = oracle.render(wl, aniso=True)
+    s, st_s = oracle.render(wl)
+    assert st_a == st_s
+    lit = s[0] > 0
+    assert lit.sum() > 200                      # most pixels see the relayed order
+    assert np.all((a[0] > 0) == lit)
+    np.testing.assert_allclose(a[0][lit] / s[0][lit], relay_ratio(height_m), rtol=1e-12)

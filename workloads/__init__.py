@@ -14,6 +14,7 @@ from .scenes import (  # noqa: F401
     wavelength_bins,
     tiny_grating,
     parallel_mirror,
+    grating_relay,
     terrain_scene,
     mid_terrain,
     large_scene,

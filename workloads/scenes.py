@@ -151,6 +151,38 @@ def parallel_mirror(width: int = 16, height: int = 16, spp: int = 4, n_lambda: i
                     max_depth=2, seed=seed)
 
 
+def grating_relay(width: int = 16, height: int = 16, spp: int = 8, seed: int = 9,
+                  height_m: float = 2e-3) -> Workload:
+    """A grating relayed by a mirror.  A 0.5 mm square grating quad in z=0 (pitch 1 um,
+    amplitude 0.1 um, grooves across x) is seen at normal incidence by an orthographic sensor
+    1 cm above it, lambda = 0.55 um.  Its -1 order (sin(o) = 0.55, towards +x) meets a smooth
+    mirror (reflectance 0.9) in the plane z = height_m, facing down and off to the side of the
+    sensor's view, and a plane wave travelling along (-sin(o), 0, cos(o)) reaches that mirror at
+    the specular direction of the relayed beam.  Light reaches the sensor only through the -1
+    order and the mirror: the other propagating orders miss the mirror, and the grating cannot
+    see the source.  Every such path has the same geometry, so its contribution depends only on
+    the ray's footprint on the mirror."""
+    lam = 0.55
+    s_o = lam / 1.0
+    c_o = math.sqrt(1.0 - s_o * s_o)
+    half = 0.25e-3
+    xm = height_m * s_o / c_o                        # where the beam from x = 0 meets the mirror
+    verts = np.array([[-half, -half, 0.0], [half, -half, 0.0], [half, half, 0.0], [-half, half, 0.0],
+                      [xm - 0.3e-3, -0.3e-3, height_m], [xm + 0.3e-3, -0.3e-3, height_m],
+                      [xm + 0.3e-3, 0.3e-3, height_m], [xm - 0.3e-3, 0.3e-3, height_m]], np.float64)
+    tris = np.array([[0, 1, 2], [0, 2, 3], [4, 5, 6], [4, 6, 7]], np.int32)
+    mats = [Material(GRATING, height_um=0.1, length_um=1.0, gdir=(1.0, 0.0, 0.0)),
+            Material(SMOOTH, reflectance=0.9)]
+    scene = Scene(verts=verts, tris=tris, tri_mat=np.array([0, 0, 1, 1], np.int32), materials=mats,
+                  normals=None)
+    pitch = 0.4e-3 / width
+    sensor = _ortho_sensor(np.array([0.0, 0.0, 0.01]), np.array([0.0, 0.0, -1.0]),
+                           np.array([0.0, 1.0, 0.0]), width, height, pitch, 20e-6)
+    src = Source(PLANE_WAVE, dir=np.array([-s_o, 0.0, c_o]), power=1.0)
+    return Workload("grating-relay", scene, sensor, [src], np.array([lam]), spp=spp, max_depth=2,
+                    seed=seed)
+
+
 # --------------------------------------------------------------------------------------
 # Terrain: value-noise heightfield with per-tile materials
 # --------------------------------------------------------------------------------------
