@@ -186,6 +186,30 @@ def hero_leg(R, wl, ms_plain, args):
             "frame_speedup_vs_one_wavelength_paths": round(ms_plain / ms, 3)}
 
 
+def aniso_leg(R, wl, ms_plain, img_plain, args):
+    """Anisotropic generalized rays (matrix beta, rho) on the same workload and random streams:
+    frame time, path segments per second, and the image difference from the scalar rays."""
+    import torch
+    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+               rr_enable=wl.rr_enable, rr_p=wl.rr_p, aniso=True)
+    img = torch.zeros((len(wl.lambdas_um), wl.sensor.height, wl.sensor.width), device=R.dev)
+    _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
+    diff = float(torch.linalg.vector_norm((img - img_plain).double()) /
+                 torch.linalg.vector_norm(img_plain.double()))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(R.stream)
+    for _ in range(args.steps):
+        R.trace(wl.lambdas_um, o, image=img, stats=False)
+    e1.record(R.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    return {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
+            "ms_per_step": round(ms, 3), "segments_per_step": st["segments"],
+            "frame_time_vs_scalar_rays": round(ms / ms_plain, 3), "rel_l2_vs_scalar_ray_image": diff}
+
+
 # Coherent measurement: vector operations of one (sample, slit node) evaluation in the FP64
 # mode, the way the kernel writes them: distance (1 FMA + a square root of ~6), phase (1),
 # amplitude (4 multiplies, a division of ~8, a square root of ~6), sincos with its range
@@ -229,6 +253,8 @@ def main():
                     help="skip the learned-p_w leg (training takes a few seconds)")
     ap.add_argument("--no-hero", dest="hero", action="store_false",
                     help="skip the hero-wavelength leg")
+    ap.add_argument("--no-aniso", dest="aniso", action="store_false",
+                    help="skip the anisotropic-ray leg")
     ap.add_argument("--no-coherent", dest="coherent", action="store_false",
                     help="skip the coherent-measurement leg")
     ap.add_argument("--workload", choices=["mid", "large"], default="mid",
@@ -331,6 +357,8 @@ def main():
     }
     if args.hero and len(wl.lambdas_um) % 4 == 0:
         out["hero"] = hero_leg(R, wl, ms_step, args)
+    if args.aniso:
+        out["aniso"] = aniso_leg(R, wl, ms_step, img, args)
     if args.coherent and args.workload == "mid":
         out["coherent"] = coherent_leg(R, args)
     if args.surrogate:
