@@ -76,6 +76,22 @@ def test_large_hero_sampled_pixels(large):
     assert e <= 1e-3
 
 
+def test_large_aniso_sampled_pixels(large):
+    """Anisotropic generalized rays on the large scene (boxes and tiles at every angle, six
+    interactions): they change this image by about a third against scalar rays."""
+    R, wl, torch = large
+    img, st = R.render_workload(wl, aniso=True)
+    g = img.cpu().numpy()
+    print("large aniso:", st)
+    assert st["paths"] == 1920 * 1080 * 64 * 16
+    assert st["nonfinite"] == 0
+    pix_yx, pix = _pixels(g, 800, 200, 3)
+    o, _ = oracle.render(wl, pixels=pix, n_threads=0, aniso=True)
+    e = rel_l2(g[:, pix_yx[:, 0], pix_yx[:, 1]], o)
+    print("large aniso: rel L2 on", len(pix), "pixels:", e)
+    assert e <= 1e-3
+
+
 def test_large_surrogate_sampled_pixels(large):
     R, wl, torch = large
     from paper_2303_15762_amd.surrogate import Surrogate
