@@ -688,7 +688,8 @@ void interact_aniso(V3 di, V3 do_, V3 n, Aniso& A) {
         V3 sp = onto_surface(ei[b], di, n);
         for (int a = 0; a < 2; ++a) G[a][b] = dot(eo[a], sp);
     }
-    double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    double det = G[0][0] * G[1][1] - G[0][1] * G[1][0];   // +-cos(o) / cos(i)
+    if (!(std::fabs(det) > 1e-6)) return;   // a continuation along the surface: the map is singular
     Gi[0][0] = G[1][1] / det;
     Gi[0][1] = -G[0][1] / det;
     Gi[1][0] = -G[1][0] / det;

@@ -195,7 +195,9 @@ __device__ inline void aniso_interact(AnisoRay& R, const f3& di, const f3& dout,
     transverse_frame(dout, eo0, eo1);
     float G[2][2];
     onto_surface_map(di, n, eo0, eo1, G);
-    const float idet = 1.0f / (G[0][0] * G[1][1] - G[0][1] * G[1][0]);
+    const float det = G[0][0] * G[1][1] - G[0][1] * G[1][0];   // +-cos(o) / cos(i)
+    if (!(fabsf(det) > 1e-6f)) return;   // a continuation along the surface: the map is singular
+    const float idet = 1.0f / det;
     const float Gi[2][2] = {{G[1][1] * idet, -G[0][1] * idet}, {-G[1][0] * idet, G[0][0] * idet}};
     const float rr[2][2] = {{R.rr[0], R.rr[1]}, {R.rr[1], R.rr[2]}};
     const float rk[2][2] = {{R.rk[0], R.rk[1]}, {R.rk[2], R.rk[3]}};

@@ -215,3 +215,14 @@ def test_grating_relay_image_ratio_is_the_footprint_ratio(height_m):
     assert lit.sum() > 200                      # most pixels see the relayed order
     assert np.all((a[0] > 0) == lit)
     np.testing.assert_allclose(a[0][lit] / s[0][lit], relay_ratio(height_m), rtol=1e-12)
+
+
+def test_continuation_along_the_surface_leaves_the_moments():
+    # cos(o) -> 0: the map from the surface onto the outgoing transverse plane is singular
+    n = np.array([0.0, 0.0, 1.0])
+    di = unit([0.3, 0.0, -1.0])
+    do = unit([1.0, 0.0, 1e-9])
+    S0 = oracle.aniso_free(iso(2.0), 300.0, 11.0)
+    S1 = oracle.aniso_interact(S0, di, do, n)
+    np.testing.assert_array_equal(S1, S0)
+    assert np.all(np.isfinite(S1))
