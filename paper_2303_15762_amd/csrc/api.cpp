@@ -529,6 +529,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     const bool fp8 = o->bsdf_mode == GR_BSDF_SURROGATE_FP8;
     a.sq = defer ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
     float* dense = defer ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
+    a.sdense = dense;
 
     GR_HIP(c, hipSetDevice(c->device));
     const int grid = defer ? c->grid_sur : (a.hero ? c->grid_hero : (a.aniso ? c->grid_aniso : c->grid_plain));
@@ -562,17 +563,18 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
         a.path_begin = 0;
         if (total > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
     } else {
-        // launches of at most WL.chunk paths: trace (queries queued), one batched network
-        // pass over the queue, results added to the path records in a fixed order
+        // launches of at most WL.chunk paths: trace (queries queued; each path clears its own
+        // result slots), one batched network pass over the queue, results added to the path
+        // records in a fixed order by the paths' first queries
         const int D = o->max_depth;
         for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
             const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
             a.path_begin = p0;
             a.n_paths = pn;
-            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, pn * (uint64_t)D, c->stream));
+            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, 0, c->stream));
             GR_HIP(c, grw::launch_trace(a, grid, c->stream));
             GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
-            GR_HIP(c, grw::launch_sur_merge(dense, D, a.records, p0, pn, c->stream));
+            GR_HIP(c, grw::launch_sur_merge_queued(a.sq, a.sq_count, dense, D, a.records, p0, c->grid_batch, c->stream));
         }
         a.n_paths = total;
     }

@@ -74,6 +74,8 @@ struct TraceArgs {
     int bsdf_mode;
     SurrogateDev sur;
     uint4* sq;                       // deferred learned-p_w queries, 2 uint4 each, or null
+    float* sdense;                   // their result slots [paths of the launch][max_depth]; the
+                                     // persistent kernel zeroes a path's slots when it starts it
     unsigned long long* sq_count;
     float* records;                  // [n_paths]
     int* ovf;                        // traversal stack overflow [ovf_n][grid * 256], or null
@@ -125,6 +127,11 @@ hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* s
                               hipStream_t s);
 // records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
 hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
+hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
+                                   float* records, uint64_t p0, int grid, hipStream_t s);
+// Bit 31 of a queued query's slot field marks the first query of its path (the one at its
+// lowest interaction); slots stay below 2^29.
+constexpr uint32_t kSlotFirst = 0x80000000u;
 int trace_grid_size(int device, bool sur, bool hero = false, bool aniso = false);
 
 // Batch p_w evaluation (trace.hip).

@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     d3 o = d3{0.0, 0.0, 0.0};
     f3 d = mk3(0, 0, 1);
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
+    bool qfirst = true;   // DEFER: the path has queued no learned-p_w query yet
     AnisoRay ar;   // ANISO: the ray's second moments (beta2, rho unused)
     if constexpr (ANISO) aniso_iso(ar, 1.0f);
     // hero-wavelength members: wavenumber, beta^2, rho, T = f / p_h, R = p / p_h, estimate
@@ -347,6 +348,13 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         }
                         alpha = 1.0f;
                         contrib = 0.0f;
+                        if constexpr (DEFER) {
+                            // clear the path's result slots: the merge sums them from the
+                            // path's first queued interaction on
+                            float* ds = A.sdense + (idx - A.path_begin) * (uint64_t)A.max_depth;
+                            for (int dd = 0; dd < A.max_depth; ++dd) ds[dd] = 0.0f;
+                            qfirst = true;
+                        }
                         depth = 0;
                         prev = -1;
                         live = true;
@@ -547,7 +555,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                                     const uint32_t r = __builtin_amdgcn_mbcnt_hi(
                                         (uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
                                     uint4* q = A.sq + 2 * (qb + r);
-                                    const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
+                                    const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth) |
+                                                          (qfirst ? kSlotFirst : 0u);
+                                    qfirst = false;
                                     q[0] = make_uint4(bf16_pair(sx[0], sx[1]), bf16_pair(sx[2], sx[3]),
                                                       bf16_pair(sx[4], sx[5]), bf16_pair(sx[6], sx[7]));
                                     q[1] = make_uint4(bf16_pair(sx[8], sx[9]),
@@ -711,6 +721,32 @@ __global__ __launch_bounds__(256) void sur_merge_kernel(const float* __restrict_
     float s = 0.0f;
     for (int d = 0; d < depth; ++d) s += dense[i * depth + d];
     records[p0 + i] += s;
+}
+
+// The persistent kernel's merge: one thread per queued query, and the first query of each path
+// adds the path's result slots from its interaction on, in depth order (the slots before it
+// and those of interactions without a query hold zeros), so the sum is the one of the dense
+// merge above, with the work of the queue rather than of every slot.
+__global__ __launch_bounds__(256) void sur_merge_queued_kernel(const uint4* __restrict__ q,
+                                                               const unsigned long long* __restrict__ count,
+                                                               const float* __restrict__ dense, int depth,
+                                                               float* __restrict__ records, uint64_t p0) {
+    const uint64_t n = *count;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = q[2 * i + 1].w;
+        if (!(w & kSlotFirst)) continue;
+        const uint32_t slot = w & ~kSlotFirst;
+        const uint64_t p = slot / (uint32_t)depth;
+        float s = 0.0f;
+        for (uint32_t d = slot; d < (uint32_t)((p + 1) * (uint64_t)depth); ++d) s += dense[d];
+        records[p0 + p] += s;
+    }
+}
+
+hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
+                                   float* records, uint64_t p0, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(sur_merge_queued_kernel, dim3(grid), dim3(256), 0, s, q, count, dense, depth, records, p0);
+    return hipGetLastError();
 }
 
 hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count, float* dense, uint64_t n,
