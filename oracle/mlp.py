@@ -104,23 +104,21 @@ def _scale(amax):
     return (amax / E4M3_MAX) if amax > 1e-30 else 0.0
 
 
-def forward_e4m3(Ws, bs, X, block=64):
+def forward_e4m3(Ws, bs, X):
     """Forward pass with the FP8 mode's quantization: each hidden layer's weights scaled by
-    max|W| / 448 and rounded to E4M3; each layer's input activations, per block of `block`
-    rows, scaled by their max |a| / 448 and rounded to E4M3; products and sums exact (FP64),
-    then multiplied back by both scales; the output layer unquantized."""
-    X = np.asarray(X, np.float64)
-    out = np.zeros(X.shape[0])
+    max|W| / 448 and rounded to E4M3; each layer's input activations, per row (query), scaled
+    by the row's max |a| / 448 and rounded to E4M3; products and sums exact (FP64), then
+    multiplied back by both scales; the output layer unquantized."""
+    a = np.asarray(X, np.float64)
     wq, ws = [], []
     for W in Ws[:-1]:
         s = _scale(np.abs(W).max())
         ws.append(s)
         wq.append(e4m3_round(W / s) if s > 0 else np.zeros_like(W))
-    for r0 in range(0, X.shape[0], block):
-        a = X[r0:r0 + block]
-        for l in range(len(Ws) - 1):
-            s = _scale(np.abs(a).max())
-            aq = e4m3_round(a / s) if s > 0 else np.zeros_like(a)
-            a = gelu((aq @ wq[l]) * (ws[l] * s) + bs[l])
-        out[r0:r0 + block] = (a @ Ws[-1] + bs[-1])[:, 0]
-    return out
+    for l in range(len(Ws) - 1):
+        amax = np.abs(a).max(axis=1)
+        s = np.where(amax > 1e-30, amax / E4M3_MAX, 0.0)
+        safe = np.where(s > 0, s, 1.0)
+        aq = np.where(s[:, None] > 0, e4m3_round(a / safe[:, None]), 0.0)
+        a = gelu((aq @ wq[l]) * (ws[l] * s)[:, None] + bs[l])
+    return (a @ Ws[-1] + bs[-1])[:, 0]

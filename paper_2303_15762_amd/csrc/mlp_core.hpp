@@ -226,9 +226,12 @@ __device__ __forceinline__ void e4m3_scale(float amax, float& s, float& inv) {
 
 __device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -kE4M3Max), kE4M3Max); }
 
-__device__ __forceinline__ long input_frag8(const float* stage, int nb, int lane, float inv) {
+// The staged input row of a query holds its 10 features, its activation scale at index 14 and
+// the reciprocal at 15 (the fragments read features below 10 only).
+__device__ __forceinline__ long input_frag8(const float* stage, int nb, int lane) {
     const int g = lane >> 4, c = lane & 15;
     const float* row = stage + (16 * nb + c) * 16;
+    const float inv = row[15];
     float v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -251,19 +254,25 @@ __device__ __forceinline__ long act_frag8(const f32x4 (&h)[4][4], int kb, int nb
 __device__ inline float mlp_forward_wave_fp8(const MlpDev8& M, const float* x, float* stage) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
+    // activations are scaled per query (max |a| / 448 over its features), so a query's result
+    // does not depend on the other queries of its batch
     float am = 0.0f;
 #pragma unroll
     for (int f = 0; f < MLP_IN; ++f) am = fmaxf(am, fabsf(x[f]));
-    float s_act, inv_act;
-    e4m3_scale(wave_absmax(am), s_act, inv_act);
+    float s_own, inv_own;
+    e4m3_scale(am, s_own, inv_own);
 #pragma unroll
-    for (int f = 0; f < 16; ++f) stage[lane * 16 + f] = f < MLP_IN ? x[f] : 0.0f;
+    for (int f = 0; f < 16; ++f) stage[lane * 16 + f] = f < MLP_IN ? x[f] : (f == 14 ? s_own : (f == 15 ? inv_own : 0.0f));
     wave_sync_lds();
     f32x4 h[4][4];
+    float s_act[4];   // scale of query 16 nb + (lane & 15), whose outputs this lane holds
     {
         long bin[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) bin[nb] = input_frag8(stage, nb, lane, inv_act);
+        for (int nb = 0; nb < 4; ++nb) {
+            bin[nb] = input_frag8(stage, nb, lane);
+            s_act[nb] = stage[(16 * nb + (lane & 15)) * 16 + 14];
+        }
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const long a = M.wf[fwd_frag(0, mt, 0) * 64 + lane];
@@ -278,19 +287,25 @@ __device__ inline float mlp_forward_wave_fp8(const MlpDev8& M, const float* x, f
 #pragma unroll
     for (int layer = 0; layer < 4; ++layer) {
         if (layer > 0) {
-            am = 0.0f;
+            // per query: the 16 of its features in this lane, then the lanes c, c + 16, c + 32,
+            // c + 48 that hold the rest
+            float inv_act[4];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+            for (int nb = 0; nb < 4; ++nb) {
+                float m = 0.0f;
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb)
+                for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) am = fmaxf(am, fabsf(h[mt][nb][i]));
-            e4m3_scale(wave_absmax(am), s_act, inv_act);
+                    for (int i = 0; i < 4; ++i) m = fmaxf(m, fabsf(h[mt][nb][i]));
+                m = fmaxf(m, __shfl_xor(m, 16));
+                m = fmaxf(m, __shfl_xor(m, 32));
+                e4m3_scale(m, s_act[nb], inv_act[nb]);
+            }
             long b[2][4];
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) b[kb][nb] = act_frag8(h, kb, nb, inv_act);
+                for (int nb = 0; nb < 4; ++nb) b[kb][nb] = act_frag8(h, kb, nb, inv_act[nb]);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const long a0 = M.wf[fwd_frag(layer, mt, 0) * 64 + lane];
@@ -304,16 +319,17 @@ __device__ inline float mlp_forward_wave_fp8(const MlpDev8& M, const float* x, f
             }
         }
         // dequantize, bias, activation; the layer's output features of this lane are 16 mt + 4 g + i
-        const float deq = M.wscale[layer] * s_act;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             float bb[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) bb[i] = M.bias[layer * 64 + 16 * mt + 4 * g + i];
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb)
+            for (int nb = 0; nb < 4; ++nb) {
+                const float deq = M.wscale[layer] * s_act[nb];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) h[mt][nb][i] = gelu_f(h[mt][nb][i] * deq + bb[i]);
+            }
         }
     }
     float part[4];

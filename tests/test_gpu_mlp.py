@@ -68,7 +68,7 @@ def test_forward_matches_oracle(env):
 
 
 def test_forward_fp8_matches_e4m3_oracle(env):
-    """FP8 mode: weights per layer and activations per 64 rows quantized to E4M3 (scale max / 448),
+    """FP8 mode: weights per layer and activations per row quantized to E4M3 (scale max / 448),
     FP32 accumulation.  The oracle's quantized forward pass in FP64 is the reference; a value
     that sits on an E4M3 rounding boundary can round the other way from FP32 inputs, so the
     bound is that of the BF16 path."""
