@@ -224,7 +224,7 @@ int gr_workspace_paths(const gr_ctx* ctx, void* workspace, float** paths_dev);
  *   image     : device float [n_lambda][height][width]; contributions are ADDED to it.
  *   stats     : optional; when given the call synchronises the stream and fills it.
  * Surrogate modes: in-domain rough-surface measurements are queued by the trace kernel and
- * evaluated by one batched matrix-core pass per launch of at most 64M paths and 2^29 (path,
+ * evaluated by one batched matrix-core pass per launch of at most 256M paths and 2^30 (path,
  * interaction) slots (the workspace
  * holds that launch's queue, 32 B per path and interaction, and one float per slot); the
  * results are added to the path records in a fixed order.

@@ -97,13 +97,14 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack; }
 
 // The learned-p_w path renders in launches of at most this many paths: each launch queues at
-// most one query per path and interaction (32 B) and owns one result float per slot (slot
-// numbers are 32-bit: 2^26 paths x 64 interactions at most).  Each launch ends in a tail where
-// waves wait for their slowest path, so launches are made as large as the memory allows.
-constexpr uint64_t kSurChunk = 1ull << 26;
-// ... and at most this many (path, interaction) slots per launch (16 GB of queued queries),
-// which bounds deep paths.
-constexpr uint64_t kSurSlots = 1ull << 29;
+// most one query per path and interaction (32 B) and owns one result float per slot.  Each
+// launch ends in a tail where waves wait for their slowest path, so launches are made as
+// large as the memory allows.
+constexpr uint64_t kSurChunk = 1ull << 28;
+// ... and at most this many (path, interaction) slots per launch (32 GB of queued queries and
+// 4 GB of results), which bounds deep paths; slot numbers stay below 2^31, the bit above
+// them marks a path's first query.
+constexpr uint64_t kSurSlots = 1ull << 30;
 // The wavefront kernels keep per-path state of a launch of at most this many paths.
 constexpr uint64_t kWfChunk = 1ull << 23;
 

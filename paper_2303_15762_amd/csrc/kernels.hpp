@@ -130,7 +130,7 @@ hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint6
 hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
                                    float* records, uint64_t p0, int grid, hipStream_t s);
 // Bit 31 of a queued query's slot field marks the first query of its path (the one at its
-// lowest interaction); slots stay below 2^29.
+// lowest interaction); slots stay below 2^30.
 constexpr uint32_t kSlotFirst = 0x80000000u;
 int trace_grid_size(int device, bool sur, bool hero = false, bool aniso = false);
 

@@ -90,31 +90,35 @@ def test_surrogate_cost_against_closed_form(trained):
     assert t[1] > 0 and t[0] > 0
 
 
-def test_surrogate_trace_deterministic(trained):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_surrogate_trace_deterministic(trained, mode):
     """The queued network evaluations land in per-(path, interaction) slots that are added to
-    the path records in a fixed order: two renders are bitwise identical."""
+    the path records in a fixed order, and no value depends on the queue order (the FP8
+    network scales activations per query): renders are bitwise identical, whatever order the
+    queries were queued in."""
     R, S, p, hist, torch = trained
     wl = W.mid_terrain(width=64, height=48, spp=8, n_lambda=8)
     R.load_workload(wl)
-    a, sa = R.render_workload(wl, bsdf_mode=1)
-    b, sb = R.render_workload(wl, bsdf_mode=1)
-    assert sa["surrogate_evals"] > 0 and sa["surrogate_evals"] == sb["surrogate_evals"]
-    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    a, sa = R.render_workload(wl, bsdf_mode=mode)
+    for _ in range(3):
+        b, sb = R.render_workload(wl, bsdf_mode=mode)
+        assert sa["surrogate_evals"] > 0 and sa["surrogate_evals"] == sb["surrogate_evals"]
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
 def test_surrogate_deep_paths_in_bounded_launches(trained):
-    """Up to 64 interactions per path: a launch holds at most 2^29 (path, interaction) query
-    slots, i.e. 2^23 paths here, so the 10.5M-path frame runs in two launches.  The image
+    """Up to 64 interactions per path: a launch holds at most 2^30 (path, interaction) query
+    slots, i.e. 2^24 paths here, so the 18.9M-path frame runs in two launches.  The image
     equals the sum of two renders over sample ranges that each fit one launch, and matches
     the oracle on sampled pixels."""
     import dataclasses
     R, S, p, hist, torch = trained
-    wl = dataclasses.replace(W.mid_terrain(width=512, height=512, spp=5, n_lambda=8), max_depth=64)
+    wl = dataclasses.replace(W.mid_terrain(width=512, height=512, spp=9, n_lambda=8), max_depth=64)
     R.load_workload(wl)
     img, st = R.render_workload(wl, bsdf_mode=1)
-    assert st["paths"] == 512 * 512 * 5 * 8 and st["nonfinite"] == 0 and st["surrogate_evals"] > 0
-    a, _ = R.render_workload(wl, bsdf_mode=1, spp_begin=0, spp_count=3)
-    b, _ = R.render_workload(wl, bsdf_mode=1, spp_begin=3, spp_count=2)
+    assert st["paths"] == 512 * 512 * 9 * 8 and st["nonfinite"] == 0 and st["surrogate_evals"] > 0
+    a, _ = R.render_workload(wl, bsdf_mode=1, spp_begin=0, spp_count=5)
+    b, _ = R.render_workload(wl, bsdf_mode=1, spp_begin=5, spp_count=4)
     g = img.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose((a + b).cpu().numpy(), g, rtol=1e-5, atol=1e-9 * np.abs(g).max())
     rng = np.random.default_rng(21)
