@@ -117,6 +117,11 @@ struct WsLayout {
 bool wavefront_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_WAVEFRONT) != 0; }
 bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
 bool aniso_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_ANISO) != 0; }
+// one wavelength per path with the closed-form p_w in the persistent kernel: shadow rays go
+// through a queue of their own
+bool shadow_queue_of(const gr_trace_opts* o) {
+    return !wavefront_of(o) && !hero_of(o) && o->bsdf_mode == GR_BSDF_PLAIN;
+}
 
 // Per-path wavefront arrays in this order, each padded to 256 B (element sizes in bytes).
 constexpr int kWfArrays = 27;
@@ -400,9 +405,10 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     L.queue = L.wf + L.wf_bytes;
     L.dense = L.queue;
     L.total = L.queue;
-    if (o->bsdf_mode != GR_BSDF_PLAIN) {
+    if (o->bsdf_mode != GR_BSDF_PLAIN || shadow_queue_of(o)) {
         const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
-        L.dense = L.queue + align256((size_t)slots * grw::kSurQueryBytes);
+        const size_t entry = o->bsdf_mode != GR_BSDF_PLAIN ? grw::kSurQueryBytes : grw::kShadowQueryBytes;
+        L.dense = L.queue + align256((size_t)slots * entry);
         L.total = L.dense + align256((size_t)slots * sizeof(float));
     }
     return L;
@@ -527,9 +533,10 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.ovf_n = overflow_entries(c, o);
     a.ovf = a.ovf_n ? reinterpret_cast<int*>(base + WL.ovf) : nullptr;
     const bool defer = o->bsdf_mode != GR_BSDF_PLAIN;
+    const bool shq = shadow_queue_of(o);
     const bool fp8 = o->bsdf_mode == GR_BSDF_SURROGATE_FP8;
-    a.sq = defer ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
-    float* dense = defer ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
+    a.sq = defer || shq ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
+    float* dense = defer || shq ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
     a.sdense = dense;
 
     GR_HIP(c, hipSetDevice(c->device));
@@ -558,6 +565,20 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
                 GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
                 GR_HIP(c, grw::launch_sur_merge(dense, D, a.records, p0, pn, c->stream));
             }
+        }
+        a.n_paths = total;
+    } else if (shq) {
+        // launches of at most WL.chunk paths: trace (measurement values to the path's slots,
+        // shadow rays queued), the queued shadow rays in full waves, records from the slots
+        const int D = o->max_depth;
+        for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
+            const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
+            a.path_begin = p0;
+            a.n_paths = pn;
+            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, 0, c->stream));
+            GR_HIP(c, grw::launch_trace(a, grid, c->stream));
+            GR_HIP(c, grw::launch_shadow(a, grid, c->stream));
+            GR_HIP(c, grw::launch_shadow_merge(dense, D, a.records, p0, pn, a.inv_spp_norm, a.stats, c->stream));
         }
         a.n_paths = total;
     } else if (!defer) {

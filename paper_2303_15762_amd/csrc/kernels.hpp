@@ -73,7 +73,8 @@ struct TraceArgs {
     uint64_t seed;
     int bsdf_mode;
     SurrogateDev sur;
-    uint4* sq;                       // deferred learned-p_w queries, 2 uint4 each, or null
+    uint4* sq;                       // deferred learned-p_w queries (2 uint4 each) or queued
+                                     // shadow rays (3 uint4 each), or null
     float* sdense;                   // their result slots [paths of the launch][max_depth]; the
                                      // persistent kernel zeroes a path's slots when it starts it
     unsigned long long* sq_count;
@@ -127,6 +128,12 @@ hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* s
                               hipStream_t s);
 // records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
 hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
+hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s);
+hipError_t launch_shadow_merge(const float* val, int depth, float* records, uint64_t p0, uint64_t n,
+                               float inv_spp_norm, unsigned long long* stats, hipStream_t s);
+// a queued shadow ray: mean position (3 doubles), travel direction of the light, emitter
+// distance, triangle left, slot
+constexpr int kShadowQueryBytes = 48;
 hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
                                    float* records, uint64_t p0, int grid, hipStream_t s);
 // Bit 31 of a queued query's slot field marks the first query of its path (the one at its

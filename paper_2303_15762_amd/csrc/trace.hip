@@ -247,6 +247,10 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
 
     const SensorDev& sen = A.sensor;
     const uint32_t Wd = (uint32_t)sen.W, Hd = (uint32_t)sen.H, nl = (uint32_t)A.nl;
+    // SHQ: shadow rays are queued for shadow_kernel (full waves of shadow rays instead of the
+    // few lanes of a wave that measure at a vertex); a path's measurement values wait in its
+    // (path, interaction) slots, and a merge writes the record once visibility is known
+    constexpr bool SHQ = !DEFER && !HERO;
 
     bool live = false, exhausted = false;
     uint64_t idx = 0, pid = 0;
@@ -348,9 +352,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         }
                         alpha = 1.0f;
                         contrib = 0.0f;
-                        if constexpr (DEFER) {
-                            // clear the path's result slots: the merge sums them from the
-                            // path's first queued interaction on
+                        if constexpr (DEFER || SHQ) {
+                            // clear the path's result slots: the merges sum them in depth order
                             float* ds = A.sdense + (idx - A.path_begin) * (uint64_t)A.max_depth;
                             for (int dd = 0; dd < A.max_depth; ++dd) ds[dd] = 0.0f;
                             qfirst = true;
@@ -493,7 +496,34 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                         }
                     }
-                    if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
+                    if constexpr (SHQ) {
+                      if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
+                        // the measurement value now, its visibility later (shadow_kernel)
+                        ev |= 1u << EV_SHADOW;
+                        const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
+                        const float scale = alpha * L.power * (float)A.nsrc;
+                        const float v = scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, -k * dx, -k * dy, sxx,
+                                                         syy, sxy, 1.0f, 0.0f);
+                        const bool want = v != 0.0f;
+                        const unsigned long long qm = __ballot(want);
+                        if (want) {
+                            const int leader = __ffsll((long long)qm) - 1;
+                            unsigned long long qb = 0;
+                            if (lane == leader) qb = atomicAdd(A.sq_count, (unsigned long long)__popcll(qm));
+                            qb = __shfl(qb, leader);
+                            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+                            const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
+                            A.sdense[slot] = v;
+                            uint4* q = A.sq + 3 * (qb + r);
+                            const unsigned long long px = __double_as_longlong(P.x), py = __double_as_longlong(P.y),
+                                                     pz = __double_as_longlong(P.z);
+                            q[0] = make_uint4((uint32_t)px, (uint32_t)(px >> 32), (uint32_t)py, (uint32_t)(py >> 32));
+                            q[1] = make_uint4((uint32_t)pz, (uint32_t)(pz >> 32), __float_as_uint(om.x), __float_as_uint(om.y));
+                            q[2] = make_uint4(__float_as_uint(om.z), __float_as_uint(tmax_s), (uint32_t)prev, slot);
+                        }
+                      }
+                    } else if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
                         ev |= 1u << EV_SHADOW;
                         RayT sray;
                         ray_setup(sray, P, -1.0f * om);
@@ -629,7 +659,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     }
                     A.records[rb + (uint64_t)i * G] = val;
                 }
-            } else {
+            } else if constexpr (!SHQ) {
                 float val = contrib * A.inv_spp_norm;
                 if (!isfinite(val)) {
                     ev |= 1u << EV_NONFINITE;
@@ -656,6 +686,66 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         atomicAdd(A.stats + ST_SUR, w_cnt[EV_SUR]);
         atomicAdd(A.stats + ST_FALLBACK, w_cnt[EV_FALLBACK]);
     }
+}
+
+// Shadow rays queued by the trace kernel (48 B each: mean position in double, the direction
+// the light travels, the emitter distance, the triangle the ray leaves, the slot), one per
+// lane in full waves.  An occluded ray clears the measurement value in its slot.  The grid is
+// the trace kernel's, so the traversal-stack overflow region fits.
+template <int STACK>
+__global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
+    __shared__ int lds_stack[4][STACK][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
+    const size_t ostride = (size_t)gridDim.x * 256;
+    int* ovf = A.ovf ? A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
+    const uint64_t n = *A.sq_count;
+    uint32_t c_nodes = 0, c_tris = 0;
+    for (uint64_t base = ((uint64_t)blockIdx.x * 4 + wv) * 64; base < n; base += (uint64_t)gridDim.x * 256) {
+        const uint64_t i = base + lane;
+        if (i < n) {
+            const uint4* q = A.sq + 3 * i;
+            const uint4 a = q[0], b = q[1], c = q[2];
+            const d3 P = d3{__longlong_as_double((long long)(((uint64_t)a.y << 32) | a.x)),
+                            __longlong_as_double((long long)(((uint64_t)a.w << 32) | a.z)),
+                            __longlong_as_double((long long)(((uint64_t)b.y << 32) | b.x))};
+            const f3 om = mk3(__uint_as_float(b.z), __uint_as_float(b.w), __uint_as_float(c.x));
+            const float tminP = 1e-7f * (1.0f + maxabs3(to_f3(P)));
+            RayT sray;
+            ray_setup(sray, P, -1.0f * om);
+            float tm = __uint_as_float(c.y), su, sv;
+            const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk, A.lds_cap, ovf, ostride,
+                                            c_nodes, c_tris, su, sv);
+            if (occ >= 0) A.sdense[c.w] = 0.0f;
+        }
+    }
+    const unsigned long long s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris);
+    if (lane == 0) {
+        atomicAdd(A.stats + ST_NODES, s8);
+        atomicAdd(A.stats + ST_TRIS, s9);
+    }
+}
+
+// Records of a launch's paths: the measurement values of each path's interactions summed in
+// depth order (the order in which the path would have added them itself).
+__global__ __launch_bounds__(256) void shadow_merge_kernel(const float* __restrict__ val, int depth,
+                                                           float* __restrict__ records, uint64_t p0, uint64_t n,
+                                                           float inv_spp_norm, unsigned long long* stats) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        float s = 0.0f;
+        for (int d = 0; d < depth; ++d) s += val[i * depth + d];
+        float v = s * inv_spp_norm;
+        if (!isfinite(v)) {
+            bad = true;
+            v = 0.0f;
+        }
+        records[p0 + i] = v;
+    }
+    const unsigned long long nb = __popcll(__ballot(bad));
+    if ((threadIdx.x & 63) == 0 && nb) atomicAdd(stats + ST_NONFINITE, nb);
 }
 
 // Per-pixel sum of the path records in sample order (deterministic).
@@ -746,6 +836,19 @@ __global__ __launch_bounds__(256) void sur_merge_queued_kernel(const uint4* __re
 hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
                                    float* records, uint64_t p0, int grid, hipStream_t s) {
     hipLaunchKernelGGL(sur_merge_queued_kernel, dim3(grid), dim3(256), 0, s, q, count, dense, depth, records, p0);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((shadow_kernel<kLdsStack>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_shadow_merge(const float* val, int depth, float* records, uint64_t p0, uint64_t n,
+                               float inv_spp_norm, unsigned long long* stats, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(shadow_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, depth, records,
+                       p0, n, inv_spp_norm, stats);
     return hipGetLastError();
 }
 
