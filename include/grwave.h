@@ -163,14 +163,17 @@ typedef struct {
     uint64_t paths;
     uint64_t segments;          /* closest-hit queries, escaping ones included */
     uint64_t shadow_rays;       /* any-hit queries of next-event estimation */
-    uint64_t surrogate_evals;
+    uint64_t surrogate_evals;   /* learned-p_w queries evaluated by the network (the persistent
+                                   kernel queues them before their shadow rays are traced, so
+                                   occluded ones count too) */
     uint64_t fallbacks;         /* surrogate mode queries outside the trained domain */
     uint64_t evanescent;        /* paths ended by an evanescent continuation */
     uint64_t backfacing;        /* paths ended at a back-facing shading normal */
     uint64_t nonfinite;         /* non-finite contributions dropped */
     uint64_t node_visits;       /* BVH nodes fetched (closest-hit and any-hit) */
     uint64_t tri_tests;         /* triangle tests (closest-hit and any-hit) */
-    float ms;                   /* device time of the path-tracing kernel */
+    float ms;                   /* device time of the path-tracing kernels (trace, network
+                                   pass, shadow rays, record merge) */
     float ms_reduce;            /* device time of the per-pixel reduction */
 } gr_stats;
 
@@ -223,11 +226,13 @@ int gr_workspace_paths(const gr_ctx* ctx, void* workspace, float** paths_dev);
  *   workspace : device, >= gr_workspace_size bytes.
  *   image     : device float [n_lambda][height][width]; contributions are ADDED to it.
  *   stats     : optional; when given the call synchronises the stream and fills it.
- * Surrogate modes: in-domain rough-surface measurements are queued by the trace kernel and
- * evaluated by one batched matrix-core pass per launch of at most 256M paths and 2^30 (path,
- * interaction) slots (the workspace
- * holds that launch's queue, 32 B per path and interaction, and one float per slot); the
- * results are added to the path records in a fixed order.
+ * One wavelength per path (the persistent kernel): the path kernel stores each measurement
+ * value in its (path, interaction) slot and queues the measurement's shadow ray (48 B); a
+ * shadow-ray kernel traces the queue in full waves and clears the slots of occluded ones, and
+ * a merge sums each path's slots in depth order into its record.  Surrogate modes also queue
+ * in-domain rough-surface measurements (32 B each) for one batched matrix-core pass, which
+ * writes their slots before the shadow rays are traced.  Launches hold at most 256M paths and
+ * 2^30 slots within 52 GiB of queues and slots (the workspace holds one launch's).
  * Same options and seed give a bitwise identical image. */
 int gr_trace(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_trace_opts* opts,
              void* workspace, size_t workspace_bytes, float* image, gr_stats* stats);

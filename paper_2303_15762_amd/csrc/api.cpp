@@ -101,15 +101,17 @@ int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_
 // launch ends in a tail where waves wait for their slowest path, so launches are made as
 // large as the memory allows.
 constexpr uint64_t kSurChunk = 1ull << 28;
-// ... and at most this many (path, interaction) slots per launch (32 GB of queued queries and
-// 4 GB of results), which bounds deep paths; slot numbers stay below 2^31, the bit above
-// them marks a path's first query.
+// ... and at most this many (path, interaction) slots per launch, which bounds deep paths
+// (slot numbers stay below 2^30) ...
 constexpr uint64_t kSurSlots = 1ull << 30;
+// ... within this many bytes of queued network queries, queued shadow rays and results (2^30
+// slots of a shadow ray and a result; the learned p_w adds a query per slot).
+constexpr uint64_t kQueueBytes = (1ull << 30) * 52;
 // The wavefront kernels keep per-path state of a launch of at most this many paths.
 constexpr uint64_t kWfChunk = 1ull << 23;
 
 struct WsLayout {
-    size_t records = 0, ovf = 0, wf = 0, queue = 0, dense = 0, total = 0;
+    size_t records = 0, ovf = 0, wf = 0, queue = 0, shadow = 0, dense = 0, total = 0;
     uint64_t chunk = 0;
     size_t wf_bytes = 0;
 };
@@ -117,11 +119,8 @@ struct WsLayout {
 bool wavefront_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_WAVEFRONT) != 0; }
 bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
 bool aniso_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_ANISO) != 0; }
-// one wavelength per path with the closed-form p_w in the persistent kernel: shadow rays go
-// through a queue of their own
-bool shadow_queue_of(const gr_trace_opts* o) {
-    return !wavefront_of(o) && !hero_of(o) && o->bsdf_mode == GR_BSDF_PLAIN;
-}
+// one wavelength per path in the persistent kernel: shadow rays go through a queue of their own
+bool shadow_queue_of(const gr_trace_opts* o) { return !wavefront_of(o) && !hero_of(o); }
 
 // Per-path wavefront arrays in this order, each padded to 256 B (element sizes in bytes).
 constexpr int kWfArrays = 27;
@@ -399,18 +398,18 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
-    const uint64_t sur_chunk = std::min<uint64_t>(kSurChunk, kSurSlots / (uint64_t)std::max(o->max_depth, 1));
+    const bool defer = o->bsdf_mode != GR_BSDF_PLAIN, shq = shadow_queue_of(o);
+    // bytes per (path, interaction) slot: a network query, a shadow ray, the result float
+    const uint64_t slot_bytes = (defer ? grw::kSurQueryBytes : 0) + (shq ? grw::kShadowQueryBytes : 0) + 4;
+    const uint64_t slots_max = std::min<uint64_t>(kSurSlots, kQueueBytes / slot_bytes);
+    const uint64_t sur_chunk = std::min<uint64_t>(kSurChunk, slots_max / (uint64_t)std::max(o->max_depth, 1));
     L.chunk = std::min<uint64_t>(n, wavefront_of(o) ? kWfChunk : sur_chunk);
     L.wf_bytes = wavefront_of(o) ? wf_bytes(L.chunk) : 0;
     L.queue = L.wf + L.wf_bytes;
-    L.dense = L.queue;
-    L.total = L.queue;
-    if (o->bsdf_mode != GR_BSDF_PLAIN || shadow_queue_of(o)) {
-        const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
-        const size_t entry = o->bsdf_mode != GR_BSDF_PLAIN ? grw::kSurQueryBytes : grw::kShadowQueryBytes;
-        L.dense = L.queue + align256((size_t)slots * entry);
-        L.total = L.dense + align256((size_t)slots * sizeof(float));
-    }
+    const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
+    L.shadow = L.queue + (defer ? align256((size_t)slots * grw::kSurQueryBytes) : 0);
+    L.dense = L.shadow + (shq ? align256((size_t)slots * grw::kShadowQueryBytes) : 0);
+    L.total = L.dense + (defer || shq ? align256((size_t)slots * sizeof(float)) : 0);
     return L;
 }
 }  // namespace
@@ -527,6 +526,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     const uint64_t total = a.n_paths;
     a.counter = reinterpret_cast<unsigned long long*>(base);
     a.sq_count = reinterpret_cast<unsigned long long*>(base + 128);
+    a.shq_count = reinterpret_cast<unsigned long long*>(base + 2048);
     a.stats = reinterpret_cast<unsigned long long*>(base + 256);
     a.records = reinterpret_cast<float*>(base + WL.records);
     a.lds_cap = lds_cap_for(o);
@@ -535,7 +535,8 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     const bool defer = o->bsdf_mode != GR_BSDF_PLAIN;
     const bool shq = shadow_queue_of(o);
     const bool fp8 = o->bsdf_mode == GR_BSDF_SURROGATE_FP8;
-    a.sq = defer || shq ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
+    a.sq = defer ? reinterpret_cast<uint4*>(base + WL.queue) : nullptr;
+    a.shq = shq ? reinterpret_cast<uint4*>(base + WL.shadow) : nullptr;
     float* dense = defer || shq ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
     a.sdense = dense;
 
@@ -559,7 +560,8 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
             w.cnt = reinterpret_cast<unsigned int*>(base + 192);
             a.path_begin = p0;
             a.n_paths = pn;
-            if (defer) GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, pn * (uint64_t)D, c->stream));
+            if (defer)
+                GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, nullptr, dense, pn * (uint64_t)D, c->stream));
             GR_HIP(c, grw::launch_wavefront(a, w, c->grid_wf, c->grid_work, c->stream));
             if (defer) {
                 GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
@@ -569,36 +571,26 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
         a.n_paths = total;
     } else if (shq) {
         // launches of at most WL.chunk paths: trace (measurement values to the path's slots,
-        // shadow rays queued), the queued shadow rays in full waves, records from the slots
+        // learned-p_w queries and shadow rays queued; each path clears its own slots), one
+        // batched network pass over the query queue (its results to their slots), the queued
+        // shadow rays in full waves (an occluded one clears its slot), records from the slots
         const int D = o->max_depth;
         for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
             const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
             a.path_begin = p0;
             a.n_paths = pn;
-            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, 0, c->stream));
+            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, a.shq_count, dense, 0, c->stream));
             GR_HIP(c, grw::launch_trace(a, grid, c->stream));
+            if (defer)
+                GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
             GR_HIP(c, grw::launch_shadow(a, grid, c->stream));
             GR_HIP(c, grw::launch_shadow_merge(dense, D, a.records, p0, pn, a.inv_spp_norm, a.stats, c->stream));
         }
         a.n_paths = total;
-    } else if (!defer) {
+    } else {
+        // hero-wavelength paths: one launch, shadow rays traced in the path loop
         a.path_begin = 0;
         if (total > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
-    } else {
-        // launches of at most WL.chunk paths: trace (queries queued; each path clears its own
-        // result slots), one batched network pass over the queue, results added to the path
-        // records in a fixed order by the paths' first queries
-        const int D = o->max_depth;
-        for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
-            const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
-            a.path_begin = p0;
-            a.n_paths = pn;
-            GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, dense, 0, c->stream));
-            GR_HIP(c, grw::launch_trace(a, grid, c->stream));
-            GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
-            GR_HIP(c, grw::launch_sur_merge_queued(a.sq, a.sq_count, dense, D, a.records, p0, c->grid_batch, c->stream));
-        }
-        a.n_paths = total;
     }
     if (st) GR_HIP(c, hipEventRecord(ev[1], c->stream));
     if (total > 0)

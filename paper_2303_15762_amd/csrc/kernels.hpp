@@ -48,8 +48,9 @@ struct SurrogateDev {
 };
 
 // One deferred learned-p_w query, 32 bytes: the 10 network inputs as bfloat16 pairs (the
-// network rounds its inputs to bfloat16 anyway), the contribution scale (already divided by
-// the sample count), log of the lobe peak, and the (path, depth) slot of the result.
+// network rounds its inputs to bfloat16 anyway), the contribution scale (the wavefront form
+// divides it by the sample count; in the persistent kernel's launches the merge does), log of
+// the lobe peak, and the (path, depth) slot of the result.
 constexpr int kSurQueryBytes = 32;
 
 struct TraceArgs {
@@ -73,11 +74,13 @@ struct TraceArgs {
     uint64_t seed;
     int bsdf_mode;
     SurrogateDev sur;
-    uint4* sq;                       // deferred learned-p_w queries (2 uint4 each) or queued
-                                     // shadow rays (3 uint4 each), or null
-    float* sdense;                   // their result slots [paths of the launch][max_depth]; the
-                                     // persistent kernel zeroes a path's slots when it starts it
+    uint4* sq;                       // deferred learned-p_w queries (2 uint4 each), or null
     unsigned long long* sq_count;
+    uint4* shq;                      // queued shadow rays (3 uint4 each), or null
+    unsigned long long* shq_count;
+    float* sdense;                   // measurement values by (path, interaction) slot
+                                     // [paths of the launch][max_depth]; the persistent kernel
+                                     // zeroes a path's slots when it starts it
     float* records;                  // [n_paths]
     int* ovf;                        // traversal stack overflow [ovf_n][grid * 256], or null
     uint32_t ovf_n;                  // overflow entries per lane
@@ -123,9 +126,10 @@ int wavefront_trav_grid(int device);
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
                          uint32_t nl, hipStream_t s);
-// Zero the path dispenser, the query count and n floats of per-(path, depth) results.
-hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count, float* dense, uint64_t n,
-                              hipStream_t s);
+// Zero the path dispenser, the query and shadow-ray counts (shq_count may be null) and n
+// floats of per-(path, depth) results.
+hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count,
+                              unsigned long long* shq_count, float* dense, uint64_t n, hipStream_t s);
 // records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
 hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
 hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s);
@@ -134,11 +138,6 @@ hipError_t launch_shadow_merge(const float* val, int depth, float* records, uint
 // a queued shadow ray: mean position (3 doubles), travel direction of the light, emitter
 // distance, triangle left, slot
 constexpr int kShadowQueryBytes = 48;
-hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
-                                   float* records, uint64_t p0, int grid, hipStream_t s);
-// Bit 31 of a queued query's slot field marks the first query of its path (the one at its
-// lowest interaction); slots stay below 2^30.
-constexpr uint32_t kSlotFirst = 0x80000000u;
 int trace_grid_size(int device, bool sur, bool hero = false, bool aniso = false);
 
 // Batch p_w evaluation (trace.hip).

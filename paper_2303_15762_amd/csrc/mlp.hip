@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const Ml
             bf16_unpair(b.x, x[8], x[9]);
             scale = __uint_as_float(b.y);
             logpeak = __uint_as_float(b.z);
-            slot = b.w & ~kSlotFirst;
+            slot = b.w;
         }
         const float y = FP8 ? mlp_forward_wave_fp8(M8, x, stage[wv]) : mlp_forward_wave(M, x, stage[wv], nullptr);
         if (i < n) {

@@ -249,16 +249,17 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     const uint32_t Wd = (uint32_t)sen.W, Hd = (uint32_t)sen.H, nl = (uint32_t)A.nl;
     // SHQ: shadow rays are queued for shadow_kernel (full waves of shadow rays instead of the
     // few lanes of a wave that measure at a vertex); a path's measurement values wait in its
-    // (path, interaction) slots, and a merge writes the record once visibility is known
-    constexpr bool SHQ = !DEFER && !HERO;
+    // (path, interaction) slots, and a merge writes the record once visibility is known.
+    // DEFER (learned p_w) queues in-domain rough measurements for the batched network, whose
+    // results land in the same slots before the shadow rays are traced.
+    constexpr bool SHQ = !HERO;
 
     bool live = false, exhausted = false;
     uint64_t idx = 0, pid = 0;
     int depth = 0, prev = -1;
     d3 o = d3{0.0, 0.0, 0.0};
     f3 d = mk3(0, 0, 1);
-    float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, contrib = 0.0f, k = 1.0f;
-    bool qfirst = true;   // DEFER: the path has queued no learned-p_w query yet
+    float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, k = 1.0f;
     AnisoRay ar;   // ANISO: the ray's second moments (beta2, rho unused)
     if constexpr (ANISO) aniso_iso(ar, 1.0f);
     // hero-wavelength members: wavenumber, beta^2, rho, T = f / p_h, R = p / p_h, estimate
@@ -351,12 +352,10 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                         }
                         alpha = 1.0f;
-                        contrib = 0.0f;
-                        if constexpr (DEFER || SHQ) {
-                            // clear the path's result slots: the merges sum them in depth order
+                        if constexpr (SHQ) {
+                            // clear the path's result slots: the merge sums them in depth order
                             float* ds = A.sdense + (idx - A.path_begin) * (uint64_t)A.max_depth;
                             for (int dd = 0; dd < A.max_depth; ++dd) ds[dd] = 0.0f;
-                            qfirst = true;
                         }
                         depth = 0;
                         prev = -1;
@@ -501,21 +500,50 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         // the measurement value now, its visibility later (shadow_kernel)
                         ev |= 1u << EV_SHADOW;
                         const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
+                        const float kox = -k * dx, koy = -k * dy;
                         const float scale = alpha * L.power * (float)A.nsrc;
-                        const float v = scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, -k * dx, -k * dy, sxx,
-                                                         syy, sxy, 1.0f, 0.0f);
-                        const bool want = v != 0.0f;
+                        const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
+                        // e: 0 closed form, 1 queued for the network, 2 more than 8 lobe widths
+                        // from the lobe (p_w taken as 0)
+                        int e = 0;
+                        if (DEFER && m.kind == MAT_ROUGH) {
+                            const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
+                            float sx[MLP_IN], slp;
+                            e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sx, slp);
+                            if (e == 0) ev |= 1u << EV_FALLBACK;
+                            // append the query (one atomic per wave); every (path, depth) appends
+                            // at most once, so the queue is sized for the launch's slots
+                            const bool wq = e == 1;
+                            const unsigned long long nm = __ballot(wq);
+                            if (wq) {
+                                ev |= 1u << EV_SUR;
+                                const int leader = __ffsll((long long)nm) - 1;
+                                unsigned long long nb = 0;
+                                if (lane == leader) nb = atomicAdd(A.sq_count, (unsigned long long)__popcll(nm));
+                                nb = __shfl(nb, leader);
+                                const uint32_t r = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(nm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nm, 0u));
+                                uint4* q = A.sq + 2 * (nb + r);
+                                q[0] = make_uint4(bf16_pair(sx[0], sx[1]), bf16_pair(sx[2], sx[3]),
+                                                  bf16_pair(sx[4], sx[5]), bf16_pair(sx[6], sx[7]));
+                                q[1] = make_uint4(bf16_pair(sx[8], sx[9]), __float_as_uint(scale * m.refl),
+                                                  __float_as_uint(slp), slot);
+                            }
+                        }
+                        const float v = e == 0 ? scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy,
+                                                                  sxx, syy, sxy, 1.0f, 0.0f)
+                                               : 0.0f;
+                        const bool want = v != 0.0f || e == 1;
                         const unsigned long long qm = __ballot(want);
                         if (want) {
                             const int leader = __ffsll((long long)qm) - 1;
                             unsigned long long qb = 0;
-                            if (lane == leader) qb = atomicAdd(A.sq_count, (unsigned long long)__popcll(qm));
+                            if (lane == leader) qb = atomicAdd(A.shq_count, (unsigned long long)__popcll(qm));
                             qb = __shfl(qb, leader);
                             const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
-                            const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
-                            A.sdense[slot] = v;
-                            uint4* q = A.sq + 3 * (qb + r);
+                            if (e == 0) A.sdense[slot] = v;
+                            uint4* q = A.shq + 3 * (qb + r);
                             const unsigned long long px = __double_as_longlong(P.x), py = __double_as_longlong(P.y),
                                                      pz = __double_as_longlong(P.z);
                             q[0] = make_uint4((uint32_t)px, (uint32_t)(px >> 32), (uint32_t)py, (uint32_t)(py >> 32));
@@ -524,14 +552,13 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         }
                       }
                     } else if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
+                        // hero-wavelength paths trace their shadow rays in the path loop
                         ev |= 1u << EV_SHADOW;
                         RayT sray;
                         ray_setup(sray, P, -1.0f * om);
                         float tm = tmax_s, su, sv;
                         const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, su, sv);
-                        if (occ >= 0) {
-                            // occluded
-                        } else if constexpr (HERO) {
+                        if (occ < 0) {
                             // members: emitter-sampling density of om relative to the hero's
                             // (Gaussian angular spectrum N(k u_t; 0, rc^-2 I) k^2), then the
                             // balance-heuristic estimate of each
@@ -561,45 +588,6 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                                     if (j == i) macc[j] += add;
                                 }
                             }
-                        } else {
-                            const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
-                            const float kox = -k * dx, koy = -k * dy;
-                            const float scale = alpha * L.power * (float)A.nsrc;
-                            int e = 0;
-                            if (DEFER && m.kind == MAT_ROUGH) {
-                                const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
-                                float sx[MLP_IN], slp;
-                                e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sx, slp);
-                                if (e == 0) ev |= 1u << EV_FALLBACK;
-                                // append the query (one atomic per wave); every (path, depth)
-                                // appends at most once, so the queue and the result slots are
-                                // sized for the launch's paths x max_depth
-                                const bool want = e == 1;
-                                const unsigned long long qm = __ballot(want);
-                                if (want) {
-                                    ev |= 1u << EV_SUR;
-                                    const int leader = __ffsll((long long)qm) - 1;
-                                    unsigned long long qb = 0;
-                                    if (lane == leader) qb = atomicAdd(A.sq_count, (unsigned long long)__popcll(qm));
-                                    qb = __shfl(qb, leader);
-                                    const uint32_t r = __builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(qm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
-                                    uint4* q = A.sq + 2 * (qb + r);
-                                    const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth) |
-                                                          (qfirst ? kSlotFirst : 0u);
-                                    qfirst = false;
-                                    q[0] = make_uint4(bf16_pair(sx[0], sx[1]), bf16_pair(sx[2], sx[3]),
-                                                      bf16_pair(sx[4], sx[5]), bf16_pair(sx[6], sx[7]));
-                                    q[1] = make_uint4(bf16_pair(sx[8], sx[9]),
-                                                      __float_as_uint(scale * m.refl * A.inv_spp_norm),
-                                                      __float_as_uint(slp), slot);
-                                }
-                            }
-                            if (e == 0) {
-                                contrib += scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy,
-                                                            sxx, syy, sxy, 1.0f, 0.0f);
-                            }
-                            // e == 2: more than 8 lobe widths from the lobe, p_w taken as 0
                         }
                     }
                 }
@@ -659,13 +647,6 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     }
                     A.records[rb + (uint64_t)i * G] = val;
                 }
-            } else if constexpr (!SHQ) {
-                float val = contrib * A.inv_spp_norm;
-                if (!isfinite(val)) {
-                    ev |= 1u << EV_NONFINITE;
-                    val = 0.0f;
-                }
-                A.records[idx] = val;
             }
             live = false;
         }
@@ -700,12 +681,12 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
     lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
     const size_t ostride = (size_t)gridDim.x * 256;
     int* ovf = A.ovf ? A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
-    const uint64_t n = *A.sq_count;
+    const uint64_t n = *A.shq_count;
     uint32_t c_nodes = 0, c_tris = 0;
     for (uint64_t base = ((uint64_t)blockIdx.x * 4 + wv) * 64; base < n; base += (uint64_t)gridDim.x * 256) {
         const uint64_t i = base + lane;
         if (i < n) {
-            const uint4* q = A.sq + 3 * i;
+            const uint4* q = A.shq + 3 * i;
             const uint4 a = q[0], b = q[1], c = q[2];
             const d3 P = d3{__longlong_as_double((long long)(((uint64_t)a.y << 32) | a.x)),
                             __longlong_as_double((long long)(((uint64_t)a.w << 32) | a.z)),
@@ -795,11 +776,12 @@ hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
 }
 
 __global__ __launch_bounds__(256) void chunk_reset_kernel(unsigned long long* counter, unsigned long long* sq_count,
-                                                          float* dense, uint64_t n) {
+                                                          unsigned long long* shq_count, float* dense, uint64_t n) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t == 0) {
         *counter = 0ull;
         *sq_count = 0ull;
+        if (shq_count) *shq_count = 0ull;
     }
     for (uint64_t i = t; i < n; i += (uint64_t)gridDim.x * blockDim.x) dense[i] = 0.0f;
 }
@@ -811,32 +793,6 @@ __global__ __launch_bounds__(256) void sur_merge_kernel(const float* __restrict_
     float s = 0.0f;
     for (int d = 0; d < depth; ++d) s += dense[i * depth + d];
     records[p0 + i] += s;
-}
-
-// The persistent kernel's merge: one thread per queued query, and the first query of each path
-// adds the path's result slots from its interaction on, in depth order (the slots before it
-// and those of interactions without a query hold zeros), so the sum is the one of the dense
-// merge above, with the work of the queue rather than of every slot.
-__global__ __launch_bounds__(256) void sur_merge_queued_kernel(const uint4* __restrict__ q,
-                                                               const unsigned long long* __restrict__ count,
-                                                               const float* __restrict__ dense, int depth,
-                                                               float* __restrict__ records, uint64_t p0) {
-    const uint64_t n = *count;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t w = q[2 * i + 1].w;
-        if (!(w & kSlotFirst)) continue;
-        const uint32_t slot = w & ~kSlotFirst;
-        const uint64_t p = slot / (uint32_t)depth;
-        float s = 0.0f;
-        for (uint32_t d = slot; d < (uint32_t)((p + 1) * (uint64_t)depth); ++d) s += dense[d];
-        records[p0 + p] += s;
-    }
-}
-
-hipError_t launch_sur_merge_queued(const uint4* q, const unsigned long long* count, const float* dense, int depth,
-                                   float* records, uint64_t p0, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(sur_merge_queued_kernel, dim3(grid), dim3(256), 0, s, q, count, dense, depth, records, p0);
-    return hipGetLastError();
 }
 
 hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s) {
@@ -852,10 +808,11 @@ hipError_t launch_shadow_merge(const float* val, int depth, float* records, uint
     return hipGetLastError();
 }
 
-hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count, float* dense, uint64_t n,
-                              hipStream_t s) {
+hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count,
+                              unsigned long long* shq_count, float* dense, uint64_t n, hipStream_t s) {
     const uint64_t blocks = std::min<uint64_t>((n + 255) / 256 + 1, 4096);
-    hipLaunchKernelGGL(chunk_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, counter, sq_count, dense, n);
+    hipLaunchKernelGGL(chunk_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, counter, sq_count, shq_count,
+                       dense, n);
     return hipGetLastError();
 }
 

@@ -174,6 +174,9 @@ def test_wavefront_form_with_learned_pw(trained):
     a, sa = R.trace(wl.lambdas_um, R.opts(wavefront=False, **o))
     b, sb = R.trace(wl.lambdas_um, R.opts(wavefront=True, **o))
     e = rel_l2(b.cpu().numpy(), a.cpu().numpy().astype(np.float64))
-    print("learned p_w, wavefront vs persistent: rel L2", e, sb)
-    assert sa["surrogate_evals"] == sb["surrogate_evals"] > 0
+    print("learned p_w, wavefront vs persistent: rel L2", e, sa, sb)
     assert e <= 1e-5
+    # the persistent kernel queues a query before its shadow ray is traced (an occluded one is
+    # evaluated and then cleared); the wavefront form queues visible measurements only
+    assert sa["surrogate_evals"] >= sb["surrogate_evals"] > 0
+    assert sa["surrogate_evals"] + sa["fallbacks"] >= sb["surrogate_evals"] + sb["fallbacks"]
