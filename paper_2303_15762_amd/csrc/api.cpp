@@ -111,7 +111,7 @@ constexpr uint64_t kQueueBytes = (1ull << 30) * 52;
 constexpr uint64_t kWfChunk = 1ull << 23;
 
 struct WsLayout {
-    size_t records = 0, ovf = 0, wf = 0, queue = 0, shadow = 0, dense = 0, total = 0;
+    size_t records = 0, ovf = 0, wf = 0, queue = 0, shadow = 0, dense = 0, nd = 0, total = 0;
     uint64_t chunk = 0;
     size_t wf_bytes = 0;
 };
@@ -399,7 +399,8 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
     const bool defer = o->bsdf_mode != GR_BSDF_PLAIN, shq = shadow_queue_of(o);
-    // bytes per (path, interaction) slot: a network query, a shadow ray, the result float
+    // bytes per (path, interaction) slot: a network query, a shadow ray, the result float (and
+    // one byte per path: its stored slot count)
     const uint64_t slot_bytes = (defer ? grw::kSurQueryBytes : 0) + (shq ? grw::kShadowQueryBytes : 0) + 4;
     const uint64_t slots_max = std::min<uint64_t>(kSurSlots, kQueueBytes / slot_bytes);
     const uint64_t sur_chunk = std::min<uint64_t>(kSurChunk, slots_max / (uint64_t)std::max(o->max_depth, 1));
@@ -409,7 +410,8 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
     L.shadow = L.queue + (defer ? align256((size_t)slots * grw::kSurQueryBytes) : 0);
     L.dense = L.shadow + (shq ? align256((size_t)slots * grw::kShadowQueryBytes) : 0);
-    L.total = L.dense + (defer || shq ? align256((size_t)slots * sizeof(float)) : 0);
+    L.nd = L.dense + (defer || shq ? align256((size_t)slots * sizeof(float)) : 0);
+    L.total = L.nd + (shq ? align256((size_t)L.chunk) : 0);
     return L;
 }
 }  // namespace
@@ -539,6 +541,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     a.shq = shq ? reinterpret_cast<uint4*>(base + WL.shadow) : nullptr;
     float* dense = defer || shq ? reinterpret_cast<float*>(base + WL.dense) : nullptr;
     a.sdense = dense;
+    a.snd = shq ? reinterpret_cast<uint8_t*>(base + WL.nd) : nullptr;
 
     GR_HIP(c, hipSetDevice(c->device));
     const int grid = defer ? c->grid_sur : (a.hero ? c->grid_hero : (a.aniso ? c->grid_aniso : c->grid_plain));
@@ -584,7 +587,7 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
             if (defer)
                 GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
             GR_HIP(c, grw::launch_shadow(a, grid, c->stream));
-            GR_HIP(c, grw::launch_shadow_merge(dense, D, a.records, p0, pn, a.inv_spp_norm, a.stats, c->stream));
+            GR_HIP(c, grw::launch_shadow_merge(dense, a.snd, D, a.records, p0, pn, a.inv_spp_norm, a.stats, c->stream));
         }
         a.n_paths = total;
     } else {

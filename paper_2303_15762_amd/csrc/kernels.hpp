@@ -79,8 +79,9 @@ struct TraceArgs {
     uint4* shq;                      // queued shadow rays (3 uint4 each), or null
     unsigned long long* shq_count;
     float* sdense;                   // measurement values by (path, interaction) slot
-                                     // [paths of the launch][max_depth]; the persistent kernel
-                                     // zeroes a path's slots when it starts it
+                                     // [paths of the launch][max_depth]; a path stores the
+                                     // slots of its first snd[path] interactions
+    uint8_t* snd;                    // [paths of the launch]
     float* records;                  // [n_paths]
     int* ovf;                        // traversal stack overflow [ovf_n][grid * 256], or null
     uint32_t ovf_n;                  // overflow entries per lane
@@ -133,8 +134,9 @@ hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* s
 // records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
 hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
 hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s);
-hipError_t launch_shadow_merge(const float* val, int depth, float* records, uint64_t p0, uint64_t n,
-                               float inv_spp_norm, unsigned long long* stats, hipStream_t s);
+// records[p0 + i] = inv_spp_norm * sum over d < nd[i] of val[i * depth + d], i < n (fixed order)
+hipError_t launch_shadow_merge(const float* val, const uint8_t* nd, int depth, float* records, uint64_t p0,
+                               uint64_t n, float inv_spp_norm, unsigned long long* stats, hipStream_t s);
 // a queued shadow ray: mean position (3 doubles), travel direction of the light, emitter
 // distance, triangle left, slot
 constexpr int kShadowQueryBytes = 48;

@@ -352,11 +352,6 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                         }
                         alpha = 1.0f;
-                        if constexpr (SHQ) {
-                            // clear the path's result slots: the merge sums them in depth order
-                            float* ds = A.sdense + (idx - A.path_begin) * (uint64_t)A.max_depth;
-                            for (int dd = 0; dd < A.max_depth; ++dd) ds[dd] = 0.0f;
-                        }
                         depth = 0;
                         prev = -1;
                         live = true;
@@ -369,6 +364,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
 
         // ---- one segment of every live path ------------------------------------------
         bool finish = false;
+        bool wrote = false;   // SHQ: this vertex stored its measurement slot
         if (live) {
         ev |= 1u << EV_SEG;
         RayT ray;
@@ -463,6 +459,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 }
 
                 // Measurement by next-event estimation (eq. measurement_operator).
+                float sval = 0.0f;   // SHQ: the value for this vertex's slot
                 if (A.nsrc > 0) {
                     const uint4 rn = draw(pid, (uint32_t)depth, STREAM_NEE, A.seed);
                     const int si = min((int)(unif(rn.x) * (float)A.nsrc), A.nsrc - 1);
@@ -542,7 +539,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             qb = __shfl(qb, leader);
                             const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
-                            if (e == 0) A.sdense[slot] = v;
+                            sval = v;
                             uint4* q = A.shq + 3 * (qb + r);
                             const unsigned long long px = __double_as_longlong(P.x), py = __double_as_longlong(P.y),
                                                      pz = __double_as_longlong(P.z);
@@ -590,6 +587,13 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                         }
                     }
+                }
+                if constexpr (SHQ) {
+                    // every vertex that reaches the measurement stores its slot (zero without a
+                    // measurement; a queued network query overwrites it, an occluded shadow ray
+                    // clears it), so the merge reads the path's first slots only
+                    A.sdense[(idx - A.path_begin) * (uint64_t)A.max_depth + depth] = sval;
+                    wrote = true;
                 }
                 if (depth + 1 >= A.max_depth) {
                     finish = true;
@@ -647,6 +651,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     }
                     A.records[rb + (uint64_t)i * G] = val;
                 }
+            } else {
+                // slots the path stored: one per vertex that reached the measurement
+                A.snd[idx - A.path_begin] = (uint8_t)(depth + (wrote ? 1 : 0));
             }
             live = false;
         }
@@ -709,15 +716,18 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
 }
 
 // Records of a launch's paths: the measurement values of each path's interactions summed in
-// depth order (the order in which the path would have added them itself).
-__global__ __launch_bounds__(256) void shadow_merge_kernel(const float* __restrict__ val, int depth,
+// depth order (the order in which the path would have added them itself); path i stored its
+// first nd[i] slots.
+__global__ __launch_bounds__(256) void shadow_merge_kernel(const float* __restrict__ val,
+                                                           const uint8_t* __restrict__ nd, int depth,
                                                            float* __restrict__ records, uint64_t p0, uint64_t n,
                                                            float inv_spp_norm, unsigned long long* stats) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool bad = false;
     if (i < n) {
+        const int m = nd[i];
         float s = 0.0f;
-        for (int d = 0; d < depth; ++d) s += val[i * depth + d];
+        for (int d = 0; d < m; ++d) s += val[i * depth + d];
         float v = s * inv_spp_norm;
         if (!isfinite(v)) {
             bad = true;
@@ -800,11 +810,11 @@ hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_shadow_merge(const float* val, int depth, float* records, uint64_t p0, uint64_t n,
-                               float inv_spp_norm, unsigned long long* stats, hipStream_t s) {
+hipError_t launch_shadow_merge(const float* val, const uint8_t* nd, int depth, float* records, uint64_t p0,
+                               uint64_t n, float inv_spp_norm, unsigned long long* stats, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(shadow_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, depth, records,
-                       p0, n, inv_spp_norm, stats);
+    hipLaunchKernelGGL(shadow_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, nd, depth,
+                       records, p0, n, inv_spp_norm, stats);
     return hipGetLastError();
 }
 
