@@ -41,12 +41,14 @@ NODE_BYTES = 112     # bytes of a 4-wide node the traversal reads (boxes + child
 TRI_BYTES = 48       # bytes of a triangle record
 HIT_BYTES = 48 + 48 + 32   # closest hit: triangle, shading normals, material
 RECORD_BYTES = 4     # one float per path
+SHADOW_QUEUE_BYTES = 2 * 48 + 2 * 4   # a queued shadow ray written and read, its value stored and read
 
-# HBM traffic of one trace-kernel launch on this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE scaled by a plain copy of known size; valid only for the kernel sources it was
-# measured on (sha256 prefix of the files below).
-TRAFFIC_BYTES = {"mid": 1_644_088 * 1024, "large": 27_203_828 * 1024}
-TRAFFIC_KERNEL_HASH = "517280b47b6697b1"
+# HBM traffic of one frame's path-tracing launches on this workload (trace, shadow-ray and
+# merge kernels), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
+# size; valid only for the kernel sources it was measured on (sha256 prefix of the files
+# below).
+TRAFFIC_BYTES = {"mid": 2_900_275 * 1024, "large": 113_227_630 * 1024}
+TRAFFIC_KERNEL_HASH = "1304f6f9036d2be8"
 KERNEL_SOURCES = ["paper_2303_15762_amd/csrc/trace.hip", "paper_2303_15762_amd/csrc/trace_core.hpp",
                   "paper_2303_15762_amd/csrc/device_math.hpp",
                   "paper_2303_15762_amd/csrc/kernels.hpp"]
@@ -63,17 +65,18 @@ def kernel_hash():
 
 
 def algorithmic_bytes(st):
-    """Scene and output bytes one trace-kernel launch requests, from the in-kernel counters:
-    node and triangle fetches of both traversals, the shading reads of each closest hit
-    (approximated by segments - paths: every path ends on at most one miss) and one float
-    written per path.  Path state stays in registers and moves no memory."""
+    """Scene and output bytes one frame's path-tracing launches request, from the in-kernel
+    counters: node and triangle fetches of both traversals, the shading reads of each closest
+    hit (approximated by segments - paths: every path ends on at most one miss), each shadow
+    ray through its queue with its measurement value, and one float written per path.  Path
+    state stays in registers and moves no memory."""
     hits = max(0, st["segments"] - st["paths"])
     return (st["node_visits"] * NODE_BYTES + st["tri_tests"] * TRI_BYTES + hits * HIT_BYTES
-            + st["paths"] * RECORD_BYTES)
+            + st["shadow_rays"] * SHADOW_QUEUE_BYTES + st["paths"] * RECORD_BYTES)
 
 
 def algorithmic_ops(st):
-    """Vector operations one trace-kernel launch needs by the counts above."""
+    """Vector operations one frame's path-tracing launches need by the counts above."""
     return (st["node_visits"] * NODE_OPS + st["tri_tests"] * TRI_OPS + st["segments"] * SEGMENT_OPS
             + st["shadow_rays"] * SHADOW_OPS)
 
@@ -315,7 +318,9 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     value = segments / (ms_step * 1e-3) / 1e6
 
-    # dominant kernel: the path-tracing kernel, timed alone with HIP events on its stream
+    # dominant kernels: the path-tracing launches of one frame (trace_kernel, then
+    # shadow_kernel over the queued shadow rays and shadow_merge_kernel over the result slots),
+    # timed with HIP events on their stream without the per-pixel reduction
     kms = []
     for _ in range(3):
         img.zero_()
@@ -331,7 +336,7 @@ def main():
     traffic = (TRAFFIC_BYTES.get(args.workload) if kernel_hash() == TRAFFIC_KERNEL_HASH else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_PEAK_GOPS, 1),
                 "unit": "Gop/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": traffic,
-                "kernel": "trace_kernel", "kernel_ms": round(k_ms, 3), "algorithmic_ops": int(aops),
+                "kernel": "trace_kernel + shadow_kernel + shadow_merge_kernel", "kernel_ms": round(k_ms, 3), "algorithmic_ops": int(aops),
                 "requested_bytes": int(abytes),
                 "requested_gbs": round(abytes / (k_ms * 1e-3) / 1e9, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
                 "traffic_bytes_per_segment": (round(traffic / segments, 1) if traffic else None)}

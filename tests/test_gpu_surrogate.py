@@ -107,10 +107,11 @@ def test_surrogate_trace_deterministic(trained, mode):
 
 
 def test_surrogate_deep_paths_in_bounded_launches(trained):
-    """Up to 64 interactions per path: a launch holds at most 2^30 (path, interaction) query
-    slots, i.e. 2^24 paths here, so the 18.9M-path frame runs in two launches.  The image
-    equals the sum of two renders over sample ranges that each fit one launch, and matches
-    the oracle on sampled pixels."""
+    """Up to 64 interactions per path: a launch holds at most 52 GiB of queues and result
+    slots (84 B per (path, interaction) slot with the learned p_w: a network query, a shadow
+    ray and the value), i.e. 10.4M paths here, so the 18.9M-path frame runs in two launches.
+    The image equals the sum of two renders over sample ranges that each fit one launch, and
+    matches the oracle on sampled pixels."""
     import dataclasses
     R, S, p, hist, torch = trained
     wl = dataclasses.replace(W.mid_terrain(width=512, height=512, spp=9, n_lambda=8), max_depth=64)

@@ -245,3 +245,32 @@ def test_edge_cases(R):
     img = torch.full((1, 1, 1), 7.0, device=R.dev)
     out, st = R.trace(wl.lambdas_um, R.opts(spp_count=0, spp_norm=1, max_depth=4, seed=3), image=img)
     assert float(out[0, 0, 0]) == 7.0 and st["paths"] == 0
+
+
+def test_no_sources_leave_the_image(R):
+    """Without sources no vertex measures anything: every record is zero, so an image that
+    already holds values keeps them exactly (the measurement slots of each vertex are still
+    stored and merged)."""
+    import torch
+    wl = W.mid_terrain(width=24, height=16, spp=2, n_lambda=2)
+    R.load_workload(wl)
+    R.set_sources([])
+    img = torch.full((2, 16, 24), 0.25, device=R.dev)
+    out, st = R.trace(wl.lambdas_um, R.opts(spp_count=2, spp_norm=2, max_depth=4, seed=wl.seed), image=img)
+    assert st["paths"] == 24 * 16 * 2 * 2 and st["segments"] >= st["paths"] and st["shadow_rays"] == 0
+    assert bool((out == 0.25).all())
+    R.set_sources(wl.sources)
+
+
+@pytest.mark.parametrize("depth", [1, 9, 64])
+def test_depth_limits_match_oracle(R, depth):
+    """Path depth 1 (one slot per path), 9 and 64 (the largest allowed): the merge sums the
+    slots each path stored, in depth order; terrain crop against the oracle."""
+    import dataclasses
+    wl = dataclasses.replace(W.mid_terrain(width=33, height=21, spp=3, n_lambda=2), max_depth=depth)
+    g, st = _gpu_image(R, wl)
+    o, ost = oracle.render(wl)
+    err = rel_l2(g, o)
+    print("depth", depth, "rel L2", err, "segments", st["segments"], ost["segments"])
+    assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    assert err <= RTOL_IMAGE
