@@ -43,19 +43,21 @@ __host__ __device__ inline int bwd_frag(int layer, int mt, int kb) {   // layer 
     return (layer - 1) * 8 + mt * 2 + kb;
 }
 
-// GELU, tanh form: 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))), and its derivative.
-// tanh(y) = 1 - 2 / (exp(2y) + 1), with the hardware exponential and reciprocal (1 ulp each).
-__device__ __forceinline__ float tanh_fast(float y) {
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * y) + 1.0f);
+// GELU, tanh form: 0.5 x (1 + tanh(y)), y = sqrt(2/pi) (x + 0.044715 x^3), and its
+// derivative.  Since 0.5 (1 + tanh(y)) = 1 / (1 + exp(-2 y)), the activation is x s with
+// s = 1 / (1 + 2^(x (a + b x^2))), a = -2 sqrt(2/pi) log2(e), b = 0.044715 a: one hardware
+// base-2 exponential and one reciprocal (1 ulp each).  Large |x| saturates to x or -0.
+constexpr float kGeluA = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+constexpr float kGeluB = 0.044715f * kGeluA;
+__device__ __forceinline__ float gelu_gate(float x) {
+    const float a = x * fmaf(kGeluB, x * x, kGeluA);
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a));
 }
-__device__ __forceinline__ float gelu_f(float x) {
-    const float y = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    return 0.5f * x * (1.0f + tanh_fast(y));
-}
+__device__ __forceinline__ float gelu_f(float x) { return x * gelu_gate(x); }
+// d/dx [x s] = s + x s (1 - s) 2 y', y' = sqrt(2/pi) (1 + 3 * 0.044715 x^2)
 __device__ __forceinline__ float gelu_grad_f(float x) {
-    const float y = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    const float t = tanh_fast(y);
-    return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * x * x);
+    const float sg = gelu_gate(x);
+    return sg + x * sg * (1.0f - sg) * (2.0f * 0.7978845608028654f) * fmaf(0.134145f, x * x, 1.0f);
 }
 
 // Round-to-nearest-even float -> bfloat16 (v_cvt_pk_bf16_f32 on gfx950).
