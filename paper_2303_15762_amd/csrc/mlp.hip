@@ -284,18 +284,35 @@ __global__ __launch_bounds__(64) void mlp_backward_kernel(const TrainArgs T) {
     }
 }
 
+// Per-wave partial gradients summed in a fixed order: a block takes 64 parameters (one per
+// lane) and its four waves take every fourth partial each (wave g: partials g, g + 4, ...);
+// the four sums are then added in wave order.  The last block sums the loss partials the same
+// way.  Deterministic for a given n_waves.
 __global__ __launch_bounds__(256) void grad_reduce_kernel(const float* __restrict__ part, const float* __restrict__ lpart,
                                                           int64_t n_waves, float inv_n, float* __restrict__ grad,
                                                           float* __restrict__ loss) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < MLP_NPARAM) {
-        float s = 0.0f;
-        for (int64_t w = 0; w < n_waves; ++w) s += part[w * MLP_NPARAM + p];
-        grad[p] = s;
-    } else if (p == MLP_NPARAM) {
-        float s = 0.0f;
-        for (int64_t w = 0; w < n_waves; ++w) s += lpart[w];
-        loss[0] = s * inv_n;
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const bool is_loss = blockIdx.x == gridDim.x - 1;
+    const int p = blockIdx.x * 64 + lane;
+    float s = 0.0f;
+    if (is_loss) {
+        // lane l of wave g sums loss partials g + 4 (l + 64 j)
+        for (int64_t w = g + 4 * lane; w < n_waves; w += 256) s += lpart[w];
+    } else if (p < MLP_NPARAM) {
+#pragma unroll 8
+        for (int64_t w = g; w < n_waves; w += 4) s += part[w * MLP_NPARAM + p];
+    }
+    red[g][lane] = s;
+    __syncthreads();
+    if (g != 0) return;
+    float t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (is_loss) {
+        // fixed-order sum over the 64 lanes
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off);
+        if (lane == 0) loss[0] = t * inv_n;
+    } else if (p < MLP_NPARAM) {
+        grad[p] = t;
     }
 }
 
@@ -532,7 +549,8 @@ hipError_t mlp_backward(const float* params, const float* x, const float* t, int
     hipLaunchKernelGGL(mlp_backward_kernel, dim3((unsigned)waves), dim3(64), 0, s, T);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(grad_reduce_kernel, dim3((MLP_NPARAM + 256) / 256), dim3(256), 0, s, T.part, T.loss, waves,
+    // one block per 64 parameters, plus one for the loss
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3((MLP_NPARAM + 63) / 64 + 1), dim3(256), 0, s, T.part, T.loss, waves,
                        1.0f / (float)n, grad, loss);
     return hipGetLastError();
 }
