@@ -210,9 +210,12 @@ int gr_set_sensor(gr_ctx* ctx, const gr_sensor* sensor);
 int gr_set_sources(gr_ctx* ctx, const gr_source* sources, int32_t n);
 
 /* Workspace (device memory) needed by gr_trace for these options and n_lambda wavelengths:
- * a header, one float per path, and the traversal-stack overflow of the uploaded scene's BVH
- * (one region per persistent lane, 3 entries per BVH level beyond the LDS part).  Call it
- * after gr_scene_upload: the size depends on the scene and the device. */
+ * a header, one float per path, the traversal-stack overflow of the uploaded scene's BVH
+ * (one region per persistent lane, 3 entries per BVH level beyond the LDS part), and for one
+ * launch of the persistent kernel with one wavelength per path its queued shadow rays (48 B),
+ * measurement slots (4 B) and, with a learned p_w, network queries (32 B) per (path,
+ * interaction), plus one byte per path (at most 52 GiB of these per launch).  Call it after
+ * gr_scene_upload: the size depends on the scene and the device. */
 int gr_workspace_size(const gr_ctx* ctx, const gr_trace_opts* opts, int32_t n_lambda,
                       size_t* bytes);
 /* Device pointer (inside `workspace`) of the per-path contributions kept by
