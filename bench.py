@@ -1,9 +1,15 @@
-"""Benchmark: Mpath-segments/s of the generalized-ray tracer on the mid terrain workload.
+"""Benchmark: Mpath-segments/s of the generalized-ray tracer, plain against learned p_w.
 
-Workload: 65,536-triangle value-noise terrain with 16x16 material tiles (smooth, Gaussian
-rough, sinusoidal grating), one partially coherent area emitter, 512 x 512 sensor, 16 samples
-per pixel, 8 wavelengths, path depth <= 4 (seeded, synthetic).  One step = one full trace of
-that workload (33.6M paths) including the per-pixel reduction, inputs resident on the GPU.
+Headline workload: the large instanced scene (4,194,300 triangles: 60 displaced terrain tiles
+and 21,845 random boxes with the smooth / Gaussian rough / grating material mix, three
+partially coherent emitters), 1920 x 1080 sensor, 64 samples per pixel, 16 wavelengths, path
+depth <= 6 with Russian roulette (2.12G paths per frame; seeded, synthetic).  One step = one
+full trace of that frame including the per-pixel reduction, inputs resident on the GPU.  The
+learned-p_w legs (BF16 and FP8 matrix-core operands) render the same frame.  Each leg's image
+is compared with the FP64 oracle on every 8th row and column of the sensor (1/64 of the
+pixels, the same per-path random streams); a leg qualifies at rel. L2 <= 1e-3 (closed form)
+or <= 1e-2 (learned p_w).  The mid terrain (65,536 triangles, 512 x 512, 16 spp, 8
+wavelengths, depth <= 4) is reported as an extra leg.
 
 Prints one JSON line.  Only one GPU is supported (--gpus > 1 exits with a message).
 """
@@ -81,36 +87,65 @@ def algorithmic_ops(st):
             + st["shadow_rays"] * SHADOW_OPS)
 
 
-def cpu_baseline(wl, target_s=15.0):
+def subset_pixels(wl, step=8):
+    """Every step-th row and column of the sensor as (x, y) pairs (1/64 of the pixels at 8)."""
+    ys = np.arange(0, wl.sensor.height, step)
+    xs = np.arange(0, wl.sensor.width, step)
+    yy, xx = np.meshgrid(ys, xs, indexing="ij")
+    return np.stack([xx.ravel(), yy.ravel()], 1)
+
+
+def rel_l2_on(img_gpu, pix, ref):
+    """Relative L2 error of a GPU image [n_lambda, H, W] on the pixels pix (x, y) against the
+    oracle's [n_lambda, n_pixels]."""
+    g = img_gpu.detach().double().cpu().numpy()[:, pix[:, 1], pix[:, 0]]
+    return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+
+
+def oracle_subset(wl, pix, threads):
+    """The FP64 oracle on the pixel subset (every per-path stream as in the full frame); returns
+    (image [n_lambda, n_pixels], seconds, segments)."""
     import oracle
-    from workloads import scenes as W  # noqa: F401
     osc = oracle.OracleScene(wl.scene)
-    rng = np.random.default_rng(123)
-    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    img, st = oracle.render(wl, osc, pixels=pix, n_threads=threads)
+    return img, time.perf_counter() - t0, st["segments"], osc
 
-    def run(npx, nt):
-        pix = np.stack([rng.integers(0, wl.sensor.width, npx), rng.integers(0, wl.sensor.height, npx)], 1)
-        t0 = time.perf_counter()
-        _, st = oracle.render(wl, osc, pixels=pix, n_threads=nt)
-        return time.perf_counter() - t0, st["segments"]
 
-    dt, seg = run(64, threads)
-    npx = int(max(64, min(wl.sensor.width * wl.sensor.height, 64 * target_s / max(dt, 1e-3))))
-    dt, seg = run(npx, threads)
-    # one thread on a smaller sample (about 3 s)
-    npx1 = max(16, int(npx * 3.0 / max(target_s * threads, 1e-3)))
-    dt1, seg1 = run(npx1, 1)
+def cpu_baseline_from(wl, pix, dt, seg, osc, threads, what):
+    """The oracle's Mpath-segments/s on the subset it rendered for the image comparison, and on
+    one thread over every 16th pixel of that subset."""
+    import oracle
+    pix1 = pix[::16]
+    t0 = time.perf_counter()
+    _, st1 = oracle.render(wl, osc, pixels=pix1, n_threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": seg / dt / 1e6, "unit": "Mpath-segments/s", "cores": threads, "kind": "oracle",
-            "single_thread_value": seg1 / dt1 / 1e6,
-            "sample": f"{npx} random pixels x {wl.spp} samples x {len(wl.lambdas_um)} wavelengths of the "
-                      f"same workload ({seg} segments, {dt:.1f} s, FP64 C++ oracle, {threads} threads); "
-                      f"single thread: {npx1} pixels ({seg1} segments, {dt1:.1f} s)"}
+            "single_thread_value": st1["segments"] / dt1 / 1e6,
+            "sample": f"{what}: {len(pix)} pixels (every 8th row and column) x {wl.spp} samples x "
+                      f"{len(wl.lambdas_um)} wavelengths ({seg} segments, {dt:.1f} s, FP64 C++ oracle, "
+                      f"{threads} threads); single thread: {len(pix1)} of those pixels "
+                      f"({st1['segments']} segments, {dt1:.1f} s)"}
 
 
-def surrogate_leg(R, wl, o_plain, img, st_plain, args):
-    """Train the learned p_w (outside the timed region), then time the same workload with the
-    surrogate path, with bfloat16 and with E4M3 matrix-core operands.  Each image is compared
-    with the plain-path image of this GPU."""
+def time_frames(R, wl, o, img, steps):
+    """Mean ms per frame over `steps` traces timed with HIP events on the renderer's stream."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(R.stream)
+    for _ in range(steps):
+        R.trace(wl.lambdas_um, o, image=img, stats=False)
+    e1.record(R.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def surrogate_leg(R, wl, img_plain, ms_plain, pix, ref, steps):
+    """Train the learned p_w (outside the timed region), then render the same frame with the
+    network (bfloat16 and E4M3 matrix-core operands): frame time, each image against the FP64
+    oracle on the pixel subset, and what the network can gain at most on this frame."""
     import torch
     from paper_2303_15762_amd.surrogate import Surrogate
     S = Surrogate(R)
@@ -119,27 +154,27 @@ def surrogate_leg(R, wl, o_plain, img, st_plain, args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     S.install(p)
-    plain = img.clone()
     legs = {}
     for name, mode in (("bf16", 1), ("fp8", 2)):
         o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
                    rr_enable=wl.rr_enable, rr_p=wl.rr_p, bsdf_mode=mode)
-        img_s = torch.zeros_like(img)
+        img_s = torch.zeros_like(img_plain)
         _, st = R.trace(wl.lambdas_um, o, image=img_s, stats=True)
-        err = float((img_s - plain).norm() / plain.norm())
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(R.stream)
-        for _ in range(args.steps):
-            R.trace(wl.lambdas_um, o, image=img_s, stats=False)
-        e1.record(R.stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        legs[name] = {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 3),
-                      "rel_l2_vs_plain_gpu_image": err, "surrogate_evals_per_step": st["surrogate_evals"]}
-    # the network alone on the matrix cores: 4M encoded queries, both operand types
-    x, _, _ = S.samples(1 << 22, seed=77)
+        err_o = rel_l2_on(img_s, pix, ref) if ref is not None else None
+        err_p = float(torch.linalg.vector_norm((img_s - img_plain).double()) /
+                      torch.linalg.vector_norm(img_plain.double()))
+        ms = time_frames(R, wl, o, img_s, steps)
+        legs[name] = {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
+                      "ms_per_step": round(ms, 3), "steps": steps,
+                      "rel_l2_vs_oracle": err_o,
+                      "qualifies": (err_o is not None and err_o <= 1e-2),
+                      "rel_l2_vs_plain_gpu_image": err_p,
+                      "surrogate_evals_per_step": st["surrogate_evals"],
+                      "fallbacks_per_step": st["fallbacks"],
+                      "frame_time_vs_plain": round(ms / ms_plain, 4)}
+    # the network alone on the matrix cores: 4M encoded queries, both operand types; and the
+    # in-domain queries through gr_bsdf_eval, closed form against network
+    x, _, q = S.samples(1 << 22, seed=77, with_queries=True)
     mfma = {}
     for name, dtype, peak in (("bf16", 1, MFMA_PEAK_TFLOPS["bf16"]), ("fp8", 2, MFMA_PEAK_TFLOPS["fp8"])):
         S.forward(p, x, dtype=dtype)
@@ -155,15 +190,37 @@ def surrogate_leg(R, wl, o_plain, img, st_plain, args):
         tf = x.shape[0] * MLP_FLOPS / (ms * 1e-3) / 1e12
         mfma[name] = {"bound": "mfma", "achieved": round(tf, 1), "peak": peak, "unit": "TFLOP/s",
                       "frac": round(tf / peak, 4), "rows": int(x.shape[0]), "ms": round(ms, 4)}
+    per_query = {}
+    for name, mode in (("closed_form", 0), ("bf16", 1), ("fp8", 2)):
+        R.bsdf_eval(q, mode=mode)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(R.stream)
+        for _ in range(5):
+            R.bsdf_eval(q, mode=mode)
+        e1.record(R.stream)
+        torch.cuda.synchronize()
+        per_query[name] = e0.elapsed_time(e1) / 5 / q.shape[0] * 1e6   # ns per query
     legs["bf16"]["roofline"] = mfma["bf16"]
     legs["fp8"]["roofline"] = mfma["fp8"]
-    out = dict(legs["bf16"])
-    out.update({"unit": "Mpath-segments/s", "fallbacks_per_step": st["fallbacks"], "train_s": round(t_train, 2),
-                "train_steps": hist["step"][-1], "val_mse_log_pw": hist["val_loss"][-1], "fp8": legs["fp8"]})
+    n_in = legs["bf16"]["surrogate_evals_per_step"]
+    cf_ms = n_in * per_query["closed_form"] * 1e-6
+    out = {"bf16": legs["bf16"], "fp8": legs["fp8"],
+           "train_s": round(t_train, 2), "train_steps": hist["step"][-1],
+           "val_mse_log_pw": hist["val_loss"][-1],
+           # the in-domain queries in full waves through gr_bsdf_eval: the closed form's cost the
+           # network replaces, and the most the frame can gain from it (Amdahl)
+           "in_domain_ns_per_query": {k: round(v, 4) for k, v in per_query.items()},
+           "in_domain_speedup_per_query": {"bf16": round(per_query["closed_form"] / per_query["bf16"], 2),
+                                           "fp8": round(per_query["closed_form"] / per_query["fp8"], 2)},
+           "closed_form_pw_ms_replaced_per_frame_est": round(cf_ms, 3),
+           "closed_form_pw_share_of_frame_est": round(cf_ms / ms_plain, 5),
+           "amdahl_max_frame_speedup": round(ms_plain / max(ms_plain - cf_ms, 1e-9), 5)}
     return out
 
 
-def hero_leg(R, wl, ms_plain, args):
+def hero_leg(R, wl, ms_plain, steps):
     """Hero-wavelength paths (one path per pixel, sample and rotation group of four wavelengths)
     on the same workload: the same image estimated from a quarter of the paths.  Reported: the
     frame time, path segments per second, and wavelength-segments per second (each hero segment
@@ -174,22 +231,15 @@ def hero_leg(R, wl, ms_plain, args):
                rr_enable=wl.rr_enable, rr_p=wl.rr_p, hero=True)
     img = torch.zeros((len(wl.lambdas_um), wl.sensor.height, wl.sensor.width), device=R.dev)
     _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(R.stream)
-    for _ in range(args.steps):
-        R.trace(wl.lambdas_um, o, image=img, stats=False)
-    e1.record(R.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = time_frames(R, wl, o, img, steps)
     return {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
-            "ms_per_step": round(ms, 3), "paths_per_step": st["paths"], "segments_per_step": st["segments"],
+            "ms_per_step": round(ms, 3), "steps": steps, "paths_per_step": st["paths"],
+            "segments_per_step": st["segments"],
             "wavelength_segments_per_s_M": round(4 * st["segments"] / (ms * 1e-3) / 1e6, 2),
             "frame_speedup_vs_one_wavelength_paths": round(ms_plain / ms, 3)}
 
 
-def aniso_leg(R, wl, ms_plain, img_plain, args):
+def aniso_leg(R, wl, ms_plain, img_plain, steps):
     """Anisotropic generalized rays (matrix beta, rho) on the same workload and random streams:
     frame time, path segments per second, and the image difference from the scalar rays."""
     import torch
@@ -199,17 +249,9 @@ def aniso_leg(R, wl, ms_plain, img_plain, args):
     _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
     diff = float(torch.linalg.vector_norm((img - img_plain).double()) /
                  torch.linalg.vector_norm(img_plain.double()))
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(R.stream)
-    for _ in range(args.steps):
-        R.trace(wl.lambdas_um, o, image=img, stats=False)
-    e1.record(R.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = time_frames(R, wl, o, img, steps)
     return {"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
-            "ms_per_step": round(ms, 3), "segments_per_step": st["segments"],
+            "ms_per_step": round(ms, 3), "steps": steps, "segments_per_step": st["segments"],
             "frame_time_vs_scalar_rays": round(ms / ms_plain, 3), "rel_l2_vs_scalar_ray_image": diff}
 
 
@@ -222,7 +264,7 @@ def aniso_leg(R, wl, ms_plain, img_plain, args):
 COHERENT_NODE_OPS = 85
 
 
-def coherent_leg(R, args):
+def coherent_leg(R, steps):
     """The precision-stress measurement (double slit, z = 1 m, 0.55 um, 1024 x 64 sensor, 64
     samples, 16 Gauss-Legendre nodes per slit) in its three phase modes."""
     from workloads import coherent_case
@@ -234,7 +276,7 @@ def coherent_leg(R, args):
     for name, mode in (("fp32", 0), ("fp64", 1), ("two_float", 2)):
         R.coherent(case, phase_mode=mode, nodes_per_slit=nodes)
         ms = []
-        for _ in range(max(1, args.steps)):
+        for _ in range(max(1, steps)):
             _, t = R.coherent(case, phase_mode=mode, nodes_per_slit=nodes, timing=True)
             ms.append(t)
         m = float(np.median(ms))
@@ -246,23 +288,83 @@ def coherent_leg(R, args):
     return out
 
 
+def plain_frame(R, wl, warmup, steps):
+    """Warm up, time `steps` plain frames, then take the deterministic counters and the image of
+    one frame and the path-tracing kernels' device time (HIP events around the trace, shadow-ray
+    and merge launches on the renderer's stream) over three more frames."""
+    import torch
+    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+               rr_enable=wl.rr_enable, rr_p=wl.rr_p)
+    img = torch.zeros((len(wl.lambdas_um), wl.sensor.height, wl.sensor.width), device=R.dev)
+    for _ in range(max(1, warmup)):
+        R.trace(wl.lambdas_um, o, image=img, stats=False)
+    ms_step = time_frames(R, wl, o, img, steps)
+    kms = []
+    for _ in range(3):
+        img.zero_()
+        _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
+        kms.append(st["ms"])
+    return o, img, st, ms_step, float(np.mean(kms))
+
+
+def roofline_of(st, k_ms, workload):
+    # The kernel issues vector-ALU work near the issue limit (see the committed counters) while
+    # its scene fetches are served from the caches, so the bound is the vector ALU; the
+    # requested-bytes view against HBM is reported beside it.
+    aops = algorithmic_ops(st)
+    achieved = aops / (k_ms * 1e-3) / 1e9
+    abytes = algorithmic_bytes(st)
+    traffic = (TRAFFIC_BYTES.get(workload) if kernel_hash() == TRAFFIC_KERNEL_HASH else None)
+    return {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_PEAK_GOPS, 1),
+            "unit": "Gop/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": traffic,
+            "kernel": "trace_kernel + shadow_kernel + shadow_merge_kernel", "kernel_ms": round(k_ms, 3),
+            "algorithmic_ops": int(aops), "requested_bytes": int(abytes),
+            "requested_gbs": round(abytes / (k_ms * 1e-3) / 1e9, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
+            "traffic_gbs": (round(traffic / (k_ms * 1e-3) / 1e9, 1) if traffic else None),
+            "traffic_bytes_per_segment": (round(traffic / st["segments"], 1) if traffic else None)}
+
+
+WORKLOAD_NAMES = {
+    "large": ("large instanced scene: 4,194,300 triangles (60 displaced terrain tiles + 21,845 boxes, "
+              "smooth / rough / grating mix), 1920x1080 sensor, 64 spp, 16 wavelengths, depth<=6 with "
+              "Russian roulette, 3 partially coherent emitters; plain closed-form scattering, learned-p_w "
+              "legs on the same frame"),
+    "mid": ("mid terrain: 65,536 triangles, 512x512 sensor, 16 spp, 8 wavelengths, depth<=4, "
+            "plain closed-form scattering"),
+}
+
+
+def load(workload):
+    from workloads import mid_terrain
+    from workloads import scenes as W
+    # the oracle gets the float32-rounded values the library receives, so both render the same
+    # scene (a grazing narrow-lobe path moves with the rounding of its inputs)
+    if workload == "mid":
+        return W.as_float32_inputs(mid_terrain())
+    return W.as_float32_inputs(W.large_workload())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--leg-steps", type=int, default=3,
+                    help="timed frames of each extra leg (learned p_w, hero, anisotropic, mid), "
+                         "at most --steps")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the FP64 oracle (no rel. L2 against it, no CPU baseline)")
     ap.add_argument("--no-surrogate", dest="surrogate", action="store_false",
-                    help="skip the learned-p_w leg (training takes a few seconds)")
-    ap.add_argument("--no-hero", dest="hero", action="store_false",
-                    help="skip the hero-wavelength leg")
-    ap.add_argument("--no-aniso", dest="aniso", action="store_false",
-                    help="skip the anisotropic-ray leg")
+                    help="skip the learned-p_w legs (training takes a few seconds)")
+    ap.add_argument("--no-hero", dest="hero", action="store_false", help="skip the hero-wavelength leg")
+    ap.add_argument("--no-aniso", dest="aniso", action="store_false", help="skip the anisotropic-ray leg")
     ap.add_argument("--no-coherent", dest="coherent", action="store_false",
                     help="skip the coherent-measurement leg")
-    ap.add_argument("--workload", choices=["mid", "large"], default="mid",
-                    help="mid: the 65,536-triangle terrain (the reported line); large: the "
-                         "4,194,300-triangle instanced scene at 1920x1080, 64 spp, 16 wavelengths")
+    ap.add_argument("--no-mid", dest="mid", action="store_false",
+                    help="skip the mid-terrain leg of the large workload")
+    ap.add_argument("--workload", choices=["large", "mid"], default="large",
+                    help="large: the 4,194,300-triangle instanced scene at 1920x1080, 64 spp, 16 "
+                         "wavelengths (the reported line); mid: the 65,536-triangle terrain alone")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (scales the "
                          "HBM byte counters of a profiler run)")
@@ -284,62 +386,21 @@ def main():
 
     import torch
     from paper_2303_15762_amd import Renderer
-    from workloads import mid_terrain
-    from workloads import scenes as W
 
-    if args.workload == "mid":
-        wl = mid_terrain()
-        wl_name = ("mid terrain: 65,536 triangles, 512x512 sensor, 16 spp, 8 wavelengths, depth<=4, "
-                   "plain closed-form scattering")
-    else:
-        wl = W.as_float32_inputs(W.large_workload())
-        wl_name = ("large instanced scene: 4,194,300 triangles, 1920x1080 sensor, 64 spp, 16 wavelengths, "
-                   "depth<=6 with Russian roulette, 3 partially coherent emitters, plain closed-form scattering")
+    leg_steps = max(1, min(args.leg_steps, args.steps))
+    threads = os.cpu_count() or 1
+    wl = load(args.workload)
+    pix = subset_pixels(wl)
+    # the FP64 oracle on the pixel subset first (CPU only), so its image is at hand for every leg
+    ref = None
+    if not args.no_cpu:
+        ref, dt_or, seg_or, osc = oracle_subset(wl, pix, threads)
     R = Renderer(0)
     info = R.load_workload(wl)
-    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
-               rr_enable=wl.rr_enable, rr_p=wl.rr_p)
-    img = torch.zeros((len(wl.lambdas_um), wl.sensor.height, wl.sensor.width), device=R.dev)
-    # warmup (also gives the deterministic counters of one step)
-    st = None
-    for _ in range(max(1, args.warmup)):
-        img.zero_()
-        _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
+    o, img, st, ms_step, k_ms = plain_frame(R, wl, args.warmup, args.steps)
     segments = st["segments"]
-    stream = R.stream
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        R.trace(wl.lambdas_um, o, image=img, stats=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
     value = segments / (ms_step * 1e-3) / 1e6
-
-    # dominant kernels: the path-tracing launches of one frame (trace_kernel, then
-    # shadow_kernel over the queued shadow rays and shadow_merge_kernel over the result slots),
-    # timed with HIP events on their stream without the per-pixel reduction
-    kms = []
-    for _ in range(3):
-        img.zero_()
-        _, s2 = R.trace(wl.lambdas_um, o, image=img, stats=True)
-        kms.append(s2["ms"])
-    k_ms = float(np.mean(kms))
-    # The kernel issues vector-ALU work at the issue limit (see the committed counters) while
-    # its scene fetches are served from the caches, so the bound is the vector ALU; the
-    # requested-bytes view against HBM is reported beside it.
-    aops = algorithmic_ops(st)
-    achieved = aops / (k_ms * 1e-3) / 1e9
-    abytes = algorithmic_bytes(st)
-    traffic = (TRAFFIC_BYTES.get(args.workload) if kernel_hash() == TRAFFIC_KERNEL_HASH else None)
-    roofline = {"bound": "alu", "achieved": round(achieved, 1), "peak": round(VALU_PEAK_GOPS, 1),
-                "unit": "Gop/s", "frac": round(achieved / VALU_PEAK_GOPS, 4), "traffic": traffic,
-                "kernel": "trace_kernel + shadow_kernel + shadow_merge_kernel", "kernel_ms": round(k_ms, 3), "algorithmic_ops": int(aops),
-                "requested_bytes": int(abytes),
-                "requested_gbs": round(abytes / (k_ms * 1e-3) / 1e9, 1), "hbm_peak_gbs": HBM_PEAK_GBS,
-                "traffic_bytes_per_segment": (round(traffic / segments, 1) if traffic else None)}
+    err_plain = rel_l2_on(img, pix, ref) if ref is not None else None
 
     out = {
         "metric": "Mpath-segments/s, plain vs NN-surrogate BSDF, at <=1% rel. L2 image error",
@@ -354,22 +415,38 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl_name,
+        "config": {"workload": WORKLOAD_NAMES[args.workload],
                    "paths_per_step": st["paths"], "segments_per_step": segments,
                    "shadow_rays_per_step": st["shadow_rays"], "bvh_nodes": info["n_nodes"],
-                   "bvh_depth": info["depth"]},
-        "roofline": roofline,
+                   "bvh_depth": info["depth"], "n_tris": info["n_tris"]},
+        "rel_l2_vs_oracle": err_plain,
+        "qualifies": (err_plain is not None and err_plain <= 1e-3),
+        "rel_l2_pixels": f"{len(pix)} pixels: every 8th row and column, all samples and wavelengths",
+        "roofline": roofline_of(st, k_ms, args.workload),
     }
-    if args.hero and len(wl.lambdas_um) % 4 == 0:
-        out["hero"] = hero_leg(R, wl, ms_step, args)
-    if args.aniso:
-        out["aniso"] = aniso_leg(R, wl, ms_step, img, args)
-    if args.coherent and args.workload == "mid":
-        out["coherent"] = coherent_leg(R, args)
     if args.surrogate:
-        out["surrogate"] = surrogate_leg(R, wl, o, img, st, args)
+        out["surrogate"] = surrogate_leg(R, wl, img, ms_step, pix, ref, leg_steps)
+    if args.hero and len(wl.lambdas_um) % 4 == 0:
+        out["hero"] = hero_leg(R, wl, ms_step, leg_steps)
+    if args.aniso:
+        out["aniso"] = aniso_leg(R, wl, ms_step, img, leg_steps)
+    if args.coherent:
+        out["coherent"] = coherent_leg(R, leg_steps)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline_from(wl, pix, dt_or, seg_or, osc, threads, args.workload)
+    if args.workload == "large" and args.mid:
+        wm = load("mid")
+        pm = subset_pixels(wm)
+        ref_m = None if args.no_cpu else oracle_subset(wm, pm, threads)[0]
+        info_m = R.load_workload(wm)
+        _, img_m, st_m, ms_m, k_ms_m = plain_frame(R, wm, 1, args.steps)
+        err_m = rel_l2_on(img_m, pm, ref_m) if ref_m is not None else None
+        out["mid"] = {"workload": WORKLOAD_NAMES["mid"], "value": round(st_m["segments"] / (ms_m * 1e-3) / 1e6, 2),
+                      "unit": "Mpath-segments/s", "ms_per_step": round(ms_m, 3), "steps": args.steps,
+                      "segments_per_step": st_m["segments"], "bvh_nodes": info_m["n_nodes"],
+                      "rel_l2_vs_oracle": err_m, "qualifies": (err_m is not None and err_m <= 1e-3),
+                      "rel_l2_pixels": f"{len(pm)} pixels: every 8th row and column",
+                      "roofline": roofline_of(st_m, k_ms_m, "mid")}
     print(json.dumps(out), flush=True)
     R.close()
 

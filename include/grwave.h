@@ -95,7 +95,7 @@ typedef struct {
 enum {
     GR_TRACE_KEEP_PATHS = 1,
     GR_TRACE_SHORT_LDS_STACK = 2,
-    GR_TRACE_WAVEFRONT = 4,
+    /* 4 is not used */
     GR_TRACE_HERO = 8,
     GR_TRACE_ANISO = 16
 };
@@ -116,10 +116,7 @@ enum {
  *                          only 4 BVH traversal-stack entries per lane in LDS and the rest in
  *                          the workspace (normally 32 stay in LDS and only BVHs deeper than 9
  *                          levels overflow); the image is identical, the render slower.  It
- *                          exists to exercise the overflow path.  GR_TRACE_WAVEFRONT renders
- *                          with the wavefront kernels (per-bounce queues in the workspace)
- *                          instead of the persistent path kernel; the image is the same up to
- *                          the rounding of a few shortened paths.  GR_TRACE_HERO traces
+ *                          exists to exercise the overflow path.  GR_TRACE_HERO traces
  *                          hero-wavelength paths (Sec. "Interactive Rendering", implementation
  *                          details: the hero wavelength drives the path and up to three more
  *                          wavelengths ride along): the n_lambda wavelengths (a multiple of 4)
@@ -130,8 +127,8 @@ enum {
  *                          balance heuristic over the choice of hero (grating orders other than
  *                          0 are dispersive and carry the hero alone).  A quarter of the paths
  *                          of the default render, a different estimator of the same image; the
- *                          records keep their layout.  Closed-form p_w and the persistent
- *                          kernel only (else GR_E_UNSUPPORTED).  GR_TRACE_ANISO carries
+ *                          records keep their layout.  Closed-form p_w only (else
+ *                          GR_E_UNSUPPORTED).  GR_TRACE_ANISO carries
  *                          anisotropic generalized rays (Sec. "Generalized rays": beta, rho as
  *                          positive-definite matrices): the ray's phase-space second moments
  *                          over its two transverse axes go through the free-space law in matrix
@@ -141,9 +138,8 @@ enum {
  *                          lobe leaving at another angle than it arrived stretches the ray
  *                          along the plane of scattering; the footprint at each hit is the
  *                          ray's spatial moments on the surface.  Without the flag beta, rho
- *                          stay scalar and interactions leave them unchanged.  Closed-form p_w,
- *                          one wavelength per path and the persistent kernel only (else
- *                          GR_E_UNSUPPORTED).  Other bits are invalid. */
+ *                          stay scalar and interactions leave them unchanged.  Closed-form p_w
+ *                          and one wavelength per path only (else GR_E_UNSUPPORTED).  Other bits are invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;

@@ -18,7 +18,6 @@ ERRORS = {-1: "GR_E_INVALID", -2: "GR_E_NO_SCENE", -3: "GR_E_DEVICE", -4: "GR_E_
 GR_BSDF_PLAIN, GR_BSDF_SURROGATE_BF16, GR_BSDF_SURROGATE_FP8 = 0, 1, 2
 GR_TRACE_KEEP_PATHS = 1
 GR_TRACE_SHORT_LDS_STACK = 2
-GR_TRACE_WAVEFRONT = 4
 GR_TRACE_HERO = 8
 GR_TRACE_ANISO = 16
 GR_MLP_PARAMS = 13249

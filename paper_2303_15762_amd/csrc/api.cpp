@@ -44,8 +44,6 @@ struct gr_ctx {
     int grid_hero = 0;
     int grid_aniso = 0;
     int grid_batch = 0;              // blocks of the batched network pass
-    int grid_wf = 0;                 // blocks of the wavefront traversal kernels
-    int grid_work = 0;               // blocks of the grid-stride wavefront kernels
     grw::SurrogateState sur;
 };
 
@@ -107,80 +105,15 @@ constexpr uint64_t kSurSlots = 1ull << 30;
 // ... within this many bytes of queued network queries, queued shadow rays and results (2^30
 // slots of a shadow ray and a result; the learned p_w adds a query per slot).
 constexpr uint64_t kQueueBytes = (1ull << 30) * 52;
-// The wavefront kernels keep per-path state of a launch of at most this many paths.
-constexpr uint64_t kWfChunk = 1ull << 23;
-
 struct WsLayout {
-    size_t records = 0, ovf = 0, wf = 0, queue = 0, shadow = 0, dense = 0, nd = 0, total = 0;
+    size_t records = 0, ovf = 0, queue = 0, shadow = 0, dense = 0, nd = 0, total = 0;
     uint64_t chunk = 0;
-    size_t wf_bytes = 0;
 };
 
-bool wavefront_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_WAVEFRONT) != 0; }
 bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
 bool aniso_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_ANISO) != 0; }
 // one wavelength per path in the persistent kernel: shadow rays go through a queue of their own
-bool shadow_queue_of(const gr_trace_opts* o) { return !wavefront_of(o) && !hero_of(o); }
-
-// Per-path wavefront arrays in this order, each padded to 256 B (element sizes in bytes).
-constexpr int kWfArrays = 27;
-constexpr int kWfElem[kWfArrays] = {8, 8, 8,                       // ox oy oz
-                                    4, 4, 4, 4, 4, 4, 4,           // dx dy dz beta2 rho alpha contrib
-                                    4, 4, 4, 4, 4,                 // prev hit ht hu hv
-                                    4, 4,                          // list0 list1
-                                    4, 8, 8, 8, 4, 4, 4, 4,        // s_path s_px s_py s_pz s_dx s_dy s_dz s_tmax
-                                    4, 4};                         // s_skip s_mat
-// plus s_q ([kShadowQ][n] floats) and s_vis (bytes)
-
-size_t wf_bytes(uint64_t n) {
-    size_t b = 0;
-    for (int i = 0; i < kWfArrays; ++i) b += align256((size_t)n * kWfElem[i]);
-    b += align256((size_t)n * grw::kShadowQ * sizeof(float));
-    b += align256((size_t)n);
-    return b;
-}
-
-grw::WfArgs wf_args(char* base, uint64_t n) {
-    grw::WfArgs w{};
-    w.n = n;
-    char* p = base;
-    void* arr[kWfArrays];
-    for (int i = 0; i < kWfArrays; ++i) {
-        arr[i] = p;
-        p += align256((size_t)n * kWfElem[i]);
-    }
-    w.ox = (double*)arr[0];
-    w.oy = (double*)arr[1];
-    w.oz = (double*)arr[2];
-    w.dx = (float*)arr[3];
-    w.dy = (float*)arr[4];
-    w.dz = (float*)arr[5];
-    w.beta2 = (float*)arr[6];
-    w.rho = (float*)arr[7];
-    w.alpha = (float*)arr[8];
-    w.contrib = (float*)arr[9];
-    w.prev = (int*)arr[10];
-    w.hit = (int*)arr[11];
-    w.ht = (float*)arr[12];
-    w.hu = (float*)arr[13];
-    w.hv = (float*)arr[14];
-    w.list[0] = (uint32_t*)arr[15];
-    w.list[1] = (uint32_t*)arr[16];
-    w.s_path = (uint32_t*)arr[17];
-    w.s_px = (double*)arr[18];
-    w.s_py = (double*)arr[19];
-    w.s_pz = (double*)arr[20];
-    w.s_dx = (float*)arr[21];
-    w.s_dy = (float*)arr[22];
-    w.s_dz = (float*)arr[23];
-    w.s_tmax = (float*)arr[24];
-    w.s_skip = (int*)arr[25];
-    w.s_mat = (int*)arr[26];
-    w.s_q = (float*)p;
-    p += align256((size_t)n * grw::kShadowQ * sizeof(float));
-    w.s_vis = (uint8_t*)p;
-    return w;
-}
+bool shadow_queue_of(const gr_trace_opts* o) { return !hero_of(o); }
 
 // Traversal-stack entries per lane that do not fit the LDS part.
 uint32_t overflow_entries(const gr_ctx* c, const gr_trace_opts* o) {
@@ -318,12 +251,6 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
         c->grid_batch = 4 * std::max(ncu, 1);
-        c->grid_work = 8 * std::max(ncu, 1);
-    }
-    c->grid_wf = grw::wavefront_trav_grid(c->device);
-    if (c->grid_wf <= 0) {
-        free_scene(c);
-        return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
     if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0 || c->grid_aniso <= 0) {
         free_scene(c);
@@ -394,19 +321,17 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
     const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
     const size_t lanes =
-        (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso, c->grid_wf}) * 256;
+        (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso}) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
-    L.wf = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
+    L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
     const bool defer = o->bsdf_mode != GR_BSDF_PLAIN, shq = shadow_queue_of(o);
     // bytes per (path, interaction) slot: a network query, a shadow ray, the result float (and
     // one byte per path: its stored slot count)
     const uint64_t slot_bytes = (defer ? grw::kSurQueryBytes : 0) + (shq ? grw::kShadowQueryBytes : 0) + 4;
     const uint64_t slots_max = std::min<uint64_t>(kSurSlots, kQueueBytes / slot_bytes);
     const uint64_t sur_chunk = std::min<uint64_t>(kSurChunk, slots_max / (uint64_t)std::max(o->max_depth, 1));
-    L.chunk = std::min<uint64_t>(n, wavefront_of(o) ? kWfChunk : sur_chunk);
-    L.wf_bytes = wavefront_of(o) ? wf_bytes(L.chunk) : 0;
-    L.queue = L.wf + L.wf_bytes;
+    L.chunk = std::min<uint64_t>(n, sur_chunk);
     const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
     L.shadow = L.queue + (defer ? align256((size_t)slots * grw::kSurQueryBytes) : 0);
     L.dense = L.shadow + (shq ? align256((size_t)slots * grw::kShadowQueryBytes) : 0);
@@ -430,8 +355,12 @@ int gr_workspace_paths(const gr_ctx* c, void* ws, float** paths) {
     return GR_OK;
 }
 
-int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, void* ws, size_t ws_bytes,
-             float* image, gr_stats* st) {
+}  // extern "C"
+
+namespace {
+
+int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, void* ws, size_t ws_bytes,
+               float* image, gr_stats* st) {
     if (!c) return GR_E_INVALID;
     if (!lambda || !o || !image) return fail(c, GR_E_INVALID, "trace: null argument");
     if (nl < 1 || nl > grw::kMaxLambda) return fail(c, GR_E_INVALID, "trace: n_lambda %d", nl);
@@ -442,15 +371,15 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
     if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
     if (o->flags &
-        ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_WAVEFRONT | GR_TRACE_HERO | GR_TRACE_ANISO))
+        ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_HERO | GR_TRACE_ANISO))
         return fail(c, GR_E_INVALID, "trace: flags");
-    if (aniso_of(o) && (hero_of(o) || o->bsdf_mode != GR_BSDF_PLAIN || wavefront_of(o)))
+    if (aniso_of(o) && (hero_of(o) || o->bsdf_mode != GR_BSDF_PLAIN))
         return fail(c, GR_E_UNSUPPORTED,
-                    "trace: anisotropic rays with the closed-form p_w, one wavelength per path and the persistent kernel only");
+                    "trace: anisotropic rays with the closed-form p_w and one wavelength per path only");
     if (hero_of(o)) {
         if (nl % 4 != 0) return fail(c, GR_E_INVALID, "trace: hero wavelengths need n_lambda %% 4 == 0 (got %d)", nl);
-        if (o->bsdf_mode != GR_BSDF_PLAIN || wavefront_of(o))
-            return fail(c, GR_E_UNSUPPORTED, "trace: hero wavelengths with the closed-form p_w and the persistent kernel only");
+        if (o->bsdf_mode != GR_BSDF_PLAIN)
+            return fail(c, GR_E_UNSUPPORTED, "trace: hero wavelengths with the closed-form p_w only");
     }
     if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
@@ -548,31 +477,9 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (st)
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));
-    GR_HIP(c, hipMemsetAsync(ws, 0, kWsHeader, c->stream));
+    GR_HIP(c, grw::launch_zero_words(reinterpret_cast<uint32_t*>(ws), kWsHeader / 4, c->stream));
     if (st) GR_HIP(c, hipEventRecord(ev[0], c->stream));
-    if (wavefront_of(o)) {
-        // launches of at most WL.chunk paths through the wavefront kernels (state, queues and
-        // shadow records in the workspace); with the learned p_w each launch's queued queries
-        // are evaluated and merged before the next launch reuses the queue
-        const int D = o->max_depth;
-        const grw::WfArgs w0 = wf_args(base + WL.wf, WL.chunk);
-        for (uint64_t p0 = 0; p0 < total; p0 += WL.chunk) {
-            const uint64_t pn = std::min<uint64_t>(WL.chunk, total - p0);
-            grw::WfArgs w = w0;
-            w.n = pn;
-            w.cnt = reinterpret_cast<unsigned int*>(base + 192);
-            a.path_begin = p0;
-            a.n_paths = pn;
-            if (defer)
-                GR_HIP(c, grw::launch_chunk_reset(a.counter, a.sq_count, nullptr, dense, pn * (uint64_t)D, c->stream));
-            GR_HIP(c, grw::launch_wavefront(a, w, c->grid_wf, c->grid_work, c->stream));
-            if (defer) {
-                GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
-                GR_HIP(c, grw::launch_sur_merge(dense, D, a.records, p0, pn, c->stream));
-            }
-        }
-        a.n_paths = total;
-    } else if (shq) {
+    if (shq) {
         // launches of at most WL.chunk paths: trace (measurement values to the path's slots,
         // learned-p_w queries and shadow rays queued; each path clears its own slots), one
         // batched network pass over the query queue (its results to their slots), the queued
@@ -622,6 +529,15 @@ int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o,
         st->ms_reduce = ms_r;
     }
     return GR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, void* ws, size_t ws_bytes,
+             float* image, gr_stats* st) {
+    return trace_impl(c, lambda, nl, o, ws, ws_bytes, image, st);
 }
 
 int gr_bsdf_eval(gr_ctx* c, const float* q, int64_t n, int32_t mode, float* out) {

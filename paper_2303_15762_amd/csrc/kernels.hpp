@@ -48,9 +48,8 @@ struct SurrogateDev {
 };
 
 // One deferred learned-p_w query, 32 bytes: the 10 network inputs as bfloat16 pairs (the
-// network rounds its inputs to bfloat16 anyway), the contribution scale (the wavefront form
-// divides it by the sample count; in the persistent kernel's launches the merge does), log of
-// the lobe peak, and the (path, depth) slot of the result.
+// network rounds its inputs to bfloat16 anyway), the contribution scale (the merge divides it
+// by the sample count), log of the lobe peak, and the (path, depth) slot of the result.
 constexpr int kSurQueryBytes = 32;
 
 struct TraceArgs {
@@ -95,34 +94,6 @@ enum {
     ST_NONFINITE, ST_NODES, ST_TRIS, ST_COUNT
 };
 
-// Wavefront form of the tracer (wavefront.hip): the paths of a launch advance one interaction
-// per bounce through separate kernels that work on lists: closest hit, shading, shadow rays,
-// and the measurement of the visible ones.  Per-path state lives in these arrays ([n] each).
-enum { WC_LIST0 = 0, WC_LIST1, WC_SHADOW, WC_FETCH_E, WC_FETCH_S, WC_COUNT };
-constexpr int kShadowQ = 9;   // floats of a shadow record's measurement: kix, kiy, kox, koy, sxx, syy, sxy, scale, k
-
-struct WfArgs {
-    uint64_t n;                       // paths of this launch
-    double *ox, *oy, *oz;             // path origin (double)
-    float *dx, *dy, *dz;              // travel direction
-    float *beta2, *rho, *alpha, *contrib;
-    int* prev;                        // original index of the triangle the path leaves, or -1
-    int* hit;                         // closest hit of the bounce (leaf order), or -1
-    float *ht, *hu, *hv;
-    uint32_t* list[2];                // paths entering the bounce / continuing to the next
-    // shadow rays of the bounce
-    uint32_t* s_path;
-    double *s_px, *s_py, *s_pz;
-    float *s_dx, *s_dy, *s_dz, *s_tmax;
-    int *s_skip, *s_mat;
-    float* s_q;                       // [kShadowQ][n]
-    uint8_t* s_vis;
-    unsigned int* cnt;                // [WC_COUNT] device counters
-};
-
-hipError_t launch_wavefront(const TraceArgs& a, const WfArgs& w, int grid_trav, int grid_work, hipStream_t s);
-int wavefront_trav_grid(int device);
-
 // Launchers (trace.hip).
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s);
 hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, uint32_t H, uint32_t W,
@@ -131,9 +102,9 @@ hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, 
 // floats of per-(path, depth) results.
 hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* sq_count,
                               unsigned long long* shq_count, float* dense, uint64_t n, hipStream_t s);
-// records[p0 + i] += sum over d < depth of dense[i * depth + d], i < n (fixed order).
-hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s);
 hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s);
+// p[0 .. n) = 0 (32-bit words)
+hipError_t launch_zero_words(uint32_t* p, uint64_t n, hipStream_t s);
 // records[p0 + i] = inv_spp_norm * sum over d < nd[i] of val[i * depth + d], i < n (fixed order)
 hipError_t launch_shadow_merge(const float* val, const uint8_t* nd, int depth, float* records, uint64_t p0,
                                uint64_t n, float inv_spp_norm, unsigned long long* stats, hipStream_t s);

@@ -796,13 +796,18 @@ __global__ __launch_bounds__(256) void chunk_reset_kernel(unsigned long long* co
     for (uint64_t i = t; i < n; i += (uint64_t)gridDim.x * blockDim.x) dense[i] = 0.0f;
 }
 
-__global__ __launch_bounds__(256) void sur_merge_kernel(const float* __restrict__ dense, int depth,
-                                                        float* __restrict__ records, uint64_t p0, uint64_t n) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float s = 0.0f;
-    for (int d = 0; d < depth; ++d) s += dense[i * depth + d];
-    records[p0 + i] += s;
+// Zero n 32-bit words (a kernel rather than a memset node, so a captured graph replays it
+// like any other launch).
+__global__ __launch_bounds__(256) void zero_words_kernel(uint32_t* p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t* p, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_shadow(const TraceArgs& a, int grid, hipStream_t s) {
@@ -823,13 +828,6 @@ hipError_t launch_chunk_reset(unsigned long long* counter, unsigned long long* s
     const uint64_t blocks = std::min<uint64_t>((n + 255) / 256 + 1, 4096);
     hipLaunchKernelGGL(chunk_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, counter, sq_count, shq_count,
                        dense, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_sur_merge(const float* dense, int depth, float* records, uint64_t p0, uint64_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(sur_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dense, depth, records,
-                       p0, n);
     return hipGetLastError();
 }
 

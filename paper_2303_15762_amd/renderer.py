@@ -74,7 +74,6 @@ class Renderer:
         self.h = h
         self._ws = None
         self.sensor = None
-        self.wavefront = False   # default of opts(): GR_TRACE_WAVEFRONT
 
     def close(self):
         if getattr(self, "h", None):
@@ -131,7 +130,7 @@ class Renderer:
     # -- trace -----------------------------------------------------------------------------
     def opts(self, spp_begin=0, spp_count=1, spp_norm=None, max_depth=1, bsdf_mode=0,
              rr_enable=False, rr_p=0.8, seed=0, keep_paths=False,
-             short_lds_stack=False, wavefront=None, hero=False, aniso=False) -> L.GrTraceOpts:
+             short_lds_stack=False, hero=False, aniso=False) -> L.GrTraceOpts:
         o = L.GrTraceOpts()
         o.spp_begin = int(spp_begin)
         o.spp_count = int(spp_count)
@@ -141,9 +140,8 @@ class Renderer:
         o.rr_enable = int(bool(rr_enable))
         o.rr_p = float(rr_p)
         o.seed = int(seed)
-        wf = self.wavefront if wavefront is None else wavefront
         o.flags = (L.GR_TRACE_KEEP_PATHS if keep_paths else 0) | \
-            (L.GR_TRACE_SHORT_LDS_STACK if short_lds_stack else 0) | (L.GR_TRACE_WAVEFRONT if wf else 0) | \
+            (L.GR_TRACE_SHORT_LDS_STACK if short_lds_stack else 0) | \
             (L.GR_TRACE_HERO if hero else 0) | (L.GR_TRACE_ANISO if aniso else 0)
         return o
 

@@ -90,10 +90,11 @@ def test_trace_rejects_before_device_use(ctx):
     o.bsdf_mode = 0
     assert lib.gr_trace(h, bad, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
     # flags: unknown bits, and hero-wavelength paths or anisotropic rays outside what they support
-    o.flags = 32
-    assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
-    for extra, mode in ((L.GR_TRACE_WAVEFRONT, 0), (0, 1), (0, 2)):
-        o.flags = L.GR_TRACE_ANISO | extra
+    for bad_flag in (4, 32):
+        o.flags = bad_flag
+        assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
+    for mode in (1, 2):
+        o.flags = L.GR_TRACE_ANISO
         o.bsdf_mode = mode
         assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
         assert b"anisotropic" in lib.gr_last_error(h)
@@ -104,8 +105,6 @@ def test_trace_rejects_before_device_use(ctx):
     assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
     assert b"n_lambda" in lib.gr_last_error(h)
     lam4 = (C.c_float * 4)(0.45, 0.5, 0.55, 0.6)
-    o.flags = L.GR_TRACE_HERO | L.GR_TRACE_WAVEFRONT
-    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
     o.flags = L.GR_TRACE_HERO
     o.bsdf_mode = 1
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5

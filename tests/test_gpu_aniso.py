@@ -135,7 +135,7 @@ def test_aniso_terrain_full_size_sampled_pixels(R):
 def test_aniso_rejected_where_unsupported(R):
     wl = W.mid_terrain(width=8, height=8, spp=1, n_lambda=4)
     R.load_workload(wl)
-    for kw in (dict(hero=True), dict(wavefront=True), dict(bsdf_mode=1)):
+    for kw in (dict(hero=True), dict(bsdf_mode=1)):
         o = R.opts(spp_count=1, max_depth=2, seed=1, aniso=True, **kw)
         with pytest.raises(GrError):
             R.trace(wl.lambdas_um, o)

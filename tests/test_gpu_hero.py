@@ -141,7 +141,7 @@ def test_hero_rejected_where_unsupported(R):
         R.render_workload(wl, hero=True)                   # 3 wavelengths: not groups of 4
     wl = W.mid_terrain(width=8, height=8, spp=1, n_lambda=4)
     R.load_workload(wl)
-    o = R.opts(spp_count=1, max_depth=2, seed=1, hero=True, wavefront=True)
+    o = R.opts(spp_count=1, max_depth=2, seed=1, hero=True, bsdf_mode=1)
     with pytest.raises(GrError):
         R.trace(wl.lambdas_um, o)
     img, st = R.render_workload(wl, hero=True)             # one group of 4: fine

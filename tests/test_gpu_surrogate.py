@@ -163,21 +163,3 @@ def test_fp8_surrogate_against_bf16_and_oracle(trained):
         print("image mode", mode, "rel L2", errs[mode], "surrogate evals", st["surrogate_evals"])
         assert st["surrogate_evals"] > 0
     assert errs[2] <= 1e-2
-
-
-def test_wavefront_form_with_learned_pw(trained):
-    """The learned p_w through the wavefront kernels: queued from the measurement kernel,
-    evaluated in the same batched pass, same image as the persistent kernel's."""
-    R, S, p, hist, torch = trained
-    wl = W.mid_terrain(width=41, height=29, spp=16, n_lambda=8)
-    R.load_workload(wl)
-    o = dict(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed, bsdf_mode=1)
-    a, sa = R.trace(wl.lambdas_um, R.opts(wavefront=False, **o))
-    b, sb = R.trace(wl.lambdas_um, R.opts(wavefront=True, **o))
-    e = rel_l2(b.cpu().numpy(), a.cpu().numpy().astype(np.float64))
-    print("learned p_w, wavefront vs persistent: rel L2", e, sa, sb)
-    assert e <= 1e-5
-    # the persistent kernel queues a query before its shadow ray is traced (an occluded one is
-    # evaluated and then cleared); the wavefront form queues visible measurements only
-    assert sa["surrogate_evals"] >= sb["surrogate_evals"] > 0
-    assert sa["surrogate_evals"] + sa["fallbacks"] >= sb["surrogate_evals"] + sb["fallbacks"]

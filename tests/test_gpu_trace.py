@@ -178,27 +178,6 @@ def test_traversal_stack_overflow_path(R):
         assert abs(sa[key] - sb[key]) <= 1e-3 * sa[key]
 
 
-def test_wavefront_form_matches(R):
-    """The wavefront kernels (per-bounce lists and shadow records in the workspace) trace the
-    same paths with the same random numbers: the image matches the oracle at the same bound and
-    the persistent kernel's image to FP32 rounding, the counters agree, and two renders are
-    bitwise identical."""
-    wl = W.mid_terrain(width=41, height=29, spp=16, n_lambda=8)
-    R.load_workload(wl)
-    o = dict(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed)
-    a, sa = R.trace(wl.lambdas_um, R.opts(wavefront=False, **o))
-    b, sb = R.trace(wl.lambdas_um, R.opts(wavefront=True, **o))
-    c, _ = R.trace(wl.lambdas_um, R.opts(wavefront=True, **o))
-    a, b, c = (x.cpu().numpy() for x in (a, b, c))
-    ref, _ = oracle.render(wl)
-    print("wavefront: rel L2 vs oracle", rel_l2(b, ref), "vs persistent", rel_l2(b, a), sb)
-    assert rel_l2(b, ref) <= RTOL_IMAGE
-    assert rel_l2(b, a) <= 1e-5
-    assert np.array_equal(b, c)
-    for key in ("paths", "segments", "shadow_rays", "evanescent", "backfacing"):
-        assert sa[key] == sb[key]
-
-
 def _terrain_variant(name):
     """The small terrain with rough surfaces on every tile (the Poisson-series p_w and its
     sampler everywhere), or with a second, plane-wave source, Russian roulette and paths of up
