@@ -236,6 +236,24 @@ int gr_workspace_paths(const gr_ctx* ctx, void* workspace, float** paths_dev);
 int gr_trace(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_trace_opts* opts,
              void* workspace, size_t workspace_bytes, float* image, gr_stats* stats);
 
+/* gr_trace without a workspace argument and without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same kernels, launches and image as gr_trace (bit for bit); the workspace
+ * is a 64 MiB array in the library's device memory (one per GPU, held until the process
+ * ends; its address is looked up on the first call on each device).  The call allocates
+ * nothing (no hipMalloc, hipFree, events or library allocations), clears what must start at
+ * zero with kernels (no memset nodes), enqueues on the context's stream and returns without
+ * synchronising; no statistics.
+ *   image : device float [n_lambda][height][width], caller-owned; contributions are ADDED.
+ * Errors: as gr_trace; GR_E_WORKSPACE when gr_workspace_size for these options exceeds
+ * 64 MiB (e.g. a 41 x 29 sensor with 8 wavelengths, 16 samples and depth 4 needs about
+ * 33 MB; full-size frames need gr_trace).  Every call on one GPU shares that GPU's array,
+ * which keeps the last call's contents: calls that overlap on one GPU (two streams, two
+ * contexts, two threads) race and must be serialised by the caller.  The per-path records
+ * of GR_TRACE_KEEP_PATHS stay in the array and are not accessible. */
+int gr_trace_noalloc(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_trace_opts* opts,
+                     float* image);
+
 /* Windowed diffraction density p_w(k_i,t -> k_o,t) (um^2) for a batch of queries (device).
  * Row layout (14 floats): kind, height_um, length_um, reflectance, k (um^-1), kix, kiy, kox,
  * koy (tangential wavevectors in the material frame, um^-1), sxx, syy, sxy (footprint

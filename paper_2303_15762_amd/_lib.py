@@ -89,6 +89,7 @@ SIGNATURES = [
     ("gr_workspace_paths", C.c_int, [_vp, _vp, C.POINTER(_fp)]),
     ("gr_trace", C.c_int, [_vp, _fp, C.c_int32, C.POINTER(GrTraceOpts), _vp, C.c_size_t, _fp,
                            C.POINTER(GrStats)]),
+    ("gr_trace_noalloc", C.c_int, [_vp, _fp, C.c_int32, C.POINTER(GrTraceOpts), _fp]),
     ("gr_bsdf_eval", C.c_int, [_vp, _fp, C.c_int64, C.c_int32, _fp]),
     ("gr_surrogate_samples", C.c_int, [_vp, C.c_int64, C.c_uint64, _fp, _fp, _fp, _fp]),
     ("gr_mlp_workspace_size", C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),

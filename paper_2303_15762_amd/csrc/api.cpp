@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -359,8 +360,33 @@ int gr_workspace_paths(const gr_ctx* c, void* ws, float** paths) {
 
 namespace {
 
+// Allocation-free traces run in this file-scope device array instead of a caller workspace.
+// Host code never passes `scratch` itself to a kernel (on the host the name is a stand-in, not
+// a device address): each device's copy is looked up once with hipGetSymbolAddress, with that
+// device current, and only that address is used.
+constexpr size_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up on the first call).
+hipError_t scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
+
+// gr_trace and gr_trace_noalloc: ws == nullptr with use_scratch selects the static array.
 int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, void* ws, size_t ws_bytes,
-               float* image, gr_stats* st) {
+               float* image, gr_stats* st, bool use_scratch) {
     if (!c) return GR_E_INVALID;
     if (!lambda || !o || !image) return fail(c, GR_E_INVALID, "trace: null argument");
     if (nl < 1 || nl > grw::kMaxLambda) return fail(c, GR_E_INVALID, "trace: n_lambda %d", nl);
@@ -388,6 +414,16 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
         return fail(c, GR_E_INVALID, "trace: sensor");
     size_t need = 0;
     gr_workspace_size(c, o, nl, &need);
+    if (use_scratch) {
+        if (need > kScratchBytes)
+            return fail(c, GR_E_WORKSPACE,
+                        "trace_noalloc: this trace needs %zu bytes of workspace, more than the %zu-byte static "
+                        "scratch array; use gr_trace with a caller workspace",
+                        need, kScratchBytes);
+        GR_HIP(c, hipSetDevice(c->device));
+        GR_HIP(c, scratch_address(c->device, &ws));
+        ws_bytes = kScratchBytes;
+    }
     if (!ws || ws_bytes < need) return fail(c, GR_E_WORKSPACE, "trace: workspace %zu < %zu bytes", ws_bytes, need);
     if ((reinterpret_cast<uintptr_t>(ws) & 15) != 0) return fail(c, GR_E_INVALID, "trace: workspace alignment");
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
@@ -537,7 +573,11 @@ extern "C" {
 
 int gr_trace(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, void* ws, size_t ws_bytes,
              float* image, gr_stats* st) {
-    return trace_impl(c, lambda, nl, o, ws, ws_bytes, image, st);
+    return trace_impl(c, lambda, nl, o, ws, ws_bytes, image, st, false);
+}
+
+int gr_trace_noalloc(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* o, float* image) {
+    return trace_impl(c, lambda, nl, o, nullptr, 0, image, nullptr, true);
 }
 
 int gr_bsdf_eval(gr_ctx* c, const float* q, int64_t n, int32_t mode, float* out) {

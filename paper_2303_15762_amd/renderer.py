@@ -169,6 +169,15 @@ class Renderer:
         self._check(rc, "gr_trace")
         return image, (st.as_dict() if st is not None else None)
 
+    def trace_noalloc(self, lambdas_um, opts: L.GrTraceOpts, image):
+        """gr_trace_noalloc: the same trace in the library's static device workspace; adds to the
+        caller's image [n_lambda, H, W] float32 tensor.  No allocation, no synchronisation."""
+        lam = np.ascontiguousarray(np.asarray(lambdas_um, np.float32))
+        rc = self.lib.gr_trace_noalloc(self.h, lam.ctypes.data_as(C.POINTER(C.c_float)), lam.shape[0],
+                                       C.byref(opts), _fptr(image))
+        self._check(rc, "gr_trace_noalloc")
+        return image
+
     def path_records(self, opts: L.GrTraceOpts, n_lambda: int):
         """Per-path contributions kept by the last trace with keep_paths: a tensor view
         [spp_count, H, W, n_lambda] of the workspace."""
