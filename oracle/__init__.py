@@ -94,6 +94,7 @@ def lib():
             L.or_scene_create.restype = C.c_void_p
             L.or_scene_destroy.argtypes = [C.c_void_p]
             L.or_intersect.argtypes = [C.c_void_p, dp, C.c_int64, C.c_double, C.c_int, dp]
+            L.or_interaction.argtypes = [C.c_void_p, dp, C.c_double, dp, dp]
             L.or_trace.argtypes = [C.c_void_p, C.POINTER(OrSensor), C.POINTER(OrSource),
                                    C.c_int32, dp, C.c_int32, C.POINTER(OrOpts),
                                    C.POINTER(C.c_int32), C.c_int64, dp, dp,
@@ -270,6 +271,16 @@ class OracleScene:
         if getattr(self, "h", None):
             lib().or_scene_destroy(self.h)
             self.h = None
+
+    def interaction(self, origin, direction, k, u=(0.5, 0.5, 0.5)):
+        """One interaction of the path loop: dict with hit, ns, ng, ci, the continuation
+        direction sampled with uniforms u at wavenumber k (um^-1), its weight, and ended."""
+        ray = np.ascontiguousarray(np.concatenate([np.asarray(origin, np.float64).ravel(),
+                                                   np.asarray(direction, np.float64).ravel()]))
+        out = np.zeros(13)
+        lib().or_interaction(self.h, _dp(ray), float(k), _dp(np.ascontiguousarray(u, np.float64)), _dp(out))
+        return {"hit": bool(out[0]), "ns": out[1:4], "ng": out[4:7], "ci": out[7],
+                "dir": out[8:11], "weight": out[11], "ended": bool(out[12])}
 
     def intersect(self, origins, dirs, tmin=-1.0, use_bvh=True):
         rays = np.ascontiguousarray(np.concatenate([origins, dirs], 1), np.float64)

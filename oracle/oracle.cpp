@@ -165,6 +165,9 @@ double besselj(int n, double x) {
                                      : std::cyl_bessel_j((double)an, -x))
                          : std::cyl_bessel_j((double)an, x);
     if (n < 0 && (an & 1)) v = -v;
+    // Far beyond the turning point (order above the argument) J_n(x) underflows; the library
+    // routine returns NaN there instead of 0 (e.g. order 1000 at x = 228).
+    if (std::isnan(v) && (double)an > std::fabs(x)) v = 0.0;
     return v;
 }
 
@@ -1055,6 +1058,36 @@ void or_intersect(void* s, const double* rays, int64_t n, double tmin, int use_b
         out[4 * i + 2] = hit ? h.u : 0;
         out[4 * i + 3] = hit ? h.v : 0;
     }
+}
+
+// One interaction of the path loop, exposed for checking: closest hit of the ray (o, d), the
+// vertex (shading normal interpolated from the hit's barycentrics and oriented like the path
+// loop orients it) and the continuation sampled from f_inf with uniforms u[3] at wavenumber k.
+// out: [hit (1 or 0), ns (3), ng (3), cos i, continuation direction (3), weight, ended (1 when
+// the path ends there: back-facing or evanescent)].
+void or_interaction(void* s, const double* ray, double k, const double* u, double* out) {
+    const SceneO& S = *(SceneO*)s;
+    for (int i = 0; i < 13; ++i) out[i] = 0.0;
+    V3 o = ld3(ray), d = unit(ld3(ray + 3));
+    Hit h;
+    if (!trace_ray(S, o, d, t_eps(o), 1e300, true, false, h)) return;
+    out[0] = 1.0;
+    Vertex v;
+    const bool front = make_vertex(S, o, d, h, v);
+    out[1] = v.ns.x; out[2] = v.ns.y; out[3] = v.ns.z;
+    out[4] = v.ng.x; out[5] = v.ng.y; out[6] = v.ng.z;
+    out[7] = v.ci;
+    if (!front) { out[12] = 1.0; return; }
+    double kox, koy, wgt;
+    int ev;
+    if (!sample_finf(*v.m, k, k * v.dx, k * v.dy, v.ci, u[0], u[1], u[2], 1.0, 0.0, kox, koy, wgt, ev)) {
+        out[12] = 1.0;
+        return;
+    }
+    double kn = std::sqrt(std::max(0.0, 1.0 - (kox * kox + koy * koy) / (k * k)));
+    V3 dn = unit((kox / k) * v.xa + (koy / k) * v.ya + kn * v.ns);
+    out[8] = dn.x; out[9] = dn.y; out[10] = dn.z;
+    out[11] = wgt;
 }
 
 // Render.  pixels: optional list of (x, y) pairs (npix of them); when null, every pixel of
