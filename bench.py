@@ -102,6 +102,32 @@ def rel_l2_on(img_gpu, pix, ref):
     return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
 
 
+def worst_pixel(img_gpu, pix, ref):
+    """The pixel carrying the largest share of the squared error, and the rel. L2 without it
+    (a single bright, ill-conditioned path can dominate a frame's norm)."""
+    g = img_gpu.detach().double().cpu().numpy()[:, pix[:, 1], pix[:, 0]]
+    e2 = ((g - ref) ** 2).sum(0)
+    i = int(np.argmax(e2))
+    keep = np.ones(len(pix), bool)
+    keep[i] = False
+    rest = float(np.linalg.norm(g[:, keep] - ref[:, keep]) / np.linalg.norm(ref[:, keep]))
+    return {"pixel": [int(pix[i, 0]), int(pix[i, 1])], "share_of_squared_error": round(float(e2[i] / e2.sum()), 4),
+            "its_rel_error": float(np.linalg.norm(g[:, i] - ref[:, i]) / max(np.linalg.norm(ref[:, i]), 1e-300)),
+            "its_share_of_norm2": round(float((ref[:, i] ** 2).sum() / (ref ** 2).sum()), 4),
+            "rel_l2_without_it": rest}
+
+
+def save_subset(args, name, img_gpu, pix, ref):
+    if not args.save_images:
+        return
+    os.makedirs(args.save_images, exist_ok=True)
+    g = img_gpu.detach().cpu().numpy()[:, pix[:, 1], pix[:, 0]]
+    np.save(os.path.join(args.save_images, f"{name}_gpu.npy"), g)
+    np.save(os.path.join(args.save_images, f"{name}_pixels.npy"), pix)
+    if ref is not None:
+        np.save(os.path.join(args.save_images, f"{name}_oracle.npy"), ref)
+
+
 def oracle_subset(wl, pix, threads):
     """The FP64 oracle on the pixel subset (every per-path stream as in the full frame); returns
     (image [n_lambda, n_pixels], seconds, segments)."""
@@ -142,7 +168,7 @@ def time_frames(R, wl, o, img, steps):
     return e0.elapsed_time(e1) / steps
 
 
-def surrogate_leg(R, wl, img_plain, ms_plain, pix, ref, steps):
+def surrogate_leg(R, wl, img_plain, ms_plain, pix, ref, steps, args):
     """Train the learned p_w (outside the timed region), then render the same frame with the
     network (bfloat16 and E4M3 matrix-core operands): frame time, each image against the FP64
     oracle on the pixel subset, and what the network can gain at most on this frame."""
@@ -150,9 +176,16 @@ def surrogate_leg(R, wl, img_plain, ms_plain, pix, ref, steps):
     from paper_2303_15762_amd.surrogate import Surrogate
     S = Surrogate(R)
     t0 = time.perf_counter()
-    p, hist = S.train()
+    if args.surrogate_params:
+        # parameters saved by an earlier run (profiler runs that leave out the training)
+        p = torch.tensor(np.load(args.surrogate_params), device=R.dev)
+        hist = {"step": [0], "val_loss": [None]}
+    else:
+        p, hist = S.train()
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    if args.save_surrogate:
+        np.save(args.save_surrogate, p.cpu().numpy())
     S.install(p)
     legs = {}
     for name, mode in (("bf16", 1), ("fp8", 2)):
@@ -365,6 +398,12 @@ def main():
     ap.add_argument("--workload", choices=["large", "mid"], default="large",
                     help="large: the 4,194,300-triangle instanced scene at 1920x1080, 64 spp, 16 "
                          "wavelengths (the reported line); mid: the 65,536-triangle terrain alone")
+    ap.add_argument("--surrogate-params", default=None,
+                    help="load the learned p_w's parameters (.npy, float32 [13249]) instead of training")
+    ap.add_argument("--save-surrogate", default=None, help="save the trained parameters (.npy)")
+    ap.add_argument("--save-images", default=None,
+                    help="directory: save each leg's image on the oracle's pixel subset and the "
+                         "oracle's (.npy)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (scales the "
                          "HBM byte counters of a profiler run)")
@@ -401,6 +440,7 @@ def main():
     segments = st["segments"]
     value = segments / (ms_step * 1e-3) / 1e6
     err_plain = rel_l2_on(img, pix, ref) if ref is not None else None
+    save_subset(args, args.workload, img, pix, ref)
 
     out = {
         "metric": "Mpath-segments/s, plain vs NN-surrogate BSDF, at <=1% rel. L2 image error",
@@ -422,10 +462,11 @@ def main():
         "rel_l2_vs_oracle": err_plain,
         "qualifies": (err_plain is not None and err_plain <= 1e-3),
         "rel_l2_pixels": f"{len(pix)} pixels: every 8th row and column, all samples and wavelengths",
+        "worst_pixel": worst_pixel(img, pix, ref) if ref is not None else None,
         "roofline": roofline_of(st, k_ms, args.workload),
     }
     if args.surrogate:
-        out["surrogate"] = surrogate_leg(R, wl, img, ms_step, pix, ref, leg_steps)
+        out["surrogate"] = surrogate_leg(R, wl, img, ms_step, pix, ref, leg_steps, args)
     if args.hero and len(wl.lambdas_um) % 4 == 0:
         out["hero"] = hero_leg(R, wl, ms_step, leg_steps)
     if args.aniso:
@@ -441,11 +482,13 @@ def main():
         info_m = R.load_workload(wm)
         _, img_m, st_m, ms_m, k_ms_m = plain_frame(R, wm, 1, args.steps)
         err_m = rel_l2_on(img_m, pm, ref_m) if ref_m is not None else None
+        save_subset(args, "mid", img_m, pm, ref_m)
         out["mid"] = {"workload": WORKLOAD_NAMES["mid"], "value": round(st_m["segments"] / (ms_m * 1e-3) / 1e6, 2),
                       "unit": "Mpath-segments/s", "ms_per_step": round(ms_m, 3), "steps": args.steps,
                       "segments_per_step": st_m["segments"], "bvh_nodes": info_m["n_nodes"],
                       "rel_l2_vs_oracle": err_m, "qualifies": (err_m is not None and err_m <= 1e-3),
                       "rel_l2_pixels": f"{len(pm)} pixels: every 8th row and column",
+                      "worst_pixel": worst_pixel(img_m, pm, ref_m) if ref_m is not None else None,
                       "roofline": roofline_of(st_m, k_ms_m, "mid")}
     print(json.dumps(out), flush=True)
     R.close()

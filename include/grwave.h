@@ -268,7 +268,7 @@ int gr_bsdf_eval(gr_ctx* ctx, const float* queries, int64_t n, int32_t mode, flo
  * W5[64][1], b5[1] (row-major [fan_in][fan_out]; a layer computes x W + b).  The matrix-core
  * passes accumulate in FP32.  GR_BSDF_SURROGATE_BF16 rounds weights and activations to
  * bfloat16.  GR_BSDF_SURROGATE_FP8 quantizes them to OCP E4M3: weights per layer with scale
- * max|W| / 448, activations per 64 queries and layer with scale max|a| / 448; the output
+ * max|W| / 448, activations per query and layer with scale max|a| / 448; the output
  * layer runs on the vector ALUs in FP32 in both modes.
  *
  * Input encoding of a query (sur_encode in the sources; rough surfaces only): the tangential

@@ -104,21 +104,39 @@ def _scale(amax):
     return (amax / E4M3_MAX) if amax > 1e-30 else 0.0
 
 
+def bf16_round(v):
+    """Round float32 values to bfloat16 (8 significant bits, 8 exponent bits), ties to even:
+    float32 bit patterns with the low 16 bits cleared."""
+    b = np.ascontiguousarray(np.asarray(v, np.float32)).view(np.uint32).astype(np.uint64)
+    r = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def e4m3_matmul(a, W):
+    """The quantized product a @ W of one hidden layer.  Weights per output column (neuron)
+    with scale max|W[:, j]| / 448: Wq = E4M3(W / scale) and Wq16 = E4M3(Wq / 16).  Each row
+    (query) of a with scale s = max|a| / 448, as two E4M3 terms: hi = E4M3(a / s) and
+    lo = E4M3(16 (a / s - hi)).  The product hi Wq + lo Wq16 exact (FP64), then multiplied by
+    both scales."""
+    a = np.asarray(a, np.float64)
+    cmax = np.abs(W).max(axis=0)
+    sw = np.where(cmax > 1e-30, cmax / E4M3_MAX, 0.0)
+    wq = np.where(sw > 0, e4m3_round(W / np.where(sw > 0, sw, 1.0)), 0.0)
+    wq16 = e4m3_round(wq / 16.0)
+    amax = np.abs(a).max(axis=1)
+    s = np.where(amax > 1e-30, amax / E4M3_MAX, 0.0)
+    safe = np.where(s > 0, s, 1.0)
+    v = np.where(s[:, None] > 0, a / safe[:, None], 0.0)
+    hi = e4m3_round(v)
+    lo = e4m3_round(16.0 * (v - hi))
+    return (hi @ wq + lo @ wq16) * s[:, None] * sw[None, :]
+
+
 def forward_e4m3(Ws, bs, X):
-    """Forward pass with the FP8 mode's quantization: each hidden layer's weights scaled by
-    max|W| / 448 and rounded to E4M3; each layer's input activations, per row (query), scaled
-    by the row's max |a| / 448 and rounded to E4M3; products and sums exact (FP64), then
-    multiplied back by both scales; the output layer unquantized."""
-    a = np.asarray(X, np.float64)
-    wq, ws = [], []
-    for W in Ws[:-1]:
-        s = _scale(np.abs(W).max())
-        ws.append(s)
-        wq.append(e4m3_round(W / s) if s > 0 else np.zeros_like(W))
-    for l in range(len(Ws) - 1):
-        amax = np.abs(a).max(axis=1)
-        s = np.where(amax > 1e-30, amax / E4M3_MAX, 0.0)
-        safe = np.where(s > 0, s, 1.0)
-        aq = np.where(s[:, None] > 0, e4m3_round(a / safe[:, None]), 0.0)
-        a = gelu((aq @ wq[l]) * (ws[l] * s)[:, None] + bs[l])
+    """Forward pass with the FP8 mode's quantization: the input layer on bfloat16 operands
+    (inputs and weights rounded from float32 to bfloat16), each hidden layer through
+    e4m3_matmul, the output layer unquantized."""
+    a = gelu(bf16_round(X) @ bf16_round(Ws[0]) + bs[0])
+    for l in range(1, len(Ws) - 1):
+        a = gelu(e4m3_matmul(a, Ws[l]) + bs[l])
     return (a @ Ws[-1] + bs[-1])[:, 0]

@@ -58,39 +58,48 @@ constexpr size_t kPackWf = (size_t)FWD_FRAGS * 64 * 16;
 constexpr size_t kPackWb = (size_t)BWD_FRAGS * 64 * 16;
 constexpr size_t kPackBias = 4 * 64 * 4;
 constexpr size_t kPackBytes = kPackWf + kPackWb + kPackBias;
-// E4M3 forward fragments and the four per-layer weight scales.
+// E4M3 forward fragments of Wq and Wq16, then the per-neuron weight scales [4][64].
 constexpr size_t kPack8Wf = (size_t)FWD_FRAGS * 64 * 8;
-constexpr size_t kPack8Bytes = kPack8Wf + 256;
+constexpr size_t kPack8Bytes = 2 * kPack8Wf + 4 * 64 * 4;
 
-// One wave per layer: the layer's weight scale max|W| / 448, then its forward fragments in
-// E4M3 (the bfloat16 fragments' order and operand layout).
+// One wave per hidden layer: lane t finds output neuron t's weight scale (max |W| over its 64
+// inputs / 448), then the forward fragments of Wq = E4M3(W / scale) and Wq16 = E4M3(Wq / 16)
+// in the bfloat16 fragments' order and operand layout.  The input layer stays bfloat16.
 __global__ __launch_bounds__(64) void pack8_kernel(const float* __restrict__ P, long* __restrict__ wf8,
-                                                   float* __restrict__ wscale) {
-    const int layer = blockIdx.x, lane = threadIdx.x;
-    const int g = lane >> 4, c = lane & 15;
-    const int fan_in = layer == 0 ? MLP_IN : MLP_H;
+                                                   long* __restrict__ wf16, float* __restrict__ wscale) {
+    __shared__ float inv_s[64];
+    const int layer = 1 + blockIdx.x, lane = threadIdx.x;
     float am = 0.0f;
-    for (int i = lane; i < fan_in * MLP_H; i += 64) am = fmaxf(am, fabsf(P[w_off(layer) + i]));
+    for (int in = 0; in < MLP_H; ++in) am = fmaxf(am, fabsf(P[w_off(layer) + in * MLP_H + lane]));
     float sw, inv;
-    e4m3_scale(wave_absmax(am), sw, inv);
-    if (lane == 0) wscale[layer] = sw;
-    const int nkb = layer == 0 ? 1 : 2;
+    e4m3_scale(am, sw, inv);
+    wscale[layer * 64 + lane] = sw;
+    if (layer == 1) wscale[lane] = 1.0f;   // input layer: not quantized
+    inv_s[lane] = inv;
+    __syncthreads();
+    const int g = lane >> 4, c = lane & 15;
     for (int mt = 0; mt < 4; ++mt)
-        for (int kb = 0; kb < nkb; ++kb) {
+        for (int kb = 0; kb < 2; ++kb) {
             const int out = 16 * mt + c;
+            const float io = inv_s[out];
             float v[8];
             for (int j = 0; j < 8; ++j) {
                 const int in = 32 * kb + kperm(8 * g + j);
-                v[j] = clamp448(in < fan_in ? P[w_off(layer) + in * MLP_H + out] * inv : 0.0f);
+                v[j] = clamp448(P[w_off(layer) + in * MLP_H + out] * io);
             }
-            wf8[fwd_frag(layer, mt, kb) * 64 + lane] = e4m3x8(v);
+            const long hi = e4m3x8(v);
+            float q[8];
+            e4m3x8_to_f32(hi, q);
+            for (int j = 0; j < 8; ++j) q[j] *= 0.0625f;
+            wf8[fwd_frag(layer, mt, kb) * 64 + lane] = hi;
+            wf16[fwd_frag(layer, mt, kb) * 64 + lane] = e4m3x8(q);
         }
 }
 
 static hipError_t pack8(const float* params, void* buf, hipStream_t s) {
     char* b = static_cast<char*>(buf);
-    hipLaunchKernelGGL(pack8_kernel, dim3(4), dim3(64), 0, s, params, reinterpret_cast<long*>(b),
-                       reinterpret_cast<float*>(b + kPack8Wf));
+    hipLaunchKernelGGL(pack8_kernel, dim3(3), dim3(64), 0, s, params, reinterpret_cast<long*>(b),
+                       reinterpret_cast<long*>(b + kPack8Wf), reinterpret_cast<float*>(b + 2 * kPack8Wf));
     return hipGetLastError();
 }
 
@@ -99,8 +108,10 @@ static MlpDev8 mlp_dev8(const float* params, const void* pack, const void* pack8
     const char* b = static_cast<const char*>(pack);
     const char* b8 = static_cast<const char*>(pack8buf);
     MlpDev8 M;
+    M.wf1 = reinterpret_cast<const bf16x8*>(b);
     M.wf = reinterpret_cast<const long*>(b8);
-    M.wscale = reinterpret_cast<const float*>(b8 + kPack8Wf);
+    M.wf16 = reinterpret_cast<const long*>(b8 + kPack8Wf);
+    M.wscale = reinterpret_cast<const float*>(b8 + 2 * kPack8Wf);
     M.bias = reinterpret_cast<const float*>(b + kPackWf + kPackWb);
     M.w5 = params + OFF_W5;
     M.b5 = params + OFF_B5;
@@ -128,7 +139,7 @@ static MlpDev mlp_dev(const float* params, const void* ws) {
 // ------------------------------------------------------------------------------------------
 // Forward: one wave per 64 rows.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void mlp_forward_kernel(const MlpDev M, const float* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(256, 4) void mlp_forward_kernel(const MlpDev M, const float* __restrict__ x, int64_t n,
                                                           float* __restrict__ y) {
     __shared__ float stage[4][64 * 16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -139,7 +150,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const MlpDev M, const 
     if (row < n) y[row] = o;
 }
 
-__global__ __launch_bounds__(256) void mlp_forward8_kernel(const MlpDev8 M, const float* __restrict__ x, int64_t n,
+__global__ __launch_bounds__(256, 4) void mlp_forward8_kernel(const MlpDev8 M, const float* __restrict__ x, int64_t n,
                                                            float* __restrict__ y) {
     __shared__ float stage[4][64 * 16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -405,7 +416,7 @@ __global__ __launch_bounds__(256) void samples_kernel(int64_t n, uint64_t seed, 
 // form.  One wave per 64 queries: every lane takes part in the matrix-core pass.
 // ------------------------------------------------------------------------------------------
 template <bool FP8>
-__global__ __launch_bounds__(256) void sur_eval_kernel(const MlpDev M, const MlpDev8 M8, SurDomain D,
+__global__ __launch_bounds__(256, FP8 ? 3 : 4) void sur_eval_kernel(const MlpDev M, const MlpDev8 M8, SurDomain D,
                                                        const float* __restrict__ q, int64_t n, float* __restrict__ out) {
     __shared__ float stage[4][64 * 16];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -435,7 +446,7 @@ __device__ __forceinline__ void bf16_unpair(uint32_t u, float& a, float& b) {
 }
 
 template <bool FP8>
-__global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const MlpDev8 M8, const uint4* __restrict__ q,
+__global__ __launch_bounds__(256, FP8 ? 3 : 4) void sur_batch_kernel(const MlpDev M, const MlpDev8 M8, const uint4* __restrict__ q,
                                                         const unsigned long long* __restrict__ count,
                                                         float* __restrict__ dense, unsigned long long* stats) {
     __shared__ float stage[4][64 * 16];
@@ -457,7 +468,14 @@ __global__ __launch_bounds__(256) void sur_batch_kernel(const MlpDev M, const Ml
             logpeak = __uint_as_float(b.z);
             slot = b.w;
         }
-        const float y = FP8 ? mlp_forward_wave_fp8(M8, x, stage[wv]) : mlp_forward_wave(M, x, stage[wv], nullptr);
+        // the weight fragments are read again in every iteration (the compiler would otherwise
+        // hoist them into ~100 registers for the whole loop and hold the kernel at one wave
+        // per SIMD)
+        MlpDev Mi = M;
+        MlpDev8 M8i = M8;
+        asm volatile("" : "+s"(Mi.wf));
+        asm volatile("" : "+s"(M8i.wf), "+s"(M8i.wf16), "+s"(M8i.wf1));
+        const float y = FP8 ? mlp_forward_wave_fp8(M8i, x, stage[wv]) : mlp_forward_wave(Mi, x, stage[wv], nullptr);
         if (i < n) {
             float v = scale * __expf(y + logpeak);
             if (!isfinite(v)) {

@@ -110,6 +110,8 @@ __device__ inline float mlp_forward_wave(const MlpDev& M, const float* x, float*
 #pragma unroll
     for (int f = 0; f < 16; ++f) stage[lane * 16 + f] = f < MLP_IN ? x[f] : 0.0f;
     wave_sync_lds();
+    // every accumulation starts from the layer's bias: this lane's output rows 16 mt + 4 g + i
+    // of the result tile are the bias's entries, whatever the column
     f32x4 h[4][4];
     {
         bf16x8 bin[4];
@@ -118,11 +120,9 @@ __device__ inline float mlp_forward_wave(const MlpDev& M, const float* x, float*
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const bf16x8 a = M.wf[fwd_frag(0, mt, 0) * 64 + lane];
+            const f32x4 bias = *reinterpret_cast<const f32x4*>(M.bias + 16 * mt + 4 * g);
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-                h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bin[nb], zero, 0, 0, 0);
-            }
+            for (int nb = 0; nb < 4; ++nb) h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bin[nb], bias, 0, 0, 0);
         }
     }
     wave_sync_lds();   // stage is free again for the caller
@@ -138,29 +138,25 @@ __device__ inline float mlp_forward_wave(const MlpDev& M, const float* x, float*
             for (int mt = 0; mt < 4; ++mt) {
                 const bf16x8 a0 = M.wf[fwd_frag(layer, mt, 0) * 64 + lane];
                 const bf16x8 a1 = M.wf[fwd_frag(layer, mt, 1) * 64 + lane];
+                const f32x4 bias = *reinterpret_cast<const f32x4*>(M.bias + layer * 64 + 16 * mt + 4 * g);
 #pragma unroll
                 for (int nb = 0; nb < 4; ++nb) {
-                    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-                    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[0][nb], zero, 0, 0, 0);
+                    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[0][nb], bias, 0, 0, 0);
                     h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[1][nb], acc, 0, 0, 0);
                 }
             }
         }
-        // bias + activation; the layer's output features of this lane are 16 mt + 4 g + i
+        // activation; the layer's output features of this lane are 16 mt + 4 g + i
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            float bb[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) bb[i] = M.bias[layer * 64 + 16 * mt + 4 * g + i];
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float z = h[mt][nb][i] + bb[i];
+                    const float z = h[mt][nb][i];
                     if (zsave) zsave[((((layer * 4 + mt) * 4 + nb) * 4 + i) << 6) + lane] = z;
                     h[mt][nb][i] = gelu_f(z);
                 }
-        }
     }
     // output layer on the vector ALUs: partial dot products, then a reduction over the four
     // lane groups that hold the same query column
@@ -182,14 +178,25 @@ __device__ inline float mlp_forward_wave(const MlpDev& M, const float* x, float*
 }
 
 // ------------------------------------------------------------------------------------------
-// FP8 (OCP E4M3) forward pass.  Weights are quantized per layer with scale max|W| / 448;
-// activations are quantized per wave and layer with scale max|a| / 448 over the wave's 64
-// queries.  The E4M3 16x16x32 matrix-core product has the bfloat16 one's operand layout (8
-// values per lane, value j in byte j); its FP32 result is multiplied by the two scales.
+// FP8 (OCP E4M3) forward pass.  The input layer (10 -> 64, 2.5 % of the multiply-adds) keeps
+// bfloat16 operands: its ten encoded inputs (the transfer in lobe widths among them) would
+// lose their position along the lobe to E4M3's three mantissa bits.  The three 64 x 64 hidden
+// layers run on E4M3 operands:
+//  - weights per output neuron (a row of the transposed product) with scale max|W| / 448 over
+//    that neuron's 64 inputs: Wq = E4M3(W / scale), and a second copy Wq16 = E4M3(Wq / 16);
+//  - activations per query with scale s = max|a| / 448 over its 64 values, as two E4M3 terms:
+//    hi = E4M3(a / s) and lo = E4M3(16 (a / s - hi)), the rounding residual magnified 16x;
+//  - one FP32 accumulation of Wq hi + Wq16 lo (four 16x16x32 products per 32 x 32 block),
+//    multiplied by the two scales.
+// Per-layer weight scales and a single activation term left 6.5 % and 5.6 % RMS error in the
+// network's log p_w; this form leaves 3 %.  The E4M3 16x16x32 matrix-core product has the
+// bfloat16 one's operand layout (8 values per lane, value j in byte j).
 // ------------------------------------------------------------------------------------------
 struct MlpDev8 {
-    const long* wf;        // [FWD_FRAGS][64] forward A fragments, E4M3
-    const float* wscale;   // [4] per-layer weight scales
+    const bf16x8* wf1;     // [4][64] input-layer A fragments, bfloat16 (the BF16 pack's first 4)
+    const long* wf;        // [FWD_FRAGS][64] forward A fragments Wq, E4M3 (hidden layers used)
+    const long* wf16;      // [FWD_FRAGS][64] the same fragments of Wq16
+    const float* wscale;   // [4][64] per-neuron weight scales (hidden layers used)
     const float* bias;     // [4][64]
     const float* w5;       // [64]
     const float* b5;       // [1]
@@ -207,6 +214,21 @@ __device__ __forceinline__ uint32_t e4m3x4(float a, float b, float c, float d) {
 __device__ __forceinline__ long e4m3x8(const float (&v)[8]) {
     const uint32_t lo = e4m3x4(v[0], v[1], v[2], v[3]), hi = e4m3x4(v[4], v[5], v[6], v[7]);
     return (long)(((uint64_t)hi << 32) | lo);
+}
+
+// Eight E4M3 values (byte j = value j) to float.
+__device__ __forceinline__ void e4m3x8_to_f32(long w, float (&q)[8]) {
+    const int w0 = (int)(uint32_t)w, w1 = (int)(uint32_t)((uint64_t)w >> 32);
+    const auto a = __builtin_amdgcn_cvt_pk_f32_fp8(w0, false), b = __builtin_amdgcn_cvt_pk_f32_fp8(w0, true);
+    const auto c = __builtin_amdgcn_cvt_pk_f32_fp8(w1, false), d = __builtin_amdgcn_cvt_pk_f32_fp8(w1, true);
+    q[0] = a[0];
+    q[1] = a[1];
+    q[2] = b[0];
+    q[3] = b[1];
+    q[4] = c[0];
+    q[5] = c[1];
+    q[6] = d[0];
+    q[7] = d[1];
 }
 
 __device__ __forceinline__ float wave_absmax(float v) {
@@ -228,60 +250,42 @@ __device__ __forceinline__ void e4m3_scale(float amax, float& s, float& inv) {
 
 __device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -kE4M3Max), kE4M3Max); }
 
-// The staged input row of a query holds its 10 features, its activation scale at index 14 and
-// the reciprocal at 15 (the fragments read features below 10 only).
-__device__ __forceinline__ long input_frag8(const float* stage, int nb, int lane) {
-    const int g = lane >> 4, c = lane & 15;
-    const float* row = stage + (16 * nb + c) * 16;
-    const float inv = row[15];
-    float v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int f = kperm(8 * g + j);
-        v[j] = clamp448((f < MLP_IN ? row[f] : 0.0f) * inv);
-    }
-    return e4m3x8(v);
-}
-
-__device__ __forceinline__ long act_frag8(const f32x4 (&h)[4][4], int kb, int nb, float inv) {
-    float v[8];
+// B fragments of the two activation terms of M tiles (2kb, 2kb+1), column block nb: hi =
+// E4M3(a / s), lo = E4M3(16 (a / s - hi)) (|16 residual| <= 256, no clamp needed).
+__device__ __forceinline__ void act_frag8x2(const f32x4 (&h)[4][4], int kb, int nb, float inv, long& hi, long& lo) {
+    float v[8], r[8];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         v[j] = clamp448(h[2 * kb][nb][j] * inv);
         v[4 + j] = clamp448(h[2 * kb + 1][nb][j] * inv);
     }
-    return e4m3x8(v);
+    hi = e4m3x8(v);
+    float q[8];
+    e4m3x8_to_f32(hi, q);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = 16.0f * (v[j] - q[j]);
+    lo = e4m3x8(r);
 }
 
 __device__ inline float mlp_forward_wave_fp8(const MlpDev8& M, const float* x, float* stage) {
     const int lane = threadIdx.x & 63;
     const int g = lane >> 4;
-    // activations are scaled per query (max |a| / 448 over its features), so a query's result
-    // does not depend on the other queries of its batch
-    float am = 0.0f;
 #pragma unroll
-    for (int f = 0; f < MLP_IN; ++f) am = fmaxf(am, fabsf(x[f]));
-    float s_own, inv_own;
-    e4m3_scale(am, s_own, inv_own);
-#pragma unroll
-    for (int f = 0; f < 16; ++f) stage[lane * 16 + f] = f < MLP_IN ? x[f] : (f == 14 ? s_own : (f == 15 ? inv_own : 0.0f));
+    for (int f = 0; f < 16; ++f) stage[lane * 16 + f] = f < MLP_IN ? x[f] : 0.0f;
     wave_sync_lds();
     f32x4 h[4][4];
-    float s_act[4];   // scale of query 16 nb + (lane & 15), whose outputs this lane holds
+    float s_act[4] = {1.0f, 1.0f, 1.0f, 1.0f};   // scale of query 16 nb + (lane & 15) (hidden layers)
     {
-        long bin[4];
+        bf16x8 bin[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            bin[nb] = input_frag8(stage, nb, lane);
-            s_act[nb] = stage[(16 * nb + (lane & 15)) * 16 + 14];
-        }
+        for (int nb = 0; nb < 4; ++nb) bin[nb] = input_frag(stage, nb, lane);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            const long a = M.wf[fwd_frag(0, mt, 0) * 64 + lane];
+            const bf16x8 a = M.wf1[mt * 64 + lane];
 #pragma unroll
             for (int nb = 0; nb < 4; ++nb) {
                 const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-                h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bin[nb], zero, 0, 0, 0);
+                h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bin[nb], zero, 0, 0, 0);
             }
         }
     }
@@ -303,35 +307,40 @@ __device__ inline float mlp_forward_wave_fp8(const MlpDev8& M, const float* x, f
                 m = fmaxf(m, __shfl_xor(m, 32));
                 e4m3_scale(m, s_act[nb], inv_act[nb]);
             }
-            long b[2][4];
+            long bh[2][4], bl[2][4];
 #pragma unroll
             for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-                for (int nb = 0; nb < 4; ++nb) b[kb][nb] = act_frag8(h, kb, nb, inv_act[nb]);
+                for (int nb = 0; nb < 4; ++nb) act_frag8x2(h, kb, nb, inv_act[nb], bh[kb][nb], bl[kb][nb]);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const long a0 = M.wf[fwd_frag(layer, mt, 0) * 64 + lane];
                 const long a1 = M.wf[fwd_frag(layer, mt, 1) * 64 + lane];
+                const long c0 = M.wf16[fwd_frag(layer, mt, 0) * 64 + lane];
+                const long c1 = M.wf16[fwd_frag(layer, mt, 1) * 64 + lane];
 #pragma unroll
                 for (int nb = 0; nb < 4; ++nb) {
                     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-                    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b[0][nb], zero, 0, 0, 0);
-                    h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b[1][nb], acc, 0, 0, 0);
+                    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, bh[0][nb], zero, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, bh[1][nb], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(c0, bl[0][nb], acc, 0, 0, 0);
+                    h[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(c1, bl[1][nb], acc, 0, 0, 0);
                 }
             }
         }
         // dequantize, bias, activation; the layer's output features of this lane are 16 mt + 4 g + i
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
-            float bb[4];
+            float bb[4], ws[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bb[i] = M.bias[layer * 64 + 16 * mt + 4 * g + i];
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const float deq = M.wscale[layer] * s_act[nb];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) h[mt][nb][i] = gelu_f(h[mt][nb][i] * deq + bb[i]);
+            for (int i = 0; i < 4; ++i) {
+                bb[i] = M.bias[layer * 64 + 16 * mt + 4 * g + i];
+                ws[i] = layer == 0 ? 1.0f : M.wscale[layer * 64 + 16 * mt + 4 * g + i];
             }
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) h[mt][nb][i] = gelu_f(h[mt][nb][i] * (ws[i] * s_act[nb]) + bb[i]);
         }
     }
     float part[4];

@@ -63,15 +63,15 @@ def test_forward_matches_oracle(env):
         ref, _, _ = omlp.forward(Ws, bs, x.astype(np.float64))
         e = rel_l2(y, ref[:, 0])
         print("forward n", n, "rel L2", e)
-        assert e <= 2e-2
+        assert e <= 1.5e-2          # measured 5.5e-3 .. 5.8e-3 (bfloat16 operands)
         assert np.corrcoef(y, ref[:, 0])[0, 1] > 0.9999
 
 
 def test_forward_fp8_matches_e4m3_oracle(env):
-    """FP8 mode: weights per layer and activations per row quantized to E4M3 (scale max / 448),
-    FP32 accumulation.  The oracle's quantized forward pass in FP64 is the reference; a value
-    that sits on an E4M3 rounding boundary can round the other way from FP32 inputs, so the
-    bound is that of the BF16 path."""
+    """FP8 mode: input layer on bfloat16; hidden layers with E4M3 weights per neuron and
+    activations per row as two E4M3 terms (value and 16x its rounding residual), FP32
+    accumulation.  The oracle's quantized forward pass in FP64 is the reference; a value that
+    sits on an E4M3 rounding boundary can round the other way from FP32 inputs."""
     R, S, torch = env
     from paper_2303_15762_amd import GR_BSDF_SURROGATE_FP8
     from paper_2303_15762_amd.surrogate import unflatten
@@ -86,7 +86,8 @@ def test_forward_fp8_matches_e4m3_oracle(env):
         ref, _, _ = omlp.forward(Ws, bs, x.astype(np.float64))
         e8, e = rel_l2(y, ref8), rel_l2(y, ref[:, 0])
         print("fp8 forward n", n, "rel L2 vs E4M3 oracle", e8, "vs unquantized FP64", e)
-        assert e8 <= 2e-2
+        assert e8 <= 7e-3           # measured 1.6e-3 .. 2.4e-3
+        assert e <= 0.1             # the quantization itself: measured 4.3e-2
         assert np.corrcoef(y, ref8)[0, 1] > 0.9999
 
 
@@ -107,14 +108,17 @@ def test_backward_matches_oracle(env):
     e = rel_l2(g, ref)
     cos = float(g @ ref / np.linalg.norm(g) / np.linalg.norm(ref))
     print("backward rel L2", e, "cos", cos, "loss", float(loss.item()), lref)
-    assert float(loss.item()) == pytest.approx(lref, rel=2e-2)
-    assert e <= 2e-2 and cos >= 0.999
+    assert float(loss.item()) == pytest.approx(lref, rel=2e-3)
+    assert e <= 3e-3 and cos >= 0.99999      # measured 8.9e-4, cos 0.9999996
     # per-layer blocks agree too
     o = 0
+    per = []
     for dW, db in zip(dWs, dbs):
         for blk in (dW.ravel(), db):
-            assert rel_l2(g[o:o + blk.size], blk) <= 5e-2
+            per.append(rel_l2(g[o:o + blk.size], blk))
             o += blk.size
+    print("backward per-block rel L2", ["%.2e" % v for v in per])
+    assert max(per) <= 7e-3                   # measured 1.4e-4 .. 2.4e-3
     # the gradient is deterministic
     g2, _ = S.backward(torch.tensor(p, device=R.dev), torch.tensor(x, device=R.dev),
                        torch.tensor(t, device=R.dev))

@@ -69,25 +69,40 @@ def test_surrogate_trace_matches_oracle(trained):
 
 
 def test_surrogate_cost_against_closed_form(trained):
-    """What the network buys: p_w of rough-surface queries in its domain, closed form (a
-    Poisson series of ~12 sqrt(g) Gaussians) against one matrix-core pass per 64 queries."""
+    """What the network buys: p_w of rough-surface queries inside its domain (g in [16, 400]),
+    closed form (a Poisson series of ~12 sqrt(g) Gaussians, one exponential each) against one
+    matrix-core pass per 64 queries.  Measured: the bfloat16 network is 1.15-1.25x faster per
+    query (it is bound by the two transcendental instructions of each of its 256 GELUs per
+    query); the FP8 network with its two-term activations is slower than the closed form.  On
+    a frame the closed form of those queries is under 1 % of the time (the bench reports the
+    bound), so the frame cannot gain more than that."""
     R, S, p, hist, torch = trained
     _, _, q = S.samples(1 << 22, seed=78, with_queries=True)
     t = {}
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         R.bsdf_eval(q, mode=mode)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
+        e0.record(R.stream)
         for _ in range(5):
             R.bsdf_eval(q, mode=mode)
-        e1.record()
+        e1.record(R.stream)
         torch.cuda.synchronize()
         t[mode] = e0.elapsed_time(e1) / 5
-    print(f"p_w of {q.shape[0]} rough queries: closed form {t[0]:.3f} ms, surrogate {t[1]:.3f} ms,"
-          f" speed-up {t[0] / t[1]:.2f}x")
-    assert t[1] > 0 and t[0] > 0
+    print(f"p_w of {q.shape[0]} in-domain rough queries: closed form {t[0]:.3f} ms, BF16 network "
+          f"{t[1]:.3f} ms ({t[0] / t[1]:.2f}x), FP8 network {t[2]:.3f} ms ({t[0] / t[2]:.2f}x)")
+    assert t[0] / t[1] >= 1.05
+    # on a frame: how many measurements the network answered, and the closed form's share
+    wl = W.mid_terrain(width=128, height=96, spp=16, n_lambda=8)
+    R.load_workload(wl)
+    _, st0 = R.render_workload(wl)
+    _, st1 = R.render_workload(wl, bsdf_mode=1)
+    n_in = st1["surrogate_evals"]
+    share = n_in * (t[0] / q.shape[0]) / st0["ms"]
+    print(f"mid crop: {n_in} network queries, {st1['fallbacks']} rough queries outside its domain, "
+          f"closed form of the network's queries ~{100 * share:.2f} % of the frame's kernel time")
+    assert n_in > 0 and share < 0.05
 
 
 @pytest.mark.parametrize("mode", [1, 2])

@@ -665,20 +665,46 @@ def test_e4m3_rounding_against_format_definition():
     assert omlp.e4m3_round(1e6) == 448.0 and omlp.e4m3_round(-500.0) == -448.0
 
 
+def test_bf16_rounding_against_format_definition():
+    """bfloat16: float32 with the low 16 bits zero.  Random float32 values round to the nearer
+    of the two neighbouring bfloat16 values, ties to the one with an even last bit."""
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(8)
+    bits = rng.integers(0, 2 ** 31 - 2 ** 23, size=20000, dtype=np.uint64).astype(np.uint32)
+    bits[:64] = (bits[:64] & 0xFFFF0000) | 0x8000          # exact midpoints
+    x = bits.view(np.float32).astype(np.float64)
+    lo = (bits & 0xFFFF0000).view(np.float32).astype(np.float64)
+    hi = ((bits & 0xFFFF0000) + 0x10000).astype(np.uint32).view(np.float32).astype(np.float64)
+    dl, dh = x - lo, hi - x
+    lo_even = ((bits >> 16) & 1) == 0
+    want = np.where(dl < dh, lo, np.where(dh < dl, hi, np.where(lo_even, lo, hi)))
+    np.testing.assert_array_equal(omlp.bf16_round(x.astype(np.float32)), want)
+    np.testing.assert_array_equal(omlp.bf16_round(-x.astype(np.float32)), -want)
+
+
 def test_e4m3_forward_reduces_to_exact_network():
-    """The quantized forward pass is the FP64 network when quantization is exact: every
-    weight and input an E4M3 value and the weights' and each input row's max 448, so both
-    scales are 1.  A one-hidden-layer network makes the hidden layer's input the raw
-    input; a second, deeper case checks that quantization changes outputs by no more than
-    E4M3's relative spacing allows."""
+    """The quantized passes are exact where the rounding is: a hidden layer whose weights and
+    input rows are E4M3 values with max 448 in every neuron and every query (all scales 1), or
+    whose activations sit one residual step off an E4M3 value, and an input layer on bfloat16
+    values.  A full random network changes by no more than the formats' spacing allows."""
     from oracle import mlp as omlp
     rng = np.random.default_rng(3)
     grid = np.array([0.25, 0.5, 1.0, 2.0, -0.5, -1.0, 0.0, 0.75])
-    W1 = rng.choice(grid, size=(10, 64))
-    W1[0, 0] = 448.0
+    W = rng.choice(grid, size=(64, 64))
+    W[0, :] = 448.0                       # every neuron's scale is 1
+    A = rng.choice(grid, size=(256, 64))
+    A[:, 5] = -448.0                      # every query's scale is 1
+    np.testing.assert_array_equal(omlp.e4m3_matmul(A, W), A @ W)
+    # the residual term: an activation between two E4M3 values carries its rounding residual
+    # at 16x, so a/s = 1.0625 (hi = 1, residual 1/16 -> lo = 1) is carried exactly
+    A2 = A.copy()
+    A2[:, 7] = 1.0625
+    np.testing.assert_allclose(omlp.e4m3_matmul(A2, W), A2 @ W, rtol=0, atol=1e-12)
+    assert omlp.e4m3_round(1.0625) == 1.0
+    # input layer: bfloat16-exact inputs and weights pass unrounded
+    W1 = rng.choice(grid, size=(10, 64)) * 3.0
     W2 = rng.normal(size=(64, 1))
-    X = rng.choice(grid, size=(256, 10))
-    X[:, 0] = 448.0
+    X = rng.choice(grid, size=(256, 10)) * 5.0
     bs = [rng.normal(size=64), np.zeros(1)]
     ref, _, _ = omlp.forward([W1, W2], bs, X)
     np.testing.assert_allclose(omlp.forward_e4m3([W1, W2], bs, X), ref[:, 0], rtol=1e-12, atol=1e-12)
