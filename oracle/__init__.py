@@ -57,7 +57,7 @@ class OrOpts(C.Structure):
                 ("max_depth", C.c_int32), ("rr_enable", C.c_int32),
                 ("rr_threshold24", C.c_uint32), ("rr_p", C.c_double), ("seed", C.c_uint64),
                 ("use_bvh", C.c_int32), ("n_threads", C.c_int32), ("hero", C.c_int32),
-                ("aniso", C.c_int32)]
+                ("aniso", C.c_int32), ("composite", C.c_int32), ("reach_m", C.c_double)]
 
 
 class OrCoherent(C.Structure):
@@ -111,6 +111,14 @@ def lib():
             L.or_aniso_free.argtypes = [C.c_double, C.c_double, dp]
             L.or_aniso_interact.argtypes = [dp, dp, dp, dp]
             L.or_aniso_footprint.argtypes = [dp, dp, dp, dp, dp, dp]
+            L.or_scene_boundaries.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int64]
+            L.or_scene_boundaries.restype = C.c_int64
+            L.or_boundary_edge.argtypes = [C.c_void_p, C.c_int64, dp]
+            L.or_nearest_boundary.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64, C.c_double, dp]
+            L.or_faddeeva.argtypes = [C.c_double, C.c_double, dp]
+            L.or_halfplane_field.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, C.c_int64, dp]
+            L.or_pw_composite_batch.argtypes = [dp, C.c_int64, dp]
+            L.or_interaction_composite.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, dp, C.c_double, dp]
             _lib = L
     return _lib
 
@@ -166,6 +174,35 @@ def pw_batch(q):
     q = np.ascontiguousarray(np.asarray(q, np.float64))
     out = np.empty(q.shape[0])
     lib().or_pw_batch(_dp(q), q.shape[0], _dp(out))
+    return out
+
+
+def faddeeva(z):
+    """Faddeeva function w(z) = exp(-z^2) erfc(-i z) for Im z >= 0 (array)."""
+    z = np.asarray(z, np.complex128)
+    out = np.empty(z.shape, np.complex128)
+    buf = np.zeros(2)
+    for i, v in enumerate(z.ravel()):
+        lib().or_faddeeva(float(v.real), float(v.imag), _dp(buf))
+        out.flat[i] = complex(buf[0], buf[1])
+    return out
+
+
+def halfplane_field(S, n, c, v):
+    """Normalised window fields at transfers v [m][2]: (whole plane (real), far half-plane
+    n.x > c (complex)).  S = (sxx, syy, sxy) intensity footprint covariance (um^2)."""
+    v = np.ascontiguousarray(np.asarray(v, np.float64).reshape(-1, 2))
+    out = np.zeros((v.shape[0], 3))
+    lib().or_halfplane_field(_dp(np.ascontiguousarray(S, np.float64)), float(n[0]), float(n[1]), float(c),
+                             _dp(v), v.shape[0], _dp(out))
+    return out[:, 0], out[:, 1] + 1j * out[:, 2]
+
+
+def pw_composite_batch(q):
+    """Composite p_w for rows q [n][23] (see or_pw_composite_batch)."""
+    q = np.ascontiguousarray(q, np.float64)
+    out = np.zeros(q.shape[0])
+    lib().or_pw_composite_batch(_dp(q), q.shape[0], _dp(out))
     return out
 
 
@@ -260,6 +297,7 @@ class OracleScene:
             nrm = np.ascontiguousarray(scene.normals, np.float64)
         i32p = C.POINTER(C.c_int32)
         self._keep = (verts, tris, tm, mats, nrm)
+        self.n_boundaries = None
         self.h = L.or_scene_create(_dp(verts), verts.shape[0],
                                    _dp(nrm) if nrm is not None else None,
                                    tris.ctypes.data_as(i32p), tris.shape[0],
@@ -271,6 +309,47 @@ class OracleScene:
         if getattr(self, "h", None):
             lib().or_scene_destroy(self.h)
             self.h = None
+
+    def boundaries(self):
+        """Find the material-boundary edges (once); returns their number."""
+        if self.n_boundaries is None:
+            tris = self._keep[1]
+            n = lib().or_scene_boundaries(self.h, tris.ctypes.data_as(C.POINTER(C.c_int32)), tris.shape[0])
+            if n < 0:
+                raise RuntimeError("oracle boundary search failed")
+            self.n_boundaries = int(n)
+        return self.n_boundaries
+
+    def boundary_edges(self):
+        """[n][14]: p0 (3), p1 (3), the two materials, the two triangles' third vertices (6)."""
+        n = self.boundaries()
+        out = np.zeros((n, 14))
+        row = np.zeros(14)
+        for i in range(n):
+            lib().or_boundary_edge(self.h, i, _dp(row))
+            out[i] = row
+        return out
+
+    def nearest_boundary(self, mat, points, reach_m):
+        """Nearest boundary edge of material mat within reach of each point: [n][2] (index or
+        -1, distance)."""
+        self.boundaries()
+        P = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, 3))
+        out = np.zeros((P.shape[0], 2))
+        lib().or_nearest_boundary(self.h, int(mat), _dp(P), P.shape[0], float(reach_m), _dp(out))
+        return out
+
+    def interaction_composite(self, origin, direction, k, beta2, u, reach_m=2e-3):
+        """One interaction with composite interactions: dict with composite, c (um), n, the
+        far side's window mass, the side chosen by u[3], weight, direction and ended."""
+        self.boundaries()
+        ray = np.ascontiguousarray(np.concatenate([np.asarray(origin, np.float64).ravel(),
+                                                   np.asarray(direction, np.float64).ravel()]))
+        out = np.zeros(11)
+        lib().or_interaction_composite(self.h, _dp(ray), float(k), float(beta2),
+                                       _dp(np.ascontiguousarray(u, np.float64)), float(reach_m), _dp(out))
+        return {"composite": bool(out[0]), "c": out[1], "n": out[2:4], "mass_far": out[4],
+                "far": bool(out[5]), "weight": out[6], "dir": out[7:10], "ended": bool(out[10])}
 
     def interaction(self, origin, direction, k, u=(0.5, 0.5, 0.5)):
         """One interaction of the path loop: dict with hit, ns, ng, ci, the continuation
@@ -320,15 +399,20 @@ def rr_threshold24(p: float) -> int:
 
 
 def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=None,
-           use_bvh=True, n_threads=0, keep_paths=False, lambdas=None, hero=False, aniso=False):
+           use_bvh=True, n_threads=0, keep_paths=False, lambdas=None, hero=False, aniso=False,
+           composite=False, reach_m=2e-3):
     """Render a workload (or a pixel subset of it).  Returns (image, stats[, paths]).
 
     image: [n_lambda, H, W] when pixels is None, else [n_lambda, n_pixels].
     hero: one path per (pixel, sample, rotation group of four wavelengths), sampled at a hero
     wavelength drawn from its group (n_lambda must be a multiple of 4).
-    aniso: anisotropic generalized rays (matrix beta, rho; not with hero)."""
+    aniso: anisotropic generalized rays (matrix beta, rho; not with hero).
+    composite: composite interactions where a material boundary lies within the footprint
+    (at most reach_m metres from the hit; scalar one-wavelength paths only)."""
     L = lib()
     oscene = OracleScene(wl.scene) if oscene is None else oscene
+    if composite:
+        oscene.boundaries()
     lam = np.ascontiguousarray(wl.lambdas_um if lambdas is None else lambdas, np.float64)
     nl = lam.shape[0]
     spp_count = wl.spp if spp_count is None else spp_count
@@ -337,7 +421,7 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
                 max_depth=wl.max_depth, rr_enable=int(wl.rr_enable),
                 rr_threshold24=rr_threshold24(wl.rr_p), rr_p=float(np.float32(wl.rr_p)),
                 seed=wl.seed, use_bvh=int(use_bvh), n_threads=n_threads, hero=int(hero),
-                aniso=int(aniso))
+                aniso=int(aniso), composite=int(composite), reach_m=float(reach_m))
     sen = _sensor_struct(wl.sensor)
     srcs = _sources_struct(wl.sources)
     if pixels is None:
@@ -348,14 +432,15 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
         npix = pix.shape[0]
     img = np.zeros((nl, npix))
     paths = np.zeros((spp_count, npix, nl)) if keep_paths else None
-    stats = (C.c_uint64 * 4)()
+    stats = (C.c_uint64 * 5)()
     i32p = C.POINTER(C.c_int32)
     rc = L.or_trace(oscene.h, C.byref(sen), srcs, len(wl.sources), _dp(lam), nl, C.byref(op),
                     pix.ctypes.data_as(i32p) if pix is not None else None, npix, _dp(img),
                     _dp(paths) if paths is not None else None, stats)
     if rc != 0:
         raise RuntimeError("oracle trace failed")
-    st = dict(segments=stats[0], shadow_rays=stats[1], evanescent=stats[2], backfacing=stats[3])
+    st = dict(segments=stats[0], shadow_rays=stats[1], evanescent=stats[2], backfacing=stats[3],
+              composite=stats[4])
     if pixels is None:
         img = img.reshape(nl, wl.sensor.height, wl.sensor.width)
     if keep_paths:

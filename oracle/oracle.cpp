@@ -137,6 +137,8 @@ typedef struct {
     int32_t n_threads;
     int32_t hero;               // 1: hero-wavelength paths over rotation groups (nl % 4 == 0)
     int32_t aniso;              // 1: anisotropic generalized rays (matrix beta, rho)
+    int32_t composite;          // 1: composite interactions at material boundaries
+    double reach_m;             // composite: largest boundary distance considered (metres)
 } or_opts;
 
 }  // extern "C"
@@ -293,6 +295,153 @@ bool sample_finf(const Mat& m, double k, double kix, double kiy, double ci, doub
 }
 
 // ------------------------------------------------------------------------------------------
+// Composite interaction at a material boundary (Sec. "Wave-Optical Rendering", the second
+// practical difficulty: a generalized ray whose footprint covers several materials meets the
+// composition of their interaction operators, and the waves the materials scatter interfere;
+// the paper leaves such composite operators to future work, so the operator below is this
+// implementation's reading, listed in the design notes).
+//
+// The footprint meets one straight boundary: surface coordinates x about the hit, the near
+// side (the hit's material) is n.x < c and the far side n.x > c, with n the unit normal of the
+// boundary line (pointing to the far side) and c >= 0 its distance from the hit.  The field
+// scattered towards the tangential transfer kappa is the Fourier integral of the amplitude
+// window times each side's reflection function over its half-plane.  A deterministic surface
+// (smooth, grating) has no stated position of its profile relative to the boundary, so its
+// phase is averaged: cross terms survive between the two sides' undiffracted mean fields only.
+// A rough side adds its ensemble mean field exp(-g/2) to that cross term and its diffuse
+// (Poisson terms n >= 1) part weighted by the window's intensity mass on its side (the local
+// reading: correlation length small against the footprint).  parity: pinned by 2-D quadrature
+// of the defining integral (phase-averaged), the sides' limits, Parseval, the library Faddeeva
+// function, and a closed-form mirror pair rendered per path.
+// ------------------------------------------------------------------------------------------
+
+// Faddeeva function w(z) = exp(-z^2) erfc(-i z), Im z >= 0.  |z| < 6 and Im z < 1: erf by
+// its Maclaurin series (Abramowitz & Stegun 7.1.5) and w = exp(-z^2) (1 - erf(-i z));
+// otherwise the Laplace continued fraction (A&S 7.1.4) evaluated backwards from depth 200
+// (further from the real axis 1 - erf cancels, and the fraction converges well there).
+std::complex<double> faddeeva(std::complex<double> z) {
+    using cd = std::complex<double>;
+    if (std::abs(z) < 6.0 && z.imag() < 1.0) {
+        const cd zeta = cd(0.0, -1.0) * z;
+        const cd z2 = zeta * zeta;
+        cd term = zeta, sum = 0.0;
+        for (int n = 0; n < 1000; ++n) {
+            const cd add = term / (double)(2 * n + 1);
+            sum += add;
+            if (n > 5 && std::abs(add) <= 1e-17 * std::abs(sum)) break;
+            term = -term * z2 / (double)(n + 1);
+        }
+        return std::exp(-z * z) * (1.0 - (2.0 / std::sqrt(kPi)) * sum);
+    }
+    cd t = z;
+    for (int n = 200; n >= 1; --n) t = z - (0.5 * n) / t;
+    return cd(0.0, 1.0 / std::sqrt(kPi)) / t;
+}
+
+// Window field over the whole plane, normalised so that its squared magnitude is the window
+// spectrum density N(v; 0, S^-1 / 4): G(v) / sqrt((2 pi)^2 int |w|^2), with the amplitude
+// window w(x) = exp(-x^T S^-1 x / 4) (S: intensity footprint covariance, um^2).
+double window_field(double sxx, double syy, double sxy, double vx, double vy) {
+    const double detS = sxx * syy - sxy * sxy;
+    const double detA = 0.25 / detS;                       // A = S^-1 / 2
+    const double G = 2.0 * kPi / std::sqrt(detA) * std::exp(-(sxx * vx * vx + 2.0 * sxy * vx * vy + syy * vy * vy));
+    return G / std::sqrt(4.0 * kPi * kPi * kPi / std::sqrt(detA));
+}
+
+// The same integral over the far half-plane n.x > c only.  In the boundary's frame
+// x = a n + b e (e = (-ny, nx)), with the window's precision A = S^-1 / 2 written Ann, Ane,
+// Aee: the b integral is Gaussian, sqrt(2 pi / Aee) exp((i v_e - Ane a)^2 / (2 Aee)), and
+// what remains is
+//   int_c^inf exp(-p a^2 / 2 + i q a) da = sqrt(pi / (2 p)) exp(-p c^2 / 2 + i q c) w(z),
+//   p = det A / Aee,  q = v_n - v_e Ane / Aee,  z = (q + i p c) / sqrt(2 p).
+std::complex<double> halfplane_field(double sxx, double syy, double sxy, double nx, double ny, double c,
+                                     double vx, double vy) {
+    const double detS = sxx * syy - sxy * sxy;
+    const double ixx = 0.5 * syy / detS, iyy = 0.5 * sxx / detS, ixy = -0.5 * sxy / detS;   // A
+    const double ex = -ny, ey = nx;
+    const double Ann = nx * nx * ixx + 2.0 * nx * ny * ixy + ny * ny * iyy;
+    const double Aee = ex * ex * ixx + 2.0 * ex * ey * ixy + ey * ey * iyy;
+    const double Ane = nx * ex * ixx + (nx * ey + ny * ex) * ixy + ny * ey * iyy;
+    const double detA = Ann * Aee - Ane * Ane;
+    const double vn = nx * vx + ny * vy, ve = ex * vx + ey * vy;
+    const double p = detA / Aee, q = vn - ve * Ane / Aee;
+    const std::complex<double> z(q / std::sqrt(2.0 * p), p * c / std::sqrt(2.0 * p));
+    const std::complex<double> ph(-0.5 * p * c * c - 0.5 * ve * ve / Aee, q * c);
+    const std::complex<double> F = std::sqrt(2.0 * kPi / Aee) * std::sqrt(kPi / (2.0 * p)) * std::exp(ph) * faddeeva(z);
+    return F / std::sqrt(4.0 * kPi * kPi * kPi / std::sqrt(detA));
+}
+
+// One side of a composite interaction: its material and the grating direction in the frame.
+struct Side { const Mat* m; double gx, gy; };
+
+// p_w of the composite interaction (density over the outgoing tangential wavevector, um^2).
+// near / far: the two sides; (nx, ny), c: the boundary in the frame; other arguments as
+// pw_eval.
+double pw_composite(const Side& nr, const Side& fr, double k, double kix, double kiy, double kox, double koy,
+                    double sxx, double syy, double sxy, double nx, double ny, double c) {
+    const double ni = (kix * kix + kiy * kiy) / (k * k);
+    const double no = (kox * kox + koy * koy) / (k * k);
+    if (ni >= 1.0 || no >= 1.0) return 0.0;
+    const double ci = std::sqrt(1.0 - ni), co = std::sqrt(1.0 - no);
+    const double qz = k * (ci + co);
+    const double kx = kox - kix, ky = koy - kiy;
+    const double snn = nx * nx * sxx + 2.0 * nx * ny * sxy + ny * ny * syy;
+    const double mass_far = 0.5 * std::erfc(c / std::sqrt(2.0 * snn));
+    const double mass[2] = {1.0 - mass_far, mass_far};
+    // window spectrum covariance S^-1 / 4 (as pw_eval) for the diffuse terms
+    const double det = sxx * syy - sxy * sxy;
+    const double wa = 0.25 * syy / det, wb = 0.25 * sxx / det, wc = -0.25 * sxy / det;
+    const Side* sd[2] = {&nr, &fr};
+    std::complex<double> mean[2];
+    double total = 0.0;
+    for (int s = 0; s < 2; ++s) {
+        const Mat& m = *sd[s]->m;
+        // this side's half-plane field: far = F, near = G - F
+        auto H = [&](double vx, double vy) {
+            const std::complex<double> F = halfplane_field(sxx, syy, sxy, nx, ny, c, vx, vy);
+            return s == 1 ? F : window_field(sxx, syy, sxy, vx, vy) - F;
+        };
+        if (m.kind == 0) {
+            const std::complex<double> h = H(kx, ky);
+            total += m.refl * std::norm(h);
+            mean[s] = std::sqrt(m.refl) * h;
+        } else if (m.kind == 2) {
+            const double K = 2.0 * kPi / m.L;
+            const double mm = qz * m.h;
+            const int J = (int)std::ceil(std::fabs(mm)) + 40;
+            mean[s] = 0.0;
+            for (int j = -J; j <= J; ++j) {
+                const double bj = besselj(j, mm);
+                if (bj == 0.0) continue;
+                const std::complex<double> h = H(kx + j * K * sd[s]->gx, ky + j * K * sd[s]->gy);
+                total += m.refl * bj * bj * std::norm(h);
+                if (j == 0) mean[s] = std::sqrt(m.refl) * bj * h;
+            }
+        } else {
+            const double g = qz * qz * m.h * m.h;
+            const std::complex<double> h = H(kx, ky);
+            total += m.refl * std::exp(-g) * std::norm(h);
+            mean[s] = std::sqrt(m.refl) * std::exp(-0.5 * g) * h;
+            if (g > 0.0) {
+                const int M = (int)std::ceil(g + 20.0 * std::sqrt(g) + 40.0);
+                const double lg = std::log(g);
+                double dif = 0.0;
+                for (int n = 1; n <= M; ++n) {
+                    const double w = std::exp(-g + n * lg - std::lgamma((double)n + 1.0));
+                    if (w == 0.0) continue;
+                    const double add = 2.0 * n / (m.L * m.L);
+                    dif += w * gauss2(kx, ky, wa + add, wb + add, wc);
+                }
+                total += m.refl * mass[s] * dif;
+            }
+        }
+    }
+    // non-negative in exact arithmetic (a phase average of squared magnitudes plus diffuse
+    // terms); far out in the boundary's diffraction streak the sum cancels to rounding
+    return std::max(0.0, total + 2.0 * std::real(mean[0] * std::conj(mean[1])));
+}
+
+// ------------------------------------------------------------------------------------------
 // Hero-wavelength spectral sampling (Sec. "Interactive Rendering", implementation details: the
 // hero wavelength drives the path, and paths without dispersive delta segments carry up to
 // three more wavelengths).  The companions here are the other members of a rotation group of
@@ -408,6 +557,12 @@ struct SceneO {
     std::vector<Mat> mats;
     std::vector<Node> nodes;
     std::vector<int> order;        // triangle indices referenced by leaves
+    // Material boundaries (composite interactions): mesh edges shared by exactly two triangles
+    // of different materials, and per material the boundary edges it lies on.
+    struct BEdge { V3 p0, p1; int mat[2]; V3 opp[2]; };   // opp: each triangle's third vertex
+    std::vector<BEdge> bedges;
+    std::vector<std::vector<int>> mat_bedges;
+    bool have_bedges = false;
 };
 
 void tri_bounds(const Tri& T, V3& lo, V3& hi) {
@@ -518,7 +673,7 @@ bool trace_ray(const SceneO& S, V3 o, V3 d, double tmin, double tmax, bool use_b
 // "Interactive Rendering": rays are traced as rays, the generalized-ray parameters are
 // carried along; measurement by next-event estimation at every interaction).
 // ------------------------------------------------------------------------------------------
-struct Stats { uint64_t segments = 0, shadow = 0, evanescent = 0, backfacing = 0; };
+struct Stats { uint64_t segments = 0, shadow = 0, evanescent = 0, backfacing = 0, composite = 0; };
 
 struct Ctx {
     const SceneO* S;
@@ -587,6 +742,113 @@ void footprint(const Vertex& v, double beta2, double& sxx, double& syy, double& 
     sxx = sr2 * (1.0 + v.dx * v.dx / (v.ci * v.ci));
     syy = sr2 * (1.0 + v.dy * v.dy / (v.ci * v.ci));
     sxy = sr2 * (v.dx * v.dy / (v.ci * v.ci));
+}
+
+// Material-boundary edges of a triangle mesh given by vertex indices tris [nt][3]: every edge
+// (unordered vertex-index pair) used by exactly two triangles whose materials differ.
+void find_boundaries(SceneO& S, const int32_t* tris, int64_t nt) {
+    std::vector<std::pair<uint64_t, int>> keys;   // (edge key, 3 * triangle + local edge)
+    keys.reserve(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int e = 0; e < 3; ++e) {
+            uint64_t a = (uint32_t)tris[3 * t + e], b = (uint32_t)tris[3 * t + (e + 1) % 3];
+            if (a > b) std::swap(a, b);
+            keys.push_back({(a << 32) | b, (int)(3 * t + e)});
+        }
+    std::sort(keys.begin(), keys.end());
+    S.bedges.clear();
+    S.mat_bedges.assign(S.mats.size(), {});
+    for (size_t i = 0; i < keys.size();) {
+        size_t j = i;
+        while (j < keys.size() && keys[j].first == keys[i].first) ++j;
+        if (j - i == 2) {
+            const int t0 = keys[i].second / 3, t1 = keys[i + 1].second / 3;
+            const int e0 = keys[i].second % 3;
+            if (S.mat[t0] != S.mat[t1]) {
+                const Tri& T0 = S.tris[t0];
+                const Tri& T1 = S.tris[t1];
+                const V3 p[3] = {T0.p0, T0.p1, T0.p2};
+                SceneO::BEdge E;
+                E.p0 = p[e0];
+                E.p1 = p[(e0 + 1) % 3];
+                E.mat[0] = S.mat[t0];
+                E.mat[1] = S.mat[t1];
+                E.opp[0] = p[(e0 + 2) % 3];
+                // the vertex of T1 that is on neither end of the edge
+                const V3 q[3] = {T1.p0, T1.p1, T1.p2};
+                const int e1 = keys[i + 1].second % 3;
+                E.opp[1] = q[(e1 + 2) % 3];
+                const int id = (int)S.bedges.size();
+                S.bedges.push_back(E);
+                S.mat_bedges[E.mat[0]].push_back(id);
+                S.mat_bedges[E.mat[1]].push_back(id);
+            }
+        }
+        i = j;
+    }
+    S.have_bedges = true;
+}
+
+double point_segment_distance(V3 P, V3 a, V3 b) {
+    const V3 ab = b - a;
+    const double l2 = dot(ab, ab);
+    double t = l2 > 0.0 ? dot(P - a, ab) / l2 : 0.0;
+    t = std::min(1.0, std::max(0.0, t));
+    return norm(P - (a + t * ab));
+}
+
+// Nearest boundary edge of material mat within distance reach (metres) of P, -1 if none;
+// equal distances go to the lower edge index.
+int nearest_boundary(const SceneO& S, int mat, V3 P, double reach, double& dist) {
+    int best = -1;
+    dist = reach;
+    for (int id : S.mat_bedges[mat]) {
+        const double d = point_segment_distance(P, S.bedges[id].p0, S.bedges[id].p1);
+        if (d < dist || (d == dist && best >= 0 && id < best)) {
+            if (d < reach) { best = id; dist = d; }
+        }
+    }
+    return best;
+}
+
+// Composite interaction at vertex v of triangle tri (material mat) with footprint S (um^2):
+// the nearest boundary edge of mat within min(2.5 beta_max, reach_m) of the hit, with
+// beta_max = sqrt(2) times the footprint's largest standard deviation (the ball that holds the
+// generalized ray, Sec. "Wave-Optical Rendering"), carried onto the tangent plane of the frame:
+// its unit normal (nx, ny) towards the far side (the side of the far triangle's third vertex),
+// its distance c >= 0, the far side (material and grating direction in the frame) and the far
+// side's share of the window's intensity mass.  False when there is none.
+bool composite_at(const SceneO& S, const Vertex& v, int mat, double sxx, double syy, double sxy, double reach_m,
+                  Side& far, double& nx, double& ny, double& c, double& mass_far) {
+    if (!S.have_bedges || S.mat_bedges[mat].empty()) return false;
+    const double lmax = 0.5 * (sxx + syy) + std::sqrt(0.25 * (sxx - syy) * (sxx - syy) + sxy * sxy);
+    const double rad = std::min(2.5 * std::sqrt(2.0 * lmax) * 1e-6, reach_m);
+    double dist;
+    const int id = nearest_boundary(S, mat, v.P, rad, dist);
+    if (id < 0) return false;
+    const SceneO::BEdge& E = S.bedges[id];
+    const int fs = E.mat[0] == mat ? 1 : 0;       // the far side: the other material
+    const V3 a3 = E.p0 - v.P, b3 = E.p1 - v.P, q3 = E.opp[fs] - v.P;
+    const double ax = dot(a3, v.xa) * 1e6, ay = dot(a3, v.ya) * 1e6;   // um
+    const double bx = dot(b3, v.xa) * 1e6, by = dot(b3, v.ya) * 1e6;
+    const double qx = dot(q3, v.xa) * 1e6, qy = dot(q3, v.ya) * 1e6;
+    const double ex = bx - ax, ey = by - ay, el = std::sqrt(ex * ex + ey * ey);
+    if (!(el > 1e-6 * norm(E.p1 - E.p0) * 1e6)) return false;   // edge seen end-on
+    nx = -ey / el;
+    ny = ex / el;
+    if (nx * (qx - ax) + ny * (qy - ay) < 0.0) { nx = -nx; ny = -ny; }
+    c = std::max(0.0, nx * ax + ny * ay);
+    const Mat& fm = S.mats[E.mat[fs]];
+    far.m = &fm;
+    far.gx = 1.0;
+    far.gy = 0.0;
+    if (fm.kind == 2) {
+        const double gx = dot(fm.gdir, v.xa), gy = dot(fm.gdir, v.ya), gl = std::sqrt(gx * gx + gy * gy);
+        if (gl > 1e-9) { far.gx = gx / gl; far.gy = gy / gl; }
+    }
+    const double snn = nx * nx * sxx + 2.0 * nx * ny * sxy + ny * ny * syy;
+    mass_far = 0.5 * std::erfc(c / std::sqrt(2.0 * snn));
+    return true;
 }
 
 // Emitter sampling for next-event estimation from P at wavenumber k.  A plane wave arrives
@@ -769,6 +1031,12 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
         else footprint(v, beta2, sxx, syy, sxy);
         // The frame's x axis is the grating direction, so the grating vector is (1, 0).
         const double gx = 1.0, gy = 0.0;
+        // Composite interaction when a material boundary lies within the footprint.
+        Side near_side{&m, gx, gy}, far_side{&m, gx, gy};
+        double bnx = 0.0, bny = 0.0, bc = 0.0, mass_far = 0.0;
+        const bool comp = op.composite &&
+                          composite_at(S, v, S.mat[h.tri], sxx, syy, sxy, op.reach_m, far_side, bnx, bny, bc, mass_far);
+        if (comp) st.composite++;
 
         // Measurement by next-event estimation (measurement operator, eq.
         // measurement_operator, with the ensemble-averaged source WDF).
@@ -786,18 +1054,23 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
                 if (!occ) {
                     double kix = k * dot(om, v.xa), kiy = k * dot(om, v.ya);
                     double kox = -k * v.dx, koy = -k * v.dy;
-                    double p = pw_eval(m, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
+                    double p = comp ? pw_composite(near_side, far_side, k, kix, kiy, kox, koy, sxx, syy, sxy, bnx, bny, bc)
+                                    : pw_eval(m, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
                     contrib += alpha * L.power * p * (double)C.nsrc;
                 }
             }
         }
         if (depth + 1 >= op.max_depth) break;
 
-        // Light-matter interaction: sample the continuation generalized ray.
+        // Light-matter interaction: sample the continuation generalized ray.  At a composite
+        // interaction the continuation samples the far side's unwindowed kernel with the
+        // probability of the window's intensity mass there (word 3 of the NEE draw), else the
+        // near side's: a one-sample estimate of the mass-weighted mixture of the two kernels.
         U4 rs = draw(pid, depth, STREAM_SCATTER, op.seed);
+        const Side& cs = (comp && !(unif(rn.v[3]) < 1.0 - mass_far)) ? far_side : near_side;
         double kix = k * v.dx, kiy = k * v.dy, kox, koy, wgt;
         int ev;
-        if (!sample_finf(m, k, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), gx, gy,
+        if (!sample_finf(*cs.m, k, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), cs.gx, cs.gy,
                          kox, koy, wgt, ev)) {
             st.evanescent += ev;
             break;
@@ -1044,6 +1317,99 @@ void* or_scene_create(const double* verts, int64_t nv, const double* normals,
 
 void or_scene_destroy(void* s) { delete (SceneO*)s; }
 
+// Find the scene's material boundaries (needed by composite rendering).  tris: the index
+// array given to or_scene_create.  Returns the number of boundary edges.
+int64_t or_scene_boundaries(void* s, const int32_t* tris, int64_t nt) {
+    SceneO& S = *(SceneO*)s;
+    if ((int64_t)S.tris.size() != nt) return -1;
+    find_boundaries(S, tris, nt);
+    return (int64_t)S.bedges.size();
+}
+
+// Boundary edge i: out [14] = p0 (3), p1 (3), materials (2), third vertices (6).
+void or_boundary_edge(void* s, int64_t i, double* out) {
+    const SceneO::BEdge& E = ((SceneO*)s)->bedges[i];
+    const V3 v[4] = {E.p0, E.p1, E.opp[0], E.opp[1]};
+    for (int j = 0; j < 2; ++j) { out[3 * j] = v[j].x; out[3 * j + 1] = v[j].y; out[3 * j + 2] = v[j].z; }
+    out[6] = E.mat[0];
+    out[7] = E.mat[1];
+    for (int j = 0; j < 2; ++j) { out[8 + 3 * j] = v[2 + j].x; out[9 + 3 * j] = v[2 + j].y; out[10 + 3 * j] = v[2 + j].z; }
+}
+
+// Nearest boundary edge of material mat within reach of points P [n][3]; out [n][2] = (edge
+// index or -1, distance).
+void or_nearest_boundary(void* s, int32_t mat, const double* P, int64_t n, double reach, double* out) {
+    const SceneO& S = *(SceneO*)s;
+    for (int64_t i = 0; i < n; ++i) {
+        double d;
+        const int id = nearest_boundary(S, mat, ld3(P + 3 * i), reach, d);
+        out[2 * i] = id;
+        out[2 * i + 1] = id >= 0 ? d : 0.0;
+    }
+}
+
+// Faddeeva function (tests): z = (re, im), im >= 0; out [2].
+void or_faddeeva(double re, double im, double* out) {
+    const std::complex<double> w = faddeeva({re, im});
+    out[0] = w.real();
+    out[1] = w.imag();
+}
+
+// Normalised window fields (tests): S [3] = (sxx, syy, sxy), boundary (nx, ny, c), v [n][2];
+// out [n][3] = (whole-plane field, far half-plane field re, im).
+void or_halfplane_field(const double* S, double nx, double ny, double c, const double* v, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        const std::complex<double> F = halfplane_field(S[0], S[1], S[2], nx, ny, c, v[2 * i], v[2 * i + 1]);
+        out[3 * i] = window_field(S[0], S[1], S[2], v[2 * i], v[2 * i + 1]);
+        out[3 * i + 1] = F.real();
+        out[3 * i + 2] = F.imag();
+    }
+}
+
+// Composite p_w for a batch (tests).  q [n][23]: near material (kind, h, L, refl, gx, gy), far
+// material (the same six), k, kix, kiy, kox, koy, sxx, syy, sxy, nx, ny, c.  out [n].
+void or_pw_composite_batch(const double* q, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        const double* r = q + 23 * i;
+        const Mat mn{(int)r[0], r[1], r[2], r[3], V3{1, 0, 0}};
+        const Mat mf{(int)r[6], r[7], r[8], r[9], V3{1, 0, 0}};
+        const Side sn{&mn, r[4], r[5]}, sf{&mf, r[10], r[11]};
+        out[i] = pw_composite(sn, sf, r[12], r[13], r[14], r[15], r[16], r[17], r[18], r[19], r[20], r[21], r[22]);
+    }
+}
+
+// One interaction with composite interactions enabled (tests): closest hit of (o, d), the
+// footprint of a ray of beta^2 = beta2 (um^2) there, the boundary found and the continuation
+// sampled with uniforms u[0..2] and side-choice uniform u[3].  out [11]: composite (1 or 0),
+// c (um), nx, ny, far mass, side (0 near, 1 far), weight, direction (3), ended.
+void or_interaction_composite(void* s, const double* ray, double k, double beta2, const double* u, double reach_m,
+                              double* out) {
+    const SceneO& S = *(SceneO*)s;
+    for (int i = 0; i < 11; ++i) out[i] = 0.0;
+    V3 o = ld3(ray), d = unit(ld3(ray + 3));
+    Hit h;
+    if (!trace_ray(S, o, d, t_eps(o), 1e300, true, false, h)) { out[10] = 1.0; return; }
+    Vertex v;
+    if (!make_vertex(S, o, d, h, v)) { out[10] = 1.0; return; }
+    double sxx, syy, sxy;
+    footprint(v, beta2, sxx, syy, sxy);
+    Side near_side{v.m, 1.0, 0.0}, far_side{v.m, 1.0, 0.0};
+    double nx = 0, ny = 0, c = 0, mf = 0;
+    const bool comp = S.have_bedges && composite_at(S, v, S.mat[h.tri], sxx, syy, sxy, reach_m, far_side, nx, ny, c, mf);
+    const bool far = comp && !(u[3] < 1.0 - mf);
+    const Side& cs = far ? far_side : near_side;
+    out[0] = comp; out[1] = c; out[2] = nx; out[3] = ny; out[4] = mf; out[5] = far;
+    double kox, koy, wgt;
+    int ev;
+    if (!sample_finf(*cs.m, k, k * v.dx, k * v.dy, v.ci, u[0], u[1], u[2], cs.gx, cs.gy, kox, koy, wgt, ev)) {
+        out[10] = 1.0;
+        return;
+    }
+    double kn = std::sqrt(std::max(0.0, 1.0 - (kox * kox + koy * koy) / (k * k)));
+    V3 dn = unit((kox / k) * v.xa + (koy / k) * v.ya + kn * v.ns);
+    out[6] = wgt; out[7] = dn.x; out[8] = dn.y; out[9] = dn.z;
+}
+
 // Closest hit for a batch of rays (tests).  rays: [n][6] (origin, direction).  out: [n][4]
 // (triangle, t, u, v); triangle = -1 on a miss.  tmin < 0 selects the default offset.
 void or_intersect(void* s, const double* rays, int64_t n, double tmin, int use_bvh, double* out) {
@@ -1093,13 +1459,14 @@ void or_interaction(void* s, const double* ray, double k, const double* u, doubl
 // Render.  pixels: optional list of (x, y) pairs (npix of them); when null, every pixel of
 // the sensor in row-major order.  image: [nl][npix].  paths (optional):
 // [spp_count][npix][nl] per-path contributions (already divided by spp_norm).
-// stats: [segments, shadow rays, evanescent kills, backfacing kills].
+// stats: [segments, shadow rays, evanescent kills, backfacing kills, composite interactions].
 int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
              const double* lambdas, int32_t nl, const or_opts* op, const int32_t* pixels,
              int64_t npix, double* image, double* paths, uint64_t* stats) {
     if (!s || !sen || !op || nl <= 0 || op->spp_count < 0 || op->max_depth < 0) return -1;
     if (op->hero && nl % 4 != 0) return -1;
     if (op->hero && op->aniso) return -1;   // hero paths carry scalar beta, rho
+    if (op->composite && (op->hero || op->aniso || !((const SceneO*)s)->have_bedges)) return -1;
     const SceneO* S = (const SceneO*)s;
     if (!pixels) npix = (int64_t)sen->width * sen->height;
     Ctx C{S, sen, src, nsrc, lambdas, nl, op};
@@ -1146,9 +1513,10 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
     std::vector<std::thread> th;
     for (int i = 0; i < nt; ++i) th.emplace_back(work, i);
     for (auto& t : th) t.join();
-    uint64_t tot[4] = {0, 0, 0, 0};
+    uint64_t tot[5] = {0, 0, 0, 0, 0};
     for (auto& st : sts) {
         tot[0] += st.segments; tot[1] += st.shadow; tot[2] += st.evanescent; tot[3] += st.backfacing;
+        tot[4] += st.composite;
     }
     if (stats) std::memcpy(stats, tot, sizeof(tot));
     return 0;

@@ -15,6 +15,7 @@ from .scenes import (  # noqa: F401
     tiny_grating,
     parallel_mirror,
     grating_relay,
+    split_mirror,
     terrain_scene,
     mid_terrain,
     large_scene,

@@ -183,6 +183,30 @@ def grating_relay(width: int = 16, height: int = 16, spp: int = 8, seed: int = 9
                     seed=seed)
 
 
+def split_mirror(width: int = 64, height: int = 4, spp: int = 4, seed: int = 11,
+                 left: Optional[Material] = None, right: Optional[Material] = None,
+                 pitch: float = 6e-6, sigma: float = 10e-6, n_lambda: int = 1) -> Workload:
+    """A 2 mm square in z=0 made of two 1 mm x 2 mm halves of different materials (x < 0:
+    `left`, default smooth with reflectance 1; x > 0: `right`, default smooth with reflectance
+    0.25), meshed as two quads that share the boundary edge x = 0 (6 vertices, 4 triangles).
+    A plane wave travels along -z; an orthographic sensor 1 cm above looks straight down, its
+    rows across the boundary (pixel x grows with world x, the sensor centred on the boundary),
+    so every path meets the surface at normal incidence at the mirror direction of the light."""
+    h = 1e-3
+    verts = np.array([[-h, -h, 0.0], [0.0, -h, 0.0], [h, -h, 0.0],
+                      [-h, h, 0.0], [0.0, h, 0.0], [h, h, 0.0]], np.float64)
+    tris = np.array([[0, 1, 4], [0, 4, 3], [1, 2, 5], [1, 5, 4]], np.int32)
+    mats = [left if left is not None else Material(SMOOTH, reflectance=1.0),
+            right if right is not None else Material(SMOOTH, reflectance=0.25)]
+    scene = Scene(verts=verts, tris=tris, tri_mat=np.array([0, 0, 1, 1], np.int32), materials=mats,
+                  normals=None)
+    sensor = _ortho_sensor(np.array([0.0, 0.0, 0.01]), np.array([0.0, 0.0, -1.0]),
+                           np.array([0.0, -1.0, 0.0]), width, height, pitch, sigma)
+    src = Source(PLANE_WAVE, dir=np.array([0.0, 0.0, -1.0]), power=1.0)
+    lam = np.array([0.55]) if n_lambda == 1 else wavelength_bins(n_lambda)
+    return Workload("split-mirror", scene, sensor, [src], lam, spp=spp, max_depth=1, seed=seed)
+
+
 # --------------------------------------------------------------------------------------
 # Terrain: value-noise heightfield with per-tile materials
 # --------------------------------------------------------------------------------------
