@@ -97,7 +97,8 @@ enum {
     GR_TRACE_SHORT_LDS_STACK = 2,
     /* 4 is not used */
     GR_TRACE_HERO = 8,
-    GR_TRACE_ANISO = 16
+    GR_TRACE_ANISO = 16,
+    GR_TRACE_COMPOSITE = 32
 };
 
 /* Trace options.
@@ -139,7 +140,19 @@ enum {
  *                          along the plane of scattering; the footprint at each hit is the
  *                          ray's spatial moments on the surface.  Without the flag beta, rho
  *                          stay scalar and interactions leave them unchanged.  Closed-form p_w
- *                          and one wavelength per path only (else GR_E_UNSUPPORTED).  Other bits are invalid. */
+ *                          and one wavelength per path only (else GR_E_UNSUPPORTED).
+ *                          GR_TRACE_COMPOSITE applies composite interactions (Sec. "Wave-Optical
+ *                          Rendering": a generalized ray whose footprint covers two materials
+ *                          meets the composition of their interaction operators, whose scattered
+ *                          waves interfere) where a material boundary found by
+ *                          gr_scene_boundaries lies within the ball that holds the ray: the
+ *                          measurement takes the composite p_w of the two sides (see
+ *                          gr_pw_composite_eval) and the continuation samples the far side's
+ *                          unwindowed kernel with the probability of the window's intensity mass
+ *                          beyond the boundary, else the near side's.  Needs gr_scene_boundaries
+ *                          (else GR_E_NO_SCENE); scalar rays, the closed-form p_w and one
+ *                          wavelength per path only (else GR_E_UNSUPPORTED).  Other bits are
+ *                          invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;
@@ -168,6 +181,7 @@ typedef struct {
     uint64_t nonfinite;         /* non-finite contributions dropped */
     uint64_t node_visits;       /* BVH nodes fetched (closest-hit and any-hit) */
     uint64_t tri_tests;         /* triangle tests (closest-hit and any-hit) */
+    uint64_t composite;         /* interactions that met a material boundary (GR_TRACE_COMPOSITE) */
     float ms;                   /* device time of the path-tracing kernels (trace, network
                                    pass, shadow rays, record merge) */
     float ms_reduce;            /* device time of the per-pixel reduction */
@@ -200,6 +214,18 @@ int gr_scene_upload(gr_ctx* ctx, const float* verts_m, int64_t nv, const float* 
                     const int32_t* tris, int64_t nt, const int32_t* tri_mat,
                     const gr_material* mats, int32_t nm);
 int gr_scene_info_get(const gr_ctx* ctx, gr_scene_info* info);
+
+/* Material boundaries of the uploaded scene, for GR_TRACE_COMPOSITE (Sec. "Wave-Optical
+ * Rendering", composite interactions): every mesh edge used by exactly two triangles (same
+ * vertex indices) whose materials differ.  For each triangle, the boundary edges of its own
+ * material within reach_m metres of it are listed on the device; a hit then takes the nearest
+ * of them within min(2.5 beta_max, reach_m), beta_max = sqrt(2) times the footprint's largest
+ * standard deviation, as one straight boundary carried onto the hit's tangent plane.
+ * reach_m in [1e-6, 1]; n_edges (optional, host) receives the number of boundary edges.
+ * Allocates device memory (64 B per edge, 8 B per triangle, 4 B per list entry); replaced by
+ * the next call and freed with the scene.  Errors: GR_E_NO_SCENE before gr_scene_upload,
+ * GR_E_INVALID for reach_m, GR_E_OOM, GR_E_UNSUPPORTED beyond 2^32 list entries. */
+int gr_scene_boundaries(gr_ctx* ctx, float reach_m, int64_t* n_edges);
 
 int gr_set_sensor(gr_ctx* ctx, const gr_sensor* sensor);
 /* Up to 16 sources; next-event estimation picks one uniformly per interaction. */
@@ -262,14 +288,32 @@ int gr_trace_noalloc(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, cons
  * where the query is inside its domain and the closed form elsewhere.  out: device [n]. */
 int gr_bsdf_eval(gr_ctx* ctx, const float* queries, int64_t n, int32_t mode, float* out);
 
+/* Composite p_w (um^2) at a straight material boundary for a batch of queries (device), the
+ * operator GR_TRACE_COMPOSITE applies (Sec. "Wave-Optical Rendering": composition of two
+ * materials' interaction operators).  In surface coordinates x about the hit, the near
+ * material fills n.x < c and the far one n.x > c; p_w is the squared Fourier integral of the
+ * amplitude window exp(-x^T S^-1 x / 4) times each side's reflection function over its
+ * half-plane, normalised like gr_bsdf_eval's p_w, averaged over the (unstated) position of
+ * each side's deterministic profile, so that the orders of a side add in power and the sides
+ * interfere through their undiffracted mean fields; a rough side's diffuse terms are its
+ * single-material ones weighted by the window's intensity mass on its side.
+ * Row layout (23 floats): near material kind, height_um, length_um, reflectance, grating
+ * direction (gx, gy) in the frame; far material (the same six); k (um^-1); kix, kiy, kox, koy
+ * (um^-1); sxx, syy, sxy (footprint covariance, um^2); nx, ny (unit normal of the boundary,
+ * towards the far side); c >= 0 (um).  out: device [n]. */
+int gr_pw_composite_eval(gr_ctx* ctx, const float* queries, int64_t n, float* out);
+
 /* Learned scattering model (the surrogate of p_w for Gaussian rough surfaces): a
  * 10 -> 64 -> 64 -> 64 -> 64 -> 1 perceptron with GELU (tanh form).
  * params: device float [13249] laid out W1[10][64], b1[64], W2[64][64], b2, W3, b3, W4, b4,
  * W5[64][1], b5[1] (row-major [fan_in][fan_out]; a layer computes x W + b).  The matrix-core
  * passes accumulate in FP32.  GR_BSDF_SURROGATE_BF16 rounds weights and activations to
- * bfloat16.  GR_BSDF_SURROGATE_FP8 quantizes them to OCP E4M3: weights per layer with scale
- * max|W| / 448, activations per query and layer with scale max|a| / 448; the output
- * layer runs on the vector ALUs in FP32 in both modes.
+ * bfloat16.  GR_BSDF_SURROGATE_FP8 runs the input layer on bfloat16 operands and the three
+ * 64 x 64 hidden layers on OCP E4M3 operands: weights per output neuron with scale
+ * max|W| / 448 over its 64 inputs (and a second E4M3 copy of the quantized weights divided by
+ * 16), activations per query and layer with scale max|a| / 448 as two E4M3 terms (the value
+ * and 16 times its rounding residual), accumulated in FP32; the output layer runs on the
+ * vector ALUs in FP32 in both modes.
  *
  * Input encoding of a query (sur_encode in the sources; rough surfaces only): the tangential
  * transfer in lobe widths sqrt(2 g) / l (g = (q_z s)^2), the incident tangential direction,

@@ -111,13 +111,17 @@ def lib():
             L.or_aniso_free.argtypes = [C.c_double, C.c_double, dp]
             L.or_aniso_interact.argtypes = [dp, dp, dp, dp]
             L.or_aniso_footprint.argtypes = [dp, dp, dp, dp, dp, dp]
-            L.or_scene_boundaries.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int64]
+            L.or_scene_boundaries.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int64, C.c_double]
             L.or_scene_boundaries.restype = C.c_int64
             L.or_boundary_edge.argtypes = [C.c_void_p, C.c_int64, dp]
             L.or_nearest_boundary.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64, C.c_double, dp]
             L.or_faddeeva.argtypes = [C.c_double, C.c_double, dp]
             L.or_halfplane_field.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp, C.c_int64, dp]
             L.or_pw_composite_batch.argtypes = [dp, C.c_int64, dp]
+            L.or_path_vertices.argtypes = [C.c_void_p, C.POINTER(OrSensor), C.POINTER(OrSource), C.c_int32, dp,
+                                           C.c_int32, C.POINTER(OrOpts), C.c_int32, C.c_int32, C.c_int64,
+                                           C.c_int32, dp, C.c_int32, dp]
+            L.or_path_vertices.restype = C.c_int32
             L.or_interaction_composite.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, dp, C.c_double, dp]
             _lib = L
     return _lib
@@ -310,19 +314,20 @@ class OracleScene:
             lib().or_scene_destroy(self.h)
             self.h = None
 
-    def boundaries(self):
-        """Find the material-boundary edges (once); returns their number."""
-        if self.n_boundaries is None:
-            tris = self._keep[1]
-            n = lib().or_scene_boundaries(self.h, tris.ctypes.data_as(C.POINTER(C.c_int32)), tris.shape[0])
-            if n < 0:
-                raise RuntimeError("oracle boundary search failed")
-            self.n_boundaries = int(n)
+    def boundaries(self, reach_m=2e-3):
+        """Find the material-boundary edges (once) and grid them for searches within reach_m;
+        returns their number."""
+        tris = self._keep[1]
+        n = lib().or_scene_boundaries(self.h, tris.ctypes.data_as(C.POINTER(C.c_int32)), tris.shape[0],
+                                      float(reach_m))
+        if n < 0:
+            raise RuntimeError("oracle boundary search failed")
+        self.n_boundaries = int(n)
         return self.n_boundaries
 
     def boundary_edges(self):
         """[n][14]: p0 (3), p1 (3), the two materials, the two triangles' third vertices (6)."""
-        n = self.boundaries()
+        n = self.boundaries() if self.n_boundaries is None else self.n_boundaries
         out = np.zeros((n, 14))
         row = np.zeros(14)
         for i in range(n):
@@ -333,7 +338,8 @@ class OracleScene:
     def nearest_boundary(self, mat, points, reach_m):
         """Nearest boundary edge of material mat within reach of each point: [n][2] (index or
         -1, distance)."""
-        self.boundaries()
+        if self.n_boundaries is None:
+            self.boundaries()
         P = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, 3))
         out = np.zeros((P.shape[0], 2))
         lib().or_nearest_boundary(self.h, int(mat), _dp(P), P.shape[0], float(reach_m), _dp(out))
@@ -342,7 +348,7 @@ class OracleScene:
     def interaction_composite(self, origin, direction, k, beta2, u, reach_m=2e-3):
         """One interaction with composite interactions: dict with composite, c (um), n, the
         far side's window mass, the side chosen by u[3], weight, direction and ended."""
-        self.boundaries()
+        self.boundaries(reach_m)
         ray = np.ascontiguousarray(np.concatenate([np.asarray(origin, np.float64).ravel(),
                                                    np.asarray(direction, np.float64).ravel()]))
         out = np.zeros(11)
@@ -412,7 +418,7 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
     L = lib()
     oscene = OracleScene(wl.scene) if oscene is None else oscene
     if composite:
-        oscene.boundaries()
+        oscene.boundaries(reach_m)
     lam = np.ascontiguousarray(wl.lambdas_um if lambdas is None else lambdas, np.float64)
     nl = lam.shape[0]
     spp_count = wl.spp if spp_count is None else spp_count
@@ -446,6 +452,27 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
     if keep_paths:
         return img, st, paths
     return img, st
+
+
+def path_vertices(wl, px, py, s, w, oscene=None, composite=False, reach_m=2e-3, aniso=False):
+    """The interactions of one path of a render: (contribution, rows [n][12] = depth,
+    triangle, hit point (3), composite, c (um), boundary normal (2), far mass, measurement,
+    continuation side (0 near, 1 far, -1 none))."""
+    oscene = OracleScene(wl.scene) if oscene is None else oscene
+    if composite:
+        oscene.boundaries(reach_m)
+    lam = np.ascontiguousarray(wl.lambdas_um, np.float64)
+    op = OrOpts(spp_begin=0, spp_count=wl.spp, spp_norm=float(wl.spp), max_depth=wl.max_depth,
+                rr_enable=int(wl.rr_enable), rr_threshold24=rr_threshold24(wl.rr_p),
+                rr_p=float(np.float32(wl.rr_p)), seed=wl.seed, use_bvh=1, n_threads=1, hero=0, aniso=int(aniso),
+                composite=int(composite), reach_m=float(reach_m))
+    sen = _sensor_struct(wl.sensor)
+    srcs = _sources_struct(wl.sources)
+    out = np.zeros((64, 12))
+    val = np.zeros(1)
+    n = lib().or_path_vertices(oscene.h, C.byref(sen), srcs, len(wl.sources), _dp(lam), lam.shape[0],
+                               C.byref(op), int(px), int(py), int(s), int(w), _dp(out), 64, _dp(val))
+    return float(val[0]), out[:n]
 
 
 # ------------------------------------------------------------------------------------------

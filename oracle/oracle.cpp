@@ -20,6 +20,7 @@
 #include <cstdint>
 #include <cstring>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 // Worker threads when the caller does not say: the hardware threads, at most 16 (a
@@ -563,6 +564,12 @@ struct SceneO {
     std::vector<BEdge> bedges;
     std::vector<std::vector<int>> mat_bedges;
     bool have_bedges = false;
+    // Uniform grid over the boundary edges (cell size bcell, origin borg): each edge is listed,
+    // in id order, in every cell that its box widened by bcell touches, so every edge within
+    // bcell of a point is listed in the point's cell.
+    double bcell = 0.0;
+    V3 borg{0, 0, 0};
+    std::unordered_map<uint64_t, std::vector<int>> bgrid;
 };
 
 void tri_bounds(const Tri& T, V3& lo, V3& hi) {
@@ -711,7 +718,13 @@ struct Vertex {
     const Mat* m;
 };
 
-// Returns false when the shading normal faces away from the incoming ray.
+// Incidence cosines at or below this end the path as back-facing: the footprint is stretched
+// along the plane of incidence by 1 / cos, and beyond a millionfold it no longer is small
+// against the geometry, which the ray-traced propagation of Sec. "Interactive Rendering"
+// assumes.
+constexpr double kGrazingCos = 1e-6;
+
+// Returns false when the shading normal faces away from the incoming ray (or grazes it).
 bool make_vertex(const SceneO& S, V3 o, V3 d, const Hit& h, Vertex& v) {
     v.P = o + h.t * d;
     const Tri& T = S.tris[h.tri];
@@ -727,7 +740,7 @@ bool make_vertex(const SceneO& S, V3 o, V3 d, const Hit& h, Vertex& v) {
     v.ng = ng;
     v.ns = ns;
     v.ci = -dot(d, ns);
-    if (v.ci <= 0.0) return false;
+    if (v.ci <= kGrazingCos) return false;
     v.m = &S.mats[S.mat[h.tri]];
     make_frame(*v.m, ns, d, v.xa, v.ya);
     v.dx = dot(d, v.xa);
@@ -789,19 +802,70 @@ void find_boundaries(SceneO& S, const int32_t* tris, int64_t nt) {
     S.have_bedges = true;
 }
 
+// Distance from P to the segment [a, b].  Where the nearest point is an end, the distance is
+// taken to that end itself, so that edges meeting at a vertex give equal distances there (the
+// ties of the nearest-boundary rule then go to the lower edge id).
 double point_segment_distance(V3 P, V3 a, V3 b) {
     const V3 ab = b - a;
     const double l2 = dot(ab, ab);
-    double t = l2 > 0.0 ? dot(P - a, ab) / l2 : 0.0;
-    t = std::min(1.0, std::max(0.0, t));
+    const double t = l2 > 0.0 ? dot(P - a, ab) / l2 : 0.0;
+    if (!(t > 0.0)) return norm(P - a);
+    if (t >= 1.0) return norm(P - b);
     return norm(P - (a + t * ab));
 }
 
 // Nearest boundary edge of material mat within distance reach (metres) of P, -1 if none;
 // equal distances go to the lower edge index.
+uint64_t bcell_key(const SceneO& S, V3 P) {
+    const int64_t x = (int64_t)std::floor((P.x - S.borg.x) / S.bcell);
+    const int64_t y = (int64_t)std::floor((P.y - S.borg.y) / S.bcell);
+    const int64_t z = (int64_t)std::floor((P.z - S.borg.z) / S.bcell);
+    return ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) | (uint64_t)(z & 0x1FFFFF);
+}
+
+void build_bgrid(SceneO& S, double cell) {
+    S.bgrid.clear();
+    S.bcell = cell;
+    S.borg = V3{1e300, 1e300, 1e300};
+    for (const auto& E : S.bedges) {
+        S.borg.x = std::min({S.borg.x, E.p0.x, E.p1.x});
+        S.borg.y = std::min({S.borg.y, E.p0.y, E.p1.y});
+        S.borg.z = std::min({S.borg.z, E.p0.z, E.p1.z});
+    }
+    S.borg = S.borg - V3{4 * cell, 4 * cell, 4 * cell};
+    for (int id = 0; id < (int)S.bedges.size(); ++id) {
+        const auto& E = S.bedges[id];
+        const int64_t lo[3] = {(int64_t)std::floor((std::min(E.p0.x, E.p1.x) - cell - S.borg.x) / cell),
+                               (int64_t)std::floor((std::min(E.p0.y, E.p1.y) - cell - S.borg.y) / cell),
+                               (int64_t)std::floor((std::min(E.p0.z, E.p1.z) - cell - S.borg.z) / cell)};
+        const int64_t hi[3] = {(int64_t)std::floor((std::max(E.p0.x, E.p1.x) + cell - S.borg.x) / cell),
+                               (int64_t)std::floor((std::max(E.p0.y, E.p1.y) + cell - S.borg.y) / cell),
+                               (int64_t)std::floor((std::max(E.p0.z, E.p1.z) + cell - S.borg.z) / cell)};
+        for (int64_t x = lo[0]; x <= hi[0]; ++x)
+            for (int64_t y = lo[1]; y <= hi[1]; ++y)
+                for (int64_t z = lo[2]; z <= hi[2]; ++z) {
+                    const uint64_t key = ((uint64_t)(x & 0x1FFFFF) << 42) | ((uint64_t)(y & 0x1FFFFF) << 21) |
+                                         (uint64_t)(z & 0x1FFFFF);
+                    S.bgrid[key].push_back(id);
+                }
+    }
+}
+
 int nearest_boundary(const SceneO& S, int mat, V3 P, double reach, double& dist) {
     int best = -1;
     dist = reach;
+    if (S.bcell > 0.0 && reach <= S.bcell) {
+        // every edge within reach of P is listed in P's cell (in id order)
+        auto it = S.bgrid.find(bcell_key(S, P));
+        if (it == S.bgrid.end()) return -1;
+        for (int id : it->second) {
+            const auto& E = S.bedges[id];
+            if (E.mat[0] != mat && E.mat[1] != mat) continue;
+            const double d = point_segment_distance(P, E.p0, E.p1);
+            if (d < dist) { best = id; dist = d; }
+        }
+        return best;
+    }
     for (int id : S.mat_bedges[mat]) {
         const double d = point_segment_distance(P, S.bedges[id].p0, S.bedges[id].p1);
         if (d < dist || (d == dist && best >= 0 && id < best)) {
@@ -992,7 +1056,10 @@ void footprint_aniso(V3 d, V3 n, V3 xa, V3 ya, const Aniso& A, double& sxx, doub
     sxy = 0.5 * (S[0][1] + S[1][0]);
 }
 
-double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
+// vtx (optional, tests): per interaction, 12 values: depth, triangle, hit point (3), composite
+// (1 or 0), boundary distance c (um), its normal (2), far-side mass, the measurement added,
+// and the side the continuation took (0 near, 1 far, -1 none).
+double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st, std::vector<double>* vtx = nullptr) {
     const SceneO& S = *C.S;
     const or_sensor& sen = *C.sen;
     const or_opts& op = *C.op;
@@ -1037,6 +1104,13 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
         const bool comp = op.composite &&
                           composite_at(S, v, S.mat[h.tri], sxx, syy, sxy, op.reach_m, far_side, bnx, bny, bc, mass_far);
         if (comp) st.composite++;
+        size_t vrow = 0;
+        if (vtx) {
+            vrow = vtx->size();
+            const double row[12] = {(double)depth, (double)h.tri, v.P.x, v.P.y, v.P.z, comp ? 1.0 : 0.0, bc, bnx, bny,
+                                    mass_far, 0.0, -1.0};
+            vtx->insert(vtx->end(), row, row + 12);
+        }
 
         // Measurement by next-event estimation (measurement operator, eq.
         // measurement_operator, with the ensemble-averaged source WDF).
@@ -1057,6 +1131,7 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
                     double p = comp ? pw_composite(near_side, far_side, k, kix, kiy, kox, koy, sxx, syy, sxy, bnx, bny, bc)
                                     : pw_eval(m, k, kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
                     contrib += alpha * L.power * p * (double)C.nsrc;
+                    if (vtx) (*vtx)[vrow + 10] = alpha * L.power * p * (double)C.nsrc;
                 }
             }
         }
@@ -1068,6 +1143,7 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st) {
         // near side's: a one-sample estimate of the mass-weighted mixture of the two kernels.
         U4 rs = draw(pid, depth, STREAM_SCATTER, op.seed);
         const Side& cs = (comp && !(unif(rn.v[3]) < 1.0 - mass_far)) ? far_side : near_side;
+        if (vtx) (*vtx)[vrow + 11] = (&cs == &far_side) ? 1.0 : 0.0;
         double kix = k * v.dx, kiy = k * v.dy, kox, koy, wgt;
         int ev;
         if (!sample_finf(*cs.m, k, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), cs.gx, cs.gy,
@@ -1317,12 +1393,15 @@ void* or_scene_create(const double* verts, int64_t nv, const double* normals,
 
 void or_scene_destroy(void* s) { delete (SceneO*)s; }
 
-// Find the scene's material boundaries (needed by composite rendering).  tris: the index
-// array given to or_scene_create.  Returns the number of boundary edges.
-int64_t or_scene_boundaries(void* s, const int32_t* tris, int64_t nt) {
+// Find the scene's material boundaries (needed by composite rendering) and grid them with
+// cells of `cell` metres (the largest reach searched through the grid; farther searches scan
+// the material's edges).  tris: the index array given to or_scene_create.  Returns the
+// number of boundary edges.
+int64_t or_scene_boundaries(void* s, const int32_t* tris, int64_t nt, double cell) {
     SceneO& S = *(SceneO*)s;
-    if ((int64_t)S.tris.size() != nt) return -1;
-    find_boundaries(S, tris, nt);
+    if ((int64_t)S.tris.size() != nt || !(cell > 0.0)) return -1;
+    if (!S.have_bedges) find_boundaries(S, tris, nt);
+    if (S.bcell != cell) build_bgrid(S, cell);
     return (int64_t)S.bedges.size();
 }
 
@@ -1346,6 +1425,21 @@ void or_nearest_boundary(void* s, int32_t mat, const double* P, int64_t n, doubl
         out[2 * i] = id;
         out[2 * i + 1] = id >= 0 ? d : 0.0;
     }
+}
+
+// The interactions of one path (tests): pixel (px, py), sample s, wavelength w of a render
+// with these options; out: up to max_rows rows of the 12 values trace_path records.  Returns
+// the number of rows (the path's contribution in *value, already divided by spp_norm).
+int32_t or_path_vertices(void* sc, const or_sensor* sen, const or_source* src, int32_t nsrc, const double* lambdas,
+                         int32_t nl, const or_opts* op, int32_t px, int32_t py, int64_t s, int32_t w, double* out,
+                         int32_t max_rows, double* value) {
+    Ctx C{(const SceneO*)sc, sen, src, nsrc, lambdas, nl, op};
+    Stats st;
+    std::vector<double> v;
+    *value = trace_path(C, px, py, s, w, st, &v) / op->spp_norm;
+    const int32_t n = (int32_t)(v.size() / 12);
+    std::memcpy(out, v.data(), sizeof(double) * 12 * (size_t)std::min(n, max_rows));
+    return n;
 }
 
 // Faddeeva function (tests): z = (re, im), im >= 0; out [2].

@@ -20,6 +20,7 @@ GR_TRACE_KEEP_PATHS = 1
 GR_TRACE_SHORT_LDS_STACK = 2
 GR_TRACE_HERO = 8
 GR_TRACE_ANISO = 16
+GR_TRACE_COMPOSITE = 32
 GR_MLP_PARAMS = 13249
 
 
@@ -52,7 +53,8 @@ class GrStats(C.Structure):
                 ("surrogate_evals", C.c_uint64), ("fallbacks", C.c_uint64),
                 ("evanescent", C.c_uint64), ("backfacing", C.c_uint64),
                 ("nonfinite", C.c_uint64), ("node_visits", C.c_uint64),
-                ("tri_tests", C.c_uint64), ("ms", C.c_float), ("ms_reduce", C.c_float)]
+                ("tri_tests", C.c_uint64), ("composite", C.c_uint64), ("ms", C.c_float),
+                ("ms_reduce", C.c_float)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
@@ -82,6 +84,7 @@ SIGNATURES = [
     ("gr_scene_upload", C.c_int, [_vp, _fp, C.c_int64, _fp, C.POINTER(C.c_int32), C.c_int64,
                                   C.POINTER(C.c_int32), C.POINTER(GrMaterial), C.c_int32]),
     ("gr_scene_info_get", C.c_int, [_vp, C.POINTER(GrSceneInfo)]),
+    ("gr_scene_boundaries", C.c_int, [_vp, C.c_float, C.POINTER(C.c_int64)]),
     ("gr_set_sensor", C.c_int, [_vp, C.POINTER(GrSensor)]),
     ("gr_set_sources", C.c_int, [_vp, C.POINTER(GrSource), C.c_int32]),
     ("gr_workspace_size", C.c_int, [_vp, C.POINTER(GrTraceOpts), C.c_int32,
@@ -91,6 +94,7 @@ SIGNATURES = [
                            C.POINTER(GrStats)]),
     ("gr_trace_noalloc", C.c_int, [_vp, _fp, C.c_int32, C.POINTER(GrTraceOpts), _fp]),
     ("gr_bsdf_eval", C.c_int, [_vp, _fp, C.c_int64, C.c_int32, _fp]),
+    ("gr_pw_composite_eval", C.c_int, [_vp, _fp, C.c_int64, _fp]),
     ("gr_surrogate_samples", C.c_int, [_vp, C.c_int64, C.c_uint64, _fp, _fp, _fp, _fp]),
     ("gr_mlp_workspace_size", C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
     ("gr_mlp_forward", C.c_int, [_vp, _fp, _fp, C.c_int64, C.c_int32, _vp, _fp]),

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgrwave.so")
 
-SOURCES = ["api.cpp", "bvh_build.cpp", "trace.hip", "mlp.hip", "coherent.hip"]
+SOURCES = ["api.cpp", "bvh_build.cpp", "boundary.cpp", "trace.hip", "mlp.hip", "coherent.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]

@@ -44,7 +44,20 @@ struct gr_ctx {
     int grid_sur = 0;
     int grid_hero = 0;
     int grid_aniso = 0;
+    int grid_comp = 0;
     int grid_batch = 0;              // blocks of the batched network pass
+    // host copies of the mesh (material boundaries are found on request)
+    std::vector<float> h_verts;
+    std::vector<int32_t> h_tris, h_tri_mat;
+    // material boundaries (gr_scene_boundaries)
+    void* d_bedges = nullptr;
+    void* d_btri = nullptr;
+    void* d_bidx = nullptr;
+    int64_t n_bedges = 0;
+    float reach_m = 0.0f;
+    bool has_boundaries = false;
+    float weid[grw::kWeidN] = {};
+    float weid_L = 0.0f;
     grw::SurrogateState sur;
 };
 
@@ -76,7 +89,17 @@ bool unit3(const float* v) {
     return std::fabs(n - 1.0) < 1e-3;
 }
 
+void free_boundaries(gr_ctx* c) {
+    if (c->d_bedges) (void)hipFree(c->d_bedges);
+    if (c->d_btri) (void)hipFree(c->d_btri);
+    if (c->d_bidx) (void)hipFree(c->d_bidx);
+    c->d_bedges = c->d_btri = c->d_bidx = nullptr;
+    c->n_bedges = 0;
+    c->has_boundaries = false;
+}
+
 void free_scene(gr_ctx* c) {
+    free_boundaries(c);
     if (c->d_nodes) (void)hipFree(c->d_nodes);
     if (c->d_tris) (void)hipFree(c->d_tris);
     if (c->d_tnorm) (void)hipFree(c->d_tnorm);
@@ -112,6 +135,7 @@ struct WsLayout {
 };
 
 bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
+bool composite_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_COMPOSITE) != 0; }
 bool aniso_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_ANISO) != 0; }
 // one wavelength per path in the persistent kernel: shadow rays go through a queue of their own
 bool shadow_queue_of(const gr_trace_opts* o) { return !hero_of(o); }
@@ -248,16 +272,54 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     c->grid_sur = grw::trace_grid_size(c->device, true);
     c->grid_hero = grw::trace_grid_size(c->device, false, true);
     c->grid_aniso = grw::trace_grid_size(c->device, false, false, true);
+    c->grid_comp = grw::trace_grid_size(c->device, false, false, false, true);
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
         c->grid_batch = 4 * std::max(ncu, 1);
     }
-    if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0 || c->grid_aniso <= 0) {
+    if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0 || c->grid_aniso <= 0 || c->grid_comp <= 0) {
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
+    c->h_verts.assign(verts, verts + 3 * nv);
+    c->h_tris.assign(tris, tris + 3 * nt);
+    c->h_tri_mat.assign(tri_mat, tri_mat + nt);
     c->has_scene = true;
+    return GR_OK;
+}
+
+int gr_scene_boundaries(gr_ctx* c, float reach_m, int64_t* n_edges) {
+    if (!c) return GR_E_INVALID;
+    if (!(reach_m >= 1e-6f && reach_m <= 1.0f)) return fail(c, GR_E_INVALID, "boundaries: reach_m outside [1e-6, 1] m");
+    if (!c->has_scene) return fail(c, GR_E_NO_SCENE, "boundaries: no scene");
+    grw::BuiltBoundaries B;
+    const int64_t nt = (int64_t)c->h_tri_mat.size();
+    if (!grw::build_boundaries(c->h_verts.data(), c->h_tris.data(), c->h_tri_mat.data(), nt, reach_m, B))
+        return fail(c, GR_E_UNSUPPORTED, "boundaries: more than 2^32 candidate entries");
+    std::vector<uint32_t> tl(2 * (size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        tl[2 * t] = B.first[t];
+        tl[2 * t + 1] = B.count[t];
+    }
+    GR_HIP(c, hipSetDevice(c->device));
+    free_boundaries(c);
+    const size_t eb = std::max<size_t>(B.edges.size(), 16) * 4, tb = tl.size() * 4,
+                 ib = std::max<size_t>(B.idx.size(), 1) * 4;
+    if (hipMalloc(&c->d_bedges, eb) != hipSuccess || hipMalloc(&c->d_btri, tb) != hipSuccess ||
+        hipMalloc(&c->d_bidx, ib) != hipSuccess) {
+        free_boundaries(c);
+        (void)hipGetLastError();
+        return fail(c, GR_E_OOM, "boundaries: device allocation of %zu bytes failed", eb + tb + ib);
+    }
+    if (!B.edges.empty()) GR_HIP(c, hipMemcpy(c->d_bedges, B.edges.data(), B.edges.size() * 4, hipMemcpyHostToDevice));
+    GR_HIP(c, hipMemcpy(c->d_btri, tl.data(), tb, hipMemcpyHostToDevice));
+    if (!B.idx.empty()) GR_HIP(c, hipMemcpy(c->d_bidx, B.idx.data(), B.idx.size() * 4, hipMemcpyHostToDevice));
+    grw::weideman_coefficients(grw::kWeidN, c->weid, &c->weid_L);
+    c->n_bedges = B.n_edges;
+    c->reach_m = reach_m;
+    c->has_boundaries = true;
+    if (n_edges) *n_edges = B.n_edges;
     return GR_OK;
 }
 
@@ -322,7 +384,7 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
     const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
     const size_t lanes =
-        (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso}) * 256;
+        (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso, c->grid_comp}) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
@@ -397,8 +459,11 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
     if (o->bsdf_mode < 0 || o->bsdf_mode > 2) return fail(c, GR_E_INVALID, "trace: bsdf_mode %d", o->bsdf_mode);
     if (o->rr_enable && !(o->rr_p > 0.0f && o->rr_p <= 1.0f)) return fail(c, GR_E_INVALID, "trace: rr_p");
     if (o->flags &
-        ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_HERO | GR_TRACE_ANISO))
+        ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_HERO | GR_TRACE_ANISO | GR_TRACE_COMPOSITE))
         return fail(c, GR_E_INVALID, "trace: flags");
+    if (composite_of(o) && (hero_of(o) || aniso_of(o) || o->bsdf_mode != GR_BSDF_PLAIN))
+        return fail(c, GR_E_UNSUPPORTED,
+                    "trace: composite interactions with scalar rays, the closed-form p_w and one wavelength per path only");
     if (aniso_of(o) && (hero_of(o) || o->bsdf_mode != GR_BSDF_PLAIN))
         return fail(c, GR_E_UNSUPPORTED,
                     "trace: anisotropic rays with the closed-form p_w and one wavelength per path only");
@@ -408,6 +473,8 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
             return fail(c, GR_E_UNSUPPORTED, "trace: hero wavelengths with the closed-form p_w only");
     }
     if (!c->has_scene || !c->has_sensor) return fail(c, GR_E_NO_SCENE, "trace: scene and sensor must be set");
+    if (composite_of(o) && !c->has_boundaries)
+        return fail(c, GR_E_NO_SCENE, "trace: composite interactions need gr_scene_boundaries");
     if (o->bsdf_mode != GR_BSDF_PLAIN && !c->sur.ready)
         return fail(c, GR_E_INVALID, "trace: surrogate mode without gr_set_surrogate");
     if (o->bsdf_mode != GR_BSDF_PLAIN && (c->sensor.width * (int64_t)c->sensor.height < 1))
@@ -478,6 +545,15 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
     a.spp_begin = o->spp_begin;
     a.hero = hero_of(o) ? 1 : 0;
     a.aniso = aniso_of(o) ? 1 : 0;
+    a.composite = composite_of(o) ? 1 : 0;
+    if (a.composite) {
+        a.bnd.edges = static_cast<const float4*>(c->d_bedges);
+        a.bnd.tri_list = static_cast<const uint2*>(c->d_btri);
+        a.bnd.idx = static_cast<const uint32_t*>(c->d_bidx);
+        a.bnd.reach_m = c->reach_m;
+        a.bnd.weid_L = c->weid_L;
+        for (int i = 0; i < grw::kWeidN; ++i) a.bnd.weid[i] = c->weid[i];
+    }
     a.per_sample = (uint32_t)(a.hero ? per / 4 : per);   // hero: one path per group of 4 wavelengths
     a.n_paths = (uint64_t)a.per_sample * (uint64_t)o->spp_count;
     a.inv_spp_norm = (float)(1.0 / (double)o->spp_norm);
@@ -509,7 +585,9 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
     a.snd = shq ? reinterpret_cast<uint8_t*>(base + WL.nd) : nullptr;
 
     GR_HIP(c, hipSetDevice(c->device));
-    const int grid = defer ? c->grid_sur : (a.hero ? c->grid_hero : (a.aniso ? c->grid_aniso : c->grid_plain));
+    const int grid = defer ? c->grid_sur
+                           : (a.hero ? c->grid_hero
+                                     : (a.aniso ? c->grid_aniso : (a.composite ? c->grid_comp : c->grid_plain)));
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     if (st)
         for (auto& e : ev) GR_HIP(c, hipEventCreate(&e));
@@ -561,6 +639,7 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
         st->nonfinite = h[grw::ST_NONFINITE];
         st->node_visits = h[grw::ST_NODES];
         st->tri_tests = h[grw::ST_TRIS];
+        st->composite = h[grw::ST_COMPOSITE];
         st->ms = ms;
         st->ms_reduce = ms_r;
     }
@@ -594,6 +673,16 @@ int gr_bsdf_eval(gr_ctx* c, const float* q, int64_t n, int32_t mode, float* out)
     } else {
         GR_HIP(c, grw::launch_bsdf_eval_surrogate(c->sur, mode == GR_BSDF_SURROGATE_FP8, q, n, out, c->stream));
     }
+    return GR_OK;
+}
+
+int gr_pw_composite_eval(gr_ctx* c, const float* q, int64_t n, float* out) {
+    if (!c) return GR_E_INVALID;
+    if (n < 0 || (n > 0 && (!q || !out))) return fail(c, GR_E_INVALID, "pw_composite_eval: arguments");
+    grw::BoundaryDev b{};
+    grw::weideman_coefficients(grw::kWeidN, b.weid, &b.weid_L);
+    GR_HIP(c, hipSetDevice(c->device));
+    GR_HIP(c, grw::launch_composite_eval(q, n, out, b, c->stream));
     return GR_OK;
 }
 

@@ -32,3 +32,28 @@ struct BuiltBVH {
 BuiltBVH build_bvh4(const float* verts, const int32_t* tris, int64_t nt);
 
 }  // namespace grw
+
+namespace grw {
+
+// Material boundaries of a triangle mesh, for composite interactions: every mesh edge
+// (unordered vertex-index pair) used by exactly two triangles of different materials, and for
+// each triangle the boundary edges of its own material that lie within `reach` metres of it
+// (candidates: the exact distance test runs at the hit).
+struct BuiltBoundaries {
+    std::vector<float> edges;        // [n][16]: p0, mat a (int bits), p1, mat b, third vertex of a (+pad), of b (+pad)
+    std::vector<uint32_t> first;     // per triangle: first entry in idx
+    std::vector<uint32_t> count;     // per triangle: number of entries
+    std::vector<uint32_t> idx;       // boundary edge ids, ascending per triangle
+    int64_t n_edges = 0;
+};
+
+// verts [nv][3], tris [nt][3] (validated), tri_mat [nt].  Fails (returns false) when the lists
+// would exceed 2^32 entries.
+bool build_boundaries(const float* verts, const int32_t* tris, const int32_t* tri_mat, int64_t nt, float reach,
+                      BuiltBoundaries& out);
+
+// Coefficients a_1 .. a_n of Weideman's rational approximation of the Faddeeva function with
+// n terms, and its parameter L = sqrt(n / sqrt(2)).
+void weideman_coefficients(int n, float* a, float* L);
+
+}  // namespace grw

@@ -208,6 +208,9 @@ __device__ inline float pw_plain(int kind, float h, float L, float refl, float k
     const float qz = k * (sqrtf(1.0f - ni) + sqrtf(1.0f - no));
     const float kx = kox - kix, ky = koy - kiy;
     const float det = sxx * syy - sxy * sxy;
+    // a window thinner than float resolves (its determinant rounds to zero or below: extreme
+    // anisotropic footprints after grazing interactions) measures nothing
+    if (!(det > 0.0f)) return 0.0f;
     const float idet = 0.25f / det;
     const float a = syy * idet, b = sxx * idet, c = -sxy * idet;
     if (kind == MAT_SMOOTH) return refl * gauss2(kx, ky, a, b, c);
@@ -308,13 +311,15 @@ __device__ __noinline__ int poisson_inverse(double g, float u0) {
 // Returns 0 on success, 1 when the path ends evanescently.  comp (optional) receives the
 // sampled component: the grating order, the rough surface's Poisson term (0 = the specular
 // delta), 0 for a smooth surface; pick_p (optional) the probability of a grating's sampled
-// order, w_j / W.
+// order, w_j / W; off (optional, 2 floats) the rough surface's sampled transfer kappa (zero
+// otherwise; a grating's is -j K along x).
 // ------------------------------------------------------------------------------------------
 __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, float ci,
                                   float u0, float u1, float u2, float& kox, float& koy,
                                   float& weight, float* cache, int cache_n, int* comp = nullptr,
-                                  float* pick_p = nullptr) {
+                                  float* pick_p = nullptr, float* off = nullptr) {
     if (comp) *comp = 0;
+    if (off) off[0] = off[1] = 0.0f;
     if (m.kind == MAT_SMOOTH) {
         kox = kix;
         koy = kiy;
@@ -388,6 +393,10 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
     const float sd = sqrtf(2.0f * (float)n) / m.L;
     kox = kix + sd * z1;
     koy = kiy + sd * z2;
+    if (off) {
+        off[0] = sd * z1;
+        off[1] = sd * z2;
+    }
     if (kox * kox + koy * koy >= k2) return 1;
     weight = m.refl;
     return 0;

@@ -52,6 +52,21 @@ struct SurrogateDev {
 // by the sample count), log of the lobe peak, and the (path, depth) slot of the result.
 constexpr int kSurQueryBytes = 32;
 
+// Terms of the rational approximation of the Faddeeva function (composite interactions).
+constexpr int kWeidN = 16;
+
+// Material boundaries of the scene (gr_scene_boundaries) for composite interactions, and the
+// constants of the device's Faddeeva approximation.
+struct BoundaryDev {
+    const float4* edges;     // 4 float4 per boundary edge: p0 (w: material of triangle a, as int
+                             // bits), p1 (w: material of triangle b), the third vertex of a, of b
+    const uint2* tri_list;   // per original triangle: (first, count) into idx
+    const uint32_t* idx;     // boundary edges of the triangle's material near it, ascending
+    float reach_m;           // largest boundary distance considered
+    float weid_L;
+    float weid[kWeidN];      // a_1 .. a_N
+};
+
 struct TraceArgs {
     SceneDev scene;
     SensorDev sensor;
@@ -65,6 +80,8 @@ struct TraceArgs {
     uint32_t per_sample;       // paths per sample: H * W * nl, or H * W * nl / 4 with hero
     int hero;                  // 1: hero-wavelength paths over rotation groups of 4 wavelengths
     int aniso;                 // 1: anisotropic generalized rays (matrix beta, rho)
+    int composite;             // 1: composite interactions at material boundaries
+    BoundaryDev bnd;
     float inv_spp_norm;
     int max_depth;
     int rr_enable;
@@ -91,7 +108,7 @@ struct TraceArgs {
 
 enum {
     ST_PATHS = 0, ST_SEGMENTS, ST_SHADOW, ST_SUR, ST_FALLBACK, ST_EVANESCENT, ST_BACKFACING,
-    ST_NONFINITE, ST_NODES, ST_TRIS, ST_COUNT
+    ST_NONFINITE, ST_NODES, ST_TRIS, ST_COMPOSITE, ST_COUNT
 };
 
 // Launchers (trace.hip).
@@ -111,9 +128,11 @@ hipError_t launch_shadow_merge(const float* val, const uint8_t* nd, int depth, f
 // a queued shadow ray: mean position (3 doubles), travel direction of the light, emitter
 // distance, triangle left, slot
 constexpr int kShadowQueryBytes = 48;
-int trace_grid_size(int device, bool sur, bool hero = false, bool aniso = false);
+int trace_grid_size(int device, bool sur, bool hero = false, bool aniso = false, bool composite = false);
 
 // Batch p_w evaluation (trace.hip).
 hipError_t launch_bsdf_eval(const float* q, int64_t n, float* out, hipStream_t s);
+// Batch composite p_w evaluation: rows of 23 floats (see gr_pw_composite_eval).
+hipError_t launch_composite_eval(const float* q, int64_t n, float* out, const BoundaryDev& b, hipStream_t s);
 
 }  // namespace grw

@@ -12,7 +12,7 @@
 // Algorithm 1 under the interactive assumption of Sec. "Interactive Rendering".
 #include <algorithm>
 
-#include "trace_core.hpp"
+#include "composite.hpp"
 
 namespace grw {
 
@@ -235,7 +235,10 @@ __device__ __forceinline__ void aniso_footprint(const AnisoRay& R, const f3& d, 
     syy = 0.5f * (h1[0] * H[1][0] + h1[1] * H[1][1]);
 }
 
-template <int STACK, bool DEFER, bool HERO, bool ANISO = false>
+// COMPOSITE: where a material boundary of the hit's material lies within the ball holding the
+// generalized ray, the measurement uses the composite p_w of the two sides and the
+// continuation samples one side's kernel with the probability of its window mass.
+template <int STACK, bool DEFER, bool HERO, bool ANISO = false, bool COMPOSITE = false>
 __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
     const int lane = threadIdx.x & 63;
@@ -258,7 +261,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     uint64_t idx = 0, pid = 0;
     int depth = 0, prev = -1;
     d3 o = d3{0.0, 0.0, 0.0};
-    f3 d = mk3(0, 0, 1);
+    // the path's direction, in double: it is renewed at every interaction from the double
+    // shading normal, so that direction errors do not build up along chains of reflections
+    d3 dd = d3{0.0, 0.0, 1.0};
     float beta2 = 1.0f, rho = 0.0f, alpha = 1.0f, k = 1.0f;
     AnisoRay ar;   // ANISO: the ray's second moments (beta2, rho unused)
     if constexpr (ANISO) aniso_iso(ar, 1.0f);
@@ -317,7 +322,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         const double fy = ((double)y + (double)unif(r0.y)) * (double)sen.pitch;
                         o = d3{sen.o[0] + fx * sen.u[0] + fy * sen.v[0], sen.o[1] + fx * sen.u[1] + fy * sen.v[1],
                                sen.o[2] + fx * sen.u[2] + fy * sen.v[2]};
-                        d = mk3(sen.d[0], sen.d[1], sen.d[2]);
+                        dd = d3{(double)sen.d[0], (double)sen.d[1], (double)sen.d[2]};
+                        const f3 d = to_f3(dd);
                         beta2 = 2.0f * sen.sigma_um * sen.sigma_um;
                         rho = 0.0f;
                         // start where the ray enters the scene bounds, so that the float
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         }
                         if constexpr (ANISO) aniso_iso(ar, beta2);
                         if (tadv > 0.0f) {
-                            o = add_scaled(o, tadv, d);
+                            o = d3{o.x + (double)tadv * dd.x, o.y + (double)tadv * dd.y, o.z + (double)tadv * dd.z};
                             const float zb = tadv * 1e6f / k;
                             if constexpr (ANISO) {
                                 aniso_free(ar, zb);
@@ -367,6 +373,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         bool wrote = false;   // SHQ: this vertex stored its measurement slot
         if (live) {
         ev |= 1u << EV_SEG;
+        const f3 d = to_f3(dd);
         RayT ray;
         ray_setup(ray, o, d);
         const float tmin = 1e-7f * (1.0f + maxabs3(to_f3(o)));
@@ -378,7 +385,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
             const float4* T = A.scene.tris + (size_t)tri * 3;
             const float4 v0 = T[0], v1 = T[1], v2 = T[2];
             double t64;
-            refine_hit(o, d, v0, v1, v2, thit, bu, bv, t64);
+            double bu64 = (double)bu, bv64 = (double)bv;
+            refine_hit(o, dd, v0, v1, v2, thit, bu64, bv64, t64);
             // Free-space propagation of the generalized ray (eq. K_free_space_propagation)
             // over the hit distance, zbar = z / |k0|, pre-update beta and rho on the right.
             if constexpr (HERO) {
@@ -399,26 +407,35 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 beta2 = beta2 + zb * (2.0f * rho + zb * orr / beta2);
                 rho = rho_n;
             }
-            const d3 P = d3{o.x + t64 * d.x, o.y + t64 * d.y, o.z + t64 * d.z};
+            const d3 P = d3{o.x + t64 * dd.x, o.y + t64 * dd.y, o.z + t64 * dd.z};
             prev = __float_as_int(v0.w);
             const DMat m = A.scene.mats[__float_as_int(v1.w)];
             f3 ng = normalize3(cross3(mk3(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z),
                                       mk3(v2.x - v0.x, v2.y - v0.y, v2.z - v0.z)));
-            f3 ns = ng;
+            // shading normal in double (barycentric interpolation of the vertex normals)
+            d3 nsd = d3{(double)ng.x, (double)ng.y, (double)ng.z};
             {
                 const float4* NN = A.scene.tnorm + (size_t)tri * 3;
                 const float4 n0 = NN[0], n1 = NN[1], n2 = NN[2];
                 if ((n0.x != 0.f || n0.y != 0.f || n0.z != 0.f) && (n1.x != 0.f || n1.y != 0.f || n1.z != 0.f) &&
                     (n2.x != 0.f || n2.y != 0.f || n2.z != 0.f)) {
-                    const float w0 = 1.0f - bu - bv;
-                    ns = normalize3(mk3(w0 * n0.x + bu * n1.x + bv * n2.x, w0 * n0.y + bu * n1.y + bv * n2.y,
-                                        w0 * n0.z + bu * n1.z + bv * n2.z));
+                    const double w0 = 1.0 - bu64 - bv64;
+                    const d3 sn = d3{w0 * n0.x + bu64 * n1.x + bv64 * n2.x, w0 * n0.y + bu64 * n1.y + bv64 * n2.y,
+                                     w0 * n0.z + bu64 * n1.z + bv64 * n2.z};
+                    const double r = 1.0 / sqrt(sn.x * sn.x + sn.y * sn.y + sn.z * sn.z);
+                    nsd = d3{sn.x * r, sn.y * r, sn.z * r};
                 }
             }
             if (dot3(d, ng) > 0.0f) ng = -1.0f * ng;
-            if (dot3(ns, ng) < 0.0f) ns = -1.0f * ns;
+            if (nsd.x * ng.x + nsd.y * ng.y + nsd.z * ng.z < 0.0) nsd = d3{-nsd.x, -nsd.y, -nsd.z};
+            const f3 ns = to_f3(nsd);
+            const double cid = -(dd.x * nsd.x + dd.y * nsd.y + dd.z * nsd.z);
+            // the float cosine for the float arithmetic below (footprint, p_w, sampling).  The
+            // path ends at an incidence cosine of 1e-6 or less: the footprint, stretched by
+            // 1 / cos along the plane of incidence, is then no longer small against the
+            // geometry (and its float covariance would overflow)
             const float ci = -dot3(d, ns);
-            if (ci <= 0.0f) {
+            if (!(cid > 1e-6) || !(ci > 1e-6f)) {
                 ev |= 1u << EV_BACKFACING;
                 finish = true;
             } else {
@@ -456,6 +473,16 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     sxx = sr2 * (1.0f + dx * dx * ic2);
                     syy = sr2 * (1.0f + dy * dy * ic2);
                     sxy = sr2 * (dx * dy * ic2);
+                }
+                // composite interaction: the boundary within the footprint, if any
+                bool comp = false;
+                int fmat = 0;
+                float gfx = 1.0f, gfy = 0.0f;
+                HalfPlane hp;
+                if constexpr (COMPOSITE) {
+                    comp = find_boundary(A.bnd, prev, __float_as_int(v1.w), P, xa, ya, sxx, syy, sxy, A.scene.mats,
+                                         fmat, gfx, gfy, hp);
+                    if (comp) ev |= 1u << EV_COMPOSITE;
                 }
 
                 // Measurement by next-event estimation (eq. measurement_operator).
@@ -527,9 +554,15 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                                                   __float_as_uint(slp), slot);
                             }
                         }
-                        const float v = e == 0 ? scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy,
-                                                                  sxx, syy, sxy, 1.0f, 0.0f)
-                                               : 0.0f;
+                        float v = 0.0f;
+                        if (e == 0) {
+                            if (COMPOSITE && comp)
+                                v = scale * pw_composite(m, 1.0f, 0.0f, A.scene.mats[fmat], gfx, gfy, k, kix, kiy, kox,
+                                                         koy, hp, A.bnd);
+                            else
+                                v = scale * pw_plain(m.kind, m.h, m.L, m.refl, k, kix, kiy, kox, koy, sxx, syy, sxy,
+                                                     1.0f, 0.0f);
+                        }
                         const bool want = v != 0.0f || e == 1;
                         const unsigned long long qm = __ballot(want);
                         if (want) {
@@ -598,18 +631,40 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 if (depth + 1 >= A.max_depth) {
                     finish = true;
                 } else {
-                    // Light-matter interaction: sample the continuation generalized ray.
+                    // Light-matter interaction: sample the continuation generalized ray.  At a
+                    // composite interaction, the far side's kernel with the probability of its
+                    // window mass (word 3 of the interaction's NEE draw), else the near side's:
+                    // a one-sample estimate of the mass-weighted mixture of the two kernels.  A
+                    // far grating is sampled in its own frame (grating vector along x).
                     const uint4 rs = draw(pid, (uint32_t)depth, STREAM_SCATTER, A.seed);
                     float kox, koy, wgt;
-                    int comp = 0;
+                    int comp_j = 0;
                     float ph = 0.0f;
-                    if (sample_finf(m, k, k * dx, k * dy, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
-                                    (float*)(int*)stk, STACK, HERO ? &comp : nullptr, HERO ? &ph : nullptr)) {
+                    float off[2];
+                    DMat cm = m;
+                    float rcx = 1.0f, rcy = 0.0f;   // the sampled side's grating direction
+                    if constexpr (COMPOSITE) {
+                        if (comp && !(unif(draw(pid, (uint32_t)depth, STREAM_NEE, A.seed).w) < 1.0f - hp.mass_far)) {
+                            cm = A.scene.mats[fmat];
+                            if (cm.kind == MAT_GRATING) {
+                                rcx = gfx;
+                                rcy = gfy;
+                            }
+                        }
+                    }
+                    const float kix_s = rcx * k * dx + rcy * k * dy, kiy_s = -rcy * k * dx + rcx * k * dy;
+                    if (sample_finf(cm, k, kix_s, kiy_s, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
+                                    (float*)(int*)stk, STACK, &comp_j, HERO ? &ph : nullptr, off)) {
                         ev |= 1u << EV_EVANESCENT;
                         finish = true;
                     } else {
+                        if constexpr (COMPOSITE) {
+                            const float ox = rcx * kox - rcy * koy, oy = rcy * kox + rcx * koy;
+                            kox = ox;
+                            koy = oy;
+                        }
                         if constexpr (HERO) {
-                            hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp, ph, mT, mR);
+                            hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp_j, ph, mT, mR);
                         } else {
                             alpha *= wgt;
                         }
@@ -625,12 +680,56 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                         }
                         if (!finish) {
-                            const float kn = sqrtf(fmaxf(0.0f, 1.0f - (kox * kox + koy * koy) / (k * k)));
-                            const f3 din = d;
-                            d = normalize3((kox / k) * xa + (koy / k) * ya + kn * ns);
-                            if constexpr (ANISO) aniso_interact(ar, din, d, ns);
+                            // the new direction in double: the tangential part of the old one
+                            // plus the sampled transfer (a grating order's -j K in its own
+                            // frame, rotated into the hit's), normal part from |d| = 1; the
+                            // frame rebuilt in double by the float frame's rule
+                            double ox = (double)off[0], oy = (double)off[1];
+                            if (cm.kind == MAT_GRATING) {
+                                ox = -(double)comp_j * (6.283185307179586 / (double)cm.L);
+                                oy = 0.0;
+                            }
+                            const double fx = (double)rcx * ox - (double)rcy * oy, fy = (double)rcy * ox + (double)rcx * oy;
+                            const d3 td = d3{dd.x + cid * nsd.x, dd.y + cid * nsd.y, dd.z + cid * nsd.z};
+                            d3 xd;
+                            bool hx = false;
+                            if (m.kind == MAT_GRATING) {
+                                const double gn = (double)m.gx * nsd.x + (double)m.gy * nsd.y + (double)m.gz * nsd.z;
+                                const d3 t = d3{m.gx - gn * nsd.x, m.gy - gn * nsd.y, m.gz - gn * nsd.z};
+                                const double t2 = t.x * t.x + t.y * t.y + t.z * t.z;
+                                if (t2 > 1e-18) {
+                                    const double r = 1.0 / sqrt(t2);
+                                    xd = d3{t.x * r, t.y * r, t.z * r};
+                                    hx = true;
+                                }
+                            }
+                            if (!hx) {
+                                const double t2 = td.x * td.x + td.y * td.y + td.z * td.z;
+                                if (t2 > 1e-24) {
+                                    const double r = 1.0 / sqrt(t2);
+                                    xd = d3{td.x * r, td.y * r, td.z * r};
+                                } else {
+                                    xd = d3{(double)xa.x, (double)xa.y, (double)xa.z};
+                                }
+                            }
+                            const d3 yd = d3{nsd.y * xd.z - nsd.z * xd.y, nsd.z * xd.x - nsd.x * xd.z,
+                                             nsd.x * xd.y - nsd.y * xd.x};
+                            const double ik = 1.0 / (double)k;
+                            const d3 tn = d3{td.x + (fx * xd.x + fy * yd.x) * ik, td.y + (fx * xd.y + fy * yd.y) * ik,
+                                             td.z + (fx * xd.z + fy * yd.z) * ik};
+                            const double kn2 = 1.0 - (tn.x * tn.x + tn.y * tn.y + tn.z * tn.z);
+                            if (!(kn2 > 0.0)) {
+                                // evanescent in double although the float sampler kept it
+                                ev |= 1u << EV_EVANESCENT;
+                                finish = true;
+                            }
+                            const double kn = sqrt(fmax(0.0, kn2));
+                            const d3 nd = d3{tn.x + kn * nsd.x, tn.y + kn * nsd.y, tn.z + kn * nsd.z};
+                            const double r = 1.0 / sqrt(nd.x * nd.x + nd.y * nd.y + nd.z * nd.z);
+                            dd = d3{nd.x * r, nd.y * r, nd.z * r};
+                            if constexpr (ANISO) aniso_interact(ar, d, to_f3(dd), ns);
                             o = P;
-                            ++depth;
+                            if (!finish) ++depth;
                         }
                     }
                 }
@@ -673,6 +772,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         atomicAdd(A.stats + ST_TRIS, s9);
         atomicAdd(A.stats + ST_SUR, w_cnt[EV_SUR]);
         atomicAdd(A.stats + ST_FALLBACK, w_cnt[EV_FALLBACK]);
+        atomicAdd(A.stats + ST_COMPOSITE, w_cnt[EV_COMPOSITE]);
     }
 }
 
@@ -761,24 +861,27 @@ __global__ __launch_bounds__(256) void bsdf_eval_kernel(const float* __restrict_
                       r[12], r[13]);
 }
 
-template <bool DEFER, bool HERO, bool ANISO = false>
+template <bool DEFER, bool HERO, bool ANISO = false, bool COMPOSITE = false>
 static int grid_for(int device) {
     int ncu = 0, nb = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER, HERO, ANISO>, 256, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, trace_kernel<kLdsStack, DEFER, HERO, ANISO, COMPOSITE>, 256,
+                                                     0) != hipSuccess)
         return 0;
     return ncu * (nb > 0 ? nb : 1);
 }
 
-int trace_grid_size(int device, bool sur, bool hero, bool aniso) {
+int trace_grid_size(int device, bool sur, bool hero, bool aniso, bool composite) {
+    if (composite) return grid_for<false, false, false, true>(device);
     if (aniso) return grid_for<false, false, true>(device);
     if (hero) return grid_for<false, true>(device);
     return sur ? grid_for<true, false>(device) : grid_for<false, false>(device);
 }
 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.aniso) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, true>), dim3(grid), dim3(256), 0, s, a);
+    if (a.composite)
+        hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (a.aniso) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.hero) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.bsdf_mode != 0) hipLaunchKernelGGL((trace_kernel<kLdsStack, true, false>), dim3(grid), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false>), dim3(grid), dim3(256), 0, s, a);
@@ -836,6 +939,31 @@ hipError_t launch_reduce(const float* records, float* image, int64_t spp_count, 
     const uint32_t per = H * W * nl;
     hipLaunchKernelGGL(reduce_kernel, dim3((per + 255) / 256), dim3(256), 0, s, records, image, spp_count,
                        H, W, nl);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void composite_eval_kernel(const float* __restrict__ q, int64_t n,
+                                                             float* __restrict__ out, const BoundaryDev B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* r = q + i * 23;
+    DMat mn, mf;
+    mn.kind = (int)r[0];
+    mn.h = r[1];
+    mn.L = r[2];
+    mn.refl = r[3];
+    mf.kind = (int)r[6];
+    mf.h = r[7];
+    mf.L = r[8];
+    mf.refl = r[9];
+    mn.gx = mn.gy = mn.gz = mn.pad = mf.gx = mf.gy = mf.gz = mf.pad = 0.0f;
+    const HalfPlane H = make_halfplane(r[17], r[18], r[19], r[20], r[21], r[22]);
+    out[i] = pw_composite(mn, r[4], r[5], mf, r[10], r[11], r[12], r[13], r[14], r[15], r[16], H, B);
+}
+
+hipError_t launch_composite_eval(const float* q, int64_t n, float* out, const BoundaryDev& b, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(composite_eval_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, n, out, b);
     return hipGetLastError();
 }
 

@@ -46,11 +46,12 @@ __device__ __forceinline__ float scene_entry(const SceneDev& S, d3 o, f3 d) {
 }
 
 // Hit distance and barycentric weights of the triangle the float test found, recomputed in
-// double precision (Moller-Trumbore on the float vertices): the position the path continues
-// from then carries no error of the float ray-space arithmetic.  Keeps the float values when
-// the double test degenerates.
-__device__ __forceinline__ void refine_hit(d3 o, f3 d, float4 a, float4 b, float4 c, float& t,
-                                           float& bu, float& bv, double& t64) {
+// double precision (Moller-Trumbore on the float vertices, along the path's double direction):
+// the position the path continues from, and the shading normal interpolated there, then carry
+// no error of the float ray-space arithmetic.  Keeps the float test's values (bu, bv on entry)
+// when the double test degenerates.
+__device__ __forceinline__ void refine_hit(d3 o, d3 d, float4 a, float4 b, float4 c, float& t,
+                                           double& bu, double& bv, double& t64) {
     t64 = (double)t;
     const double e1x = (double)b.x - a.x, e1y = (double)b.y - a.y, e1z = (double)b.z - a.z;
     const double e2x = (double)c.x - a.x, e2y = (double)c.y - a.y, e2z = (double)c.z - a.z;
@@ -67,8 +68,8 @@ __device__ __forceinline__ void refine_hit(d3 o, f3 d, float4 a, float4 b, float
     if (!(tt > 0.0)) return;
     t64 = tt;
     t = (float)tt;
-    bu = fminf(fmaxf((float)u, 0.0f), 1.0f);
-    bv = fminf(fmaxf((float)v, 0.0f), 1.0f);
+    bu = fmin(fmax(u, 0.0), 1.0);
+    bv = fmin(fmax(v, 0.0), 1.0);
 }
 
 struct RayT {
@@ -321,7 +322,7 @@ __device__ __forceinline__ unsigned long long wave_sum(uint32_t v) {
     return x;
 }
 
-enum { EV_PATH = 0, EV_SEG, EV_SHADOW, EV_SUR, EV_FALLBACK, EV_EVANESCENT, EV_BACKFACING, EV_NONFINITE, EV_COUNT };
+enum { EV_PATH = 0, EV_SEG, EV_SHADOW, EV_SUR, EV_FALLBACK, EV_EVANESCENT, EV_BACKFACING, EV_NONFINITE, EV_COMPOSITE, EV_COUNT };
 
 // bfloat16 pair (a in the low half), rounded to nearest even as the network's input stage does.
 __device__ __forceinline__ uint32_t bf16_pair(float a, float b) {

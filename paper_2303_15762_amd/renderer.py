@@ -121,6 +121,13 @@ class Renderer:
         arr = (L.GrSource * max(1, len(sources)))(*[source_struct(s) for s in sources])
         self._check(self.lib.gr_set_sources(self.h, arr, len(sources)), "gr_set_sources")
 
+    def boundaries(self, reach_m=2e-3):
+        """Find the uploaded scene's material boundaries (gr_scene_boundaries) for composite
+        interactions; returns the number of boundary edges."""
+        n = C.c_int64(0)
+        self._check(self.lib.gr_scene_boundaries(self.h, float(reach_m), C.byref(n)), "gr_scene_boundaries")
+        return int(n.value)
+
     def load_workload(self, wl):
         info = self.upload_scene(wl.scene)
         self.set_sensor(wl.sensor)
@@ -130,7 +137,7 @@ class Renderer:
     # -- trace -----------------------------------------------------------------------------
     def opts(self, spp_begin=0, spp_count=1, spp_norm=None, max_depth=1, bsdf_mode=0,
              rr_enable=False, rr_p=0.8, seed=0, keep_paths=False,
-             short_lds_stack=False, hero=False, aniso=False) -> L.GrTraceOpts:
+             short_lds_stack=False, hero=False, aniso=False, composite=False) -> L.GrTraceOpts:
         o = L.GrTraceOpts()
         o.spp_begin = int(spp_begin)
         o.spp_count = int(spp_count)
@@ -142,7 +149,8 @@ class Renderer:
         o.seed = int(seed)
         o.flags = (L.GR_TRACE_KEEP_PATHS if keep_paths else 0) | \
             (L.GR_TRACE_SHORT_LDS_STACK if short_lds_stack else 0) | \
-            (L.GR_TRACE_HERO if hero else 0) | (L.GR_TRACE_ANISO if aniso else 0)
+            (L.GR_TRACE_HERO if hero else 0) | (L.GR_TRACE_ANISO if aniso else 0) | \
+            (L.GR_TRACE_COMPOSITE if composite else 0)
         return o
 
     def workspace(self, opts: L.GrTraceOpts, n_lambda: int):
@@ -191,11 +199,12 @@ class Renderer:
             opts.spp_count, self.sensor.height, self.sensor.width, n_lambda)
 
     def render_workload(self, wl, spp_begin=0, spp_count=None, bsdf_mode=0, stats=True,
-                        keep_paths=False, hero=False, aniso=False):
+                        keep_paths=False, hero=False, aniso=False, composite=False):
         spp_count = wl.spp if spp_count is None else spp_count
         o = self.opts(spp_begin=spp_begin, spp_count=spp_count, spp_norm=wl.spp,
                       max_depth=wl.max_depth, bsdf_mode=bsdf_mode, rr_enable=wl.rr_enable,
-                      rr_p=wl.rr_p, seed=wl.seed, keep_paths=keep_paths, hero=hero, aniso=aniso)
+                      rr_p=wl.rr_p, seed=wl.seed, keep_paths=keep_paths, hero=hero, aniso=aniso,
+                      composite=composite)
         return self.trace(wl.lambdas_um, o, stats=stats)
 
     # -- scattering kernels ---------------------------------------------------------------
@@ -205,6 +214,14 @@ class Renderer:
         out = self.torch.empty(q.shape[0], dtype=self.torch.float32, device=self.dev)
         self._check(self.lib.gr_bsdf_eval(self.h, _fptr(q), q.shape[0], int(mode), _fptr(out)),
                     "gr_bsdf_eval")
+        return out
+
+    def pw_composite_eval(self, queries):
+        """queries: float32 device tensor [n, 23] (see gr_pw_composite_eval); returns [n]."""
+        q = queries.contiguous()
+        out = self.torch.empty(q.shape[0], dtype=self.torch.float32, device=self.dev)
+        self._check(self.lib.gr_pw_composite_eval(self.h, _fptr(q), q.shape[0], _fptr(out)),
+                    "gr_pw_composite_eval")
         return out
 
     # -- coherent measurement -------------------------------------------------------------

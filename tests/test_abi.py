@@ -35,7 +35,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(L.GrSensor) == 64
     assert C.sizeof(L.GrSource) == 60
     assert C.sizeof(L.GrTraceOpts) == 56
-    assert C.sizeof(L.GrStats) == 88
+    assert C.sizeof(L.GrStats) == 96
     assert C.sizeof(L.GrSceneInfo) == 40
 
 
@@ -90,7 +90,7 @@ def test_trace_rejects_before_device_use(ctx):
     o.bsdf_mode = 0
     assert lib.gr_trace(h, bad, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
     # flags: unknown bits, and hero-wavelength paths or anisotropic rays outside what they support
-    for bad_flag in (4, 32):
+    for bad_flag in (4, 64):
         o.flags = bad_flag
         assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -1
     for mode in (1, 2):
@@ -112,6 +112,20 @@ def test_trace_rejects_before_device_use(ctx):
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
     o.flags = L.GR_TRACE_HERO | L.GR_TRACE_ANISO
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
+    # composite interactions: scalar one-wavelength rays with the closed form only, and only
+    # after gr_scene_boundaries
+    for flags, mode in ((L.GR_TRACE_COMPOSITE | L.GR_TRACE_HERO, 0), (L.GR_TRACE_COMPOSITE | L.GR_TRACE_ANISO, 0),
+                        (L.GR_TRACE_COMPOSITE, 1)):
+        o.flags, o.bsdf_mode = flags, mode
+        assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
+        assert b"composite" in lib.gr_last_error(h)
+    o.flags, o.bsdf_mode = L.GR_TRACE_COMPOSITE, 0
+    assert lib.gr_trace(h, lam, 1, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
+    n = C.c_int64(0)
+    assert lib.gr_scene_boundaries(h, 2e-3, C.byref(n)) == -2
+    assert lib.gr_scene_boundaries(h, 0.0, C.byref(n)) == -1
+    assert lib.gr_scene_boundaries(h, 2.0, C.byref(n)) == -1
+    assert lib.gr_pw_composite_eval(h, None, 4, None) == -1
 
 
 def test_scene_validation(ctx):

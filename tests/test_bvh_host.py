@@ -62,3 +62,44 @@ def test_bvh_structure_and_traversal(checker, case):
     assert rc == 0 and out.startswith("OK"), out
     depth, max_sp, nodes = map(int, out.split()[1:])
     assert max_sp <= 3 * (depth + 1) + 1
+
+
+# --------------------------------------------------------------------------------------
+# Material-boundary lists of composite interactions (host code of libgrwave)
+# --------------------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def bchecker():
+    exe = "/tmp/grwave_boundary_check"
+    srcs = [os.path.join(ROOT, "tests", "boundary_check.cpp"),
+            os.path.join(ROOT, "paper_2303_15762_amd", "csrc", "boundary.cpp")]
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-o", exe] + srcs)
+    return exe
+
+
+@pytest.mark.parametrize("case", ["terrain", "instances", "split"])
+@pytest.mark.parametrize("reach", [2e-3, 0.3e-3])
+def test_boundary_lists_complete(bchecker, case, reach):
+    """Every boundary edge of a hit's material within the reach is in its triangle's list, so
+    the nearest found through the list is the nearest of all (brute force over every edge)."""
+    if case == "terrain":
+        sc = W.terrain_scene()
+    elif case == "instances":
+        sc = W.large_scene(n_inst_x=2, n_inst_y=1, n_boxes=50, seed=4, tile_nx=64, tile_ny=32)
+    else:
+        sc = W.split_mirror().scene
+    verts, tris, mats = sc.verts.astype(np.float32), sc.tris, sc.tri_mat
+    rng = np.random.default_rng(5)
+    ts = rng.integers(0, len(tris), 3000)
+    bc = rng.dirichlet([1, 1, 1], 3000)
+    lines = [f"{len(verts)} {len(tris)} {reach:.9g}"]
+    lines += [" ".join(f"{v:.9g}" for v in p) for p in verts]
+    lines += [f"{a} {b} {c} {m}" for (a, b, c), m in zip(tris, mats)]
+    lines.append(str(len(ts)))
+    lines += [f"{t} {u:.17g} {w:.17g}" for t, (_, u, w) in zip(ts, bc)]
+    r = subprocess.run([bchecker], input="\n".join(lines), capture_output=True, text=True)
+    out = r.stdout.strip()
+    assert r.returncode == 0 and out.startswith("OK"), out
+    n_edges, found, entries = map(int, out.split()[1:])
+    print(case, reach, "edges", n_edges, "queries with a boundary", found, "list entries", entries)
+    assert n_edges > 0 and found > 0

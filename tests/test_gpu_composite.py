@@ -1,0 +1,252 @@
+"""GPU parity of composite interactions at material boundaries (GR_TRACE_COMPOSITE) against
+the FP64 oracle, through the C ABI.
+
+Tolerances: the composite p_w element by element within 2e-4 relative (plus 1e-6 of the
+window's peak density where the value sits far out in the boundary's diffraction streak: the
+FP32 Faddeeva approximation is good to 6e-7, the FP32 Bessel and Poisson series to ~1e-5);
+images within the plain path's 1e-3 relative L2.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import scenes as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2303_15762_amd import Renderer
+    r = Renderer(0)
+    yield r
+    r.close()
+
+
+def _material(rng, kind):
+    if kind == 0:
+        return [0, 0.0, 1.0, rng.uniform(0.3, 1.0)]
+    if kind == 1:
+        return [1, rng.uniform(0.05, 0.5), rng.uniform(0.5, 5.0), rng.uniform(0.5, 1.0)]
+    return [2, rng.uniform(0.025, 0.15), rng.uniform(0.8, 4.0), rng.uniform(0.5, 1.0)]
+
+
+def composite_queries(n, seed):
+    """Rows of gr_pw_composite_eval over every pair of material kinds, footprints from 3 to
+    200 um, boundaries from on the hit to 2.5 beta away, outgoing wavevectors near the lobes
+    and out along the boundary's streak."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    while len(rows) < n:
+        kn, kf = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        near, far = _material(rng, kn), _material(rng, kf)
+        gn = [1.0, 0.0]
+        a = rng.uniform(0, 2 * math.pi)
+        gf = [math.cos(a), math.sin(a)]
+        lam = rng.uniform(0.4, 0.7)
+        k = 2 * math.pi / lam
+        th, ph = rng.uniform(0, 1.1), rng.uniform(0, 2 * math.pi)
+        ki = [k * math.sin(th) * math.cos(ph), k * math.sin(th) * math.sin(ph)]
+        sx, sy = np.exp(rng.uniform(math.log(3), math.log(200), 2))
+        rho = rng.uniform(-0.7, 0.7)
+        S = [sx * sx, sy * sy, rho * sx * sy]
+        b = rng.uniform(0, 2 * math.pi)
+        nrm = [math.cos(b), math.sin(b)]
+        snn = nrm[0] ** 2 * S[0] + 2 * nrm[0] * nrm[1] * S[2] + nrm[1] ** 2 * S[1]
+        c = rng.uniform(0, 2.5 * math.sqrt(2 * max(S[0], S[1])))
+        c = min(c, 4.0 * math.sqrt(snn))
+        # outgoing: specular / a grating order of either side, plus a spread, or out along n
+        sel = rng.integers(0, 3)
+        if sel == 0:
+            d = rng.normal(0, 1.0, 2) / math.sqrt(min(S[0], S[1]))
+        elif sel == 1:
+            d = rng.normal(0, 1.0) * 5.0 / math.sqrt(snn) * np.asarray(nrm) + rng.normal(0, 0.3, 2) / math.sqrt(snn)
+        else:
+            d = rng.normal(0, 1.0, 2) * 0.5
+        # the specular lobe sits at k_o,t = k_i,t, order j of a grating at k_i,t - j K g
+        j = int(rng.integers(-2, 3))
+        K = 2 * math.pi / far[2] if kf == 2 else 0.0
+        ko = [ki[0] + d[0] - j * K * gf[0] * (sel == 2), ki[1] + d[1] - j * K * gf[1] * (sel == 2)]
+        if ko[0] ** 2 + ko[1] ** 2 >= 0.98 * k * k:
+            continue
+        rows.append(near + gn + far + gf + [k] + ki + ko + S + nrm + [c])
+    return np.array(rows)
+
+
+def test_pw_composite_matches_oracle(R):
+    import torch
+    q = composite_queries(3000, 21).astype(np.float32).astype(np.float64)
+    ref = oracle.pw_composite_batch(q)
+    got = R.pw_composite_eval(torch.tensor(q, dtype=torch.float32, device=R.dev)).cpu().numpy().astype(np.float64)
+    S = q[:, 17:20]
+    peak = 2.0 * np.sqrt(S[:, 0] * S[:, 1] - S[:, 2] ** 2) / math.pi
+    err = np.abs(got - ref)
+    rel = err / np.maximum(ref, 1e-300)
+    big = ref > 1e-3 * peak
+    kinds = q[:, 0].astype(int) * 3 + q[:, 6].astype(int)
+    for kk in range(9):
+        m = big & (kinds == kk)
+        if m.any():
+            print("near/far kinds", kk // 3, kk % 3, "n", m.sum(), "max rel", rel[m].max(), "median", np.median(rel[m]))
+    print("max |err| / peak", (err / peak).max())
+    assert np.all(err <= 2e-4 * ref + 1e-6 * peak)
+
+
+def test_split_mirror_paths_match_oracle(R):
+    """Two smooth mirrors at a straight boundary, normal incidence: per-path records against
+    the oracle (which is pinned by the closed form of the same scene)."""
+    wl = W.split_mirror(width=64, height=2, spp=4)
+    R.load_workload(wl)
+    n = R.boundaries(2e-3)
+    assert n == 1
+    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=1, seed=wl.seed, keep_paths=True, composite=True)
+    _, st = R.trace(wl.lambdas_um, opts)
+    rec = R.path_records(opts, 1).cpu().numpy().astype(np.float64)
+    img, ost, paths = oracle.render(wl, composite=True, reach_m=2e-3, keep_paths=True)
+    print("split mirror: composite", st["composite"], ost["composite"])
+    assert st["composite"] == ost["composite"] > 0
+    np.testing.assert_allclose(rec.reshape(wl.spp, -1, 1), paths, rtol=2e-5, atol=0)
+
+
+@pytest.mark.parametrize("right", ["grating", "rough"])
+def test_split_mirror_other_materials(R, right):
+    """The split mirror with a grating or a rough right half (several wavelengths): image
+    against the oracle."""
+    mat = (W.Material(W.GRATING, height_um=0.08, length_um=2.0, gdir=(0.6, 0.8, 0.0), reflectance=0.9)
+           if right == "grating" else W.Material(W.ROUGH, height_um=0.05, length_um=2.0, reflectance=0.8))
+    wl = W.split_mirror(width=96, height=8, spp=8, right=mat, n_lambda=4, pitch=8e-6)
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    img, st = R.render_workload(wl, composite=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, composite=True, reach_m=2e-3)
+    e = rel_l2(g, o)
+    print(right, "rel L2", e, st["composite"], ost["composite"])
+    assert st["composite"] == ost["composite"]
+    assert e <= 1e-4
+
+
+def _terrain_window(x0, y0, w=48, h=40, spp=16):
+    return W.as_float32_inputs(W.mid_terrain(window=(x0, y0, w, h), spp=spp))
+
+
+def _explain(R, wl, g, o, reach):
+    """Where an image differs: the pixels carrying the squared error, the plain path's own
+    error on the same input, and the paths that differ most."""
+    d2 = ((g - o) ** 2).sum(0)
+    order = np.argsort(d2.ravel())[::-1][:5]
+    tot = d2.sum()
+    for i in order:
+        y, x = divmod(int(i), g.shape[2])
+        print("  pixel", (x, y), "share of squared error %.3f" % (d2.ravel()[i] / tot),
+              "gpu", g[:, y, x].sum(), "oracle", o[:, y, x].sum())
+    gp, _ = R.render_workload(wl)
+    op, _ = oracle.render(wl)
+    print("  plain path on the same input: rel L2", rel_l2(gp.cpu().numpy(), op))
+    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed, keep_paths=True,
+                  composite=True, rr_enable=wl.rr_enable, rr_p=wl.rr_p)
+    R.trace(wl.lambdas_um, opts)
+    rec = R.path_records(opts, len(wl.lambdas_um)).cpu().numpy().astype(np.float64)   # [s, H, W, nl]
+    _, _, paths = oracle.render(wl, composite=True, reach_m=reach, keep_paths=True)   # [s, npix, nl]
+    dif = np.abs(rec.reshape(paths.shape) - paths)
+    for i in np.argsort(dif.ravel())[::-1][:8]:
+        s_, p_, w_ = np.unravel_index(i, paths.shape)
+        y, x = divmod(int(p_), wl.sensor.width)
+        print("  path s=%d x=%d y=%d w=%d gpu %.6e oracle %.6e" % (s_, x, y, w_, rec.reshape(paths.shape)[s_, p_, w_],
+                                                                  paths[s_, p_, w_]))
+
+
+@pytest.mark.parametrize("reach", [2e-3, 0.3e-3])
+def test_terrain_window_matches_oracle(R, reach):
+    """A full-resolution window of the mid terrain over tile boundaries (16 samples, 8
+    wavelengths, depth 4, one partially coherent emitter)."""
+    wl = _terrain_window(230, 230)
+    R.load_workload(wl)
+    R.boundaries(reach)
+    img, st = R.render_workload(wl, composite=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, composite=True, reach_m=reach)
+    e = rel_l2(g, o)
+    print("terrain window: rel L2", e, "composite", st["composite"], ost["composite"], "segments",
+          st["segments"], ost["segments"])
+    _explain(R, wl, g, o, reach)
+    assert ost["composite"] > 1000
+    assert abs(st["composite"] - ost["composite"]) <= 1e-3 * ost["composite"] + 2
+    assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    assert e <= 1e-3
+    # the composite operator changes the image (edge diffraction, mixed continuations)
+    p, _ = oracle.render(wl)
+    print("composite vs single-material oracle images: rel L2", rel_l2(o, p))
+
+
+def test_terrain_rr_two_sources_depth6(R):
+    """Russian roulette, a second emitter and depth 6 with composite interactions."""
+    wl = _terrain_window(100, 300, w=40, h=32, spp=8)
+    wl.rr_enable = True
+    wl.max_depth = 6
+    wl.sources = wl.sources + [W.Source(W.PLANE_WAVE, dir=np.array([0.3, 0.2, -math.sqrt(1 - 0.13)]), power=0.5)]
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    img, st = R.render_workload(wl, composite=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, composite=True, reach_m=2e-3)
+    e = rel_l2(g, o)
+    print("rr/two sources/depth 6: rel L2", e, st["composite"], ost["composite"])
+    assert e <= 1e-3
+
+
+def test_terrain_low_resolution_wide_footprints(R):
+    """41 x 29 pixels over the whole terrain: footprints of ~1 mm, every boundary within the
+    2 mm reach."""
+    wl = W.as_float32_inputs(W.mid_terrain(width=41, height=29, spp=8, n_lambda=4))
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    img, st = R.render_workload(wl, composite=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, composite=True, reach_m=2e-3)
+    e = rel_l2(g, o)
+    print("terrain 41x29 composite: rel L2", e, st["composite"], ost["composite"])
+    assert e <= 1e-3
+
+
+def test_terrain_full_size_sampled_pixels(R):
+    """The mid workload at full size with composite interactions, in the configuration the
+    benchmark times; 500 pixels computed one by one by the oracle."""
+    wl = W.as_float32_inputs(W.mid_terrain())
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    img, st = R.render_workload(wl, composite=True)
+    g = img.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(4)
+    lit = np.argwhere(g.sum(0) > 0)
+    pick = np.concatenate([lit[rng.choice(len(lit), size=min(350, len(lit)), replace=False)],
+                           np.stack([rng.integers(0, 512, 150), rng.integers(0, 512, 150)], 1)])
+    pix = np.stack([pick[:, 1], pick[:, 0]], 1)
+    o, _ = oracle.render(wl, pixels=pix, composite=True, reach_m=2e-3)
+    gs = g[:, pick[:, 0], pick[:, 1]]
+    e = rel_l2(gs, o)
+    print("full size composite: sampled rel L2", e, "composite interactions", st["composite"])
+    assert st["composite"] > 1e6
+    assert e <= 1e-3
+
+
+def test_boundaries_replace_and_count(R):
+    """Boundary edges of the mid terrain: the same count as the oracle's mesh search; a second
+    call replaces the first."""
+    wl = W.mid_terrain(width=16, height=16, spp=1)
+    R.load_workload(wl)
+    n1 = R.boundaries(2e-3)
+    n2 = R.boundaries(0.5e-3)
+    osc = oracle.OracleScene(wl.scene)
+    assert n1 == n2 == osc.boundaries()

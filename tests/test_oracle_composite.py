@@ -309,8 +309,9 @@ def test_boundary_edges_and_nearest_match_brute_force():
     key_ref = {tuple(np.round(np.sort(np.stack([v[a], v[b]]), 0).ravel(), 12)) for a, b in edges}
     assert key_got == key_ref
     rng = np.random.default_rng(2)
-    reach = 1.5e-3
-    for _ in range(6):
+    # within the grid's cell (2 mm, the default) the search goes through the grid, beyond it
+    # over all of the material's edges
+    for reach in [1.5e-3, 3e-3] * 3:
         mat = int(rng.integers(0, len(scene.materials)))
         tri_of = np.nonzero(scene.tri_mat == mat)[0]
         ts = rng.choice(tri_of, 40)
