@@ -288,6 +288,46 @@ def aniso_leg(R, wl, ms_plain, img_plain, steps):
             "frame_time_vs_scalar_rays": round(ms / ms_plain, 3), "rel_l2_vs_scalar_ray_image": diff}
 
 
+def composite_leg(R, wl, ms_plain, img_plain, steps, threads, no_cpu, reach_m=2e-3, step=32):
+    """Composite interactions at material boundaries (GR_TRACE_COMPOSITE) on the same frame:
+    the boundary search on the host, the frame time and rate, the share of interactions that
+    met a boundary, the image change against single-material interactions, and the image error
+    against the FP64 oracle on every 32nd row and column (its composite p_w is ~40x slower per
+    interaction than its closed form, so a sparser subset than the plain leg's)."""
+    import torch
+    t0 = time.perf_counter()
+    n_edges = R.boundaries(reach_m)
+    build_s = time.perf_counter() - t0
+    o = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,
+               rr_enable=wl.rr_enable, rr_p=wl.rr_p, composite=True)
+    img = torch.zeros((len(wl.lambdas_um), wl.sensor.height, wl.sensor.width), device=R.dev)
+    _, st = R.trace(wl.lambdas_um, o, image=img, stats=True)
+    diff = float(torch.linalg.vector_norm((img - img_plain).double()) /
+                 torch.linalg.vector_norm(img_plain.double()))
+    out = {"reach_m": reach_m, "boundary_edges": n_edges, "boundary_build_s": round(build_s, 2),
+           "composite_per_segment": round(st["composite"] / st["segments"], 4),
+           "rel_l2_vs_single_material_image": diff}
+    ms = time_frames(R, wl, o, img, steps)
+    out.update({"value": round(st["segments"] / (ms * 1e-3) / 1e6, 2), "unit": "Mpath-segments/s",
+                "ms_per_step": round(ms, 3), "steps": steps, "segments_per_step": st["segments"],
+                "frame_time_vs_plain": round(ms / ms_plain, 3)})
+    if not no_cpu:
+        import oracle
+        pix = subset_pixels(wl, step)
+        osc = oracle.OracleScene(wl.scene)
+        t0 = time.perf_counter()
+        ref, ost = oracle.render(wl, osc, pixels=pix, n_threads=threads, composite=True, reach_m=reach_m)
+        dt = time.perf_counter() - t0
+        img.zero_()
+        R.trace(wl.lambdas_um, o, image=img, stats=False)
+        err = rel_l2_on(img, pix, ref)
+        out.update({"rel_l2_vs_oracle": err, "qualifies": err <= 1e-3,
+                    "rel_l2_pixels": f"{len(pix)} pixels: every {step}th row and column",
+                    "worst_pixel": worst_pixel(img, pix, ref),
+                    "oracle_mpath_segments_per_s": round(ost["segments"] / dt / 1e6, 3)})
+    return out
+
+
 # Coherent measurement: vector operations of one (sample, slit node) evaluation in the FP64
 # mode, the way the kernel writes them: distance (1 FMA + a square root of ~6), phase (1),
 # amplitude (4 multiplies, a division of ~8, a square root of ~6), sincos with its range
@@ -391,6 +431,8 @@ def main():
                     help="skip the learned-p_w legs (training takes a few seconds)")
     ap.add_argument("--no-hero", dest="hero", action="store_false", help="skip the hero-wavelength leg")
     ap.add_argument("--no-aniso", dest="aniso", action="store_false", help="skip the anisotropic-ray leg")
+    ap.add_argument("--no-composite", dest="composite", action="store_false",
+                    help="skip the composite-interaction leg")
     ap.add_argument("--no-coherent", dest="coherent", action="store_false",
                     help="skip the coherent-measurement leg")
     ap.add_argument("--no-mid", dest="mid", action="store_false",
@@ -471,6 +513,8 @@ def main():
         out["hero"] = hero_leg(R, wl, ms_step, leg_steps)
     if args.aniso:
         out["aniso"] = aniso_leg(R, wl, ms_step, img, leg_steps)
+    if args.composite:
+        out["composite"] = composite_leg(R, wl, ms_step, img, leg_steps, threads, args.no_cpu)
     if args.coherent:
         out["coherent"] = coherent_leg(R, leg_steps)
     if not args.no_cpu:
@@ -483,13 +527,16 @@ def main():
         _, img_m, st_m, ms_m, k_ms_m = plain_frame(R, wm, 1, args.steps)
         err_m = rel_l2_on(img_m, pm, ref_m) if ref_m is not None else None
         save_subset(args, "mid", img_m, pm, ref_m)
+        comp_m = None
+        if args.composite:
+            comp_m = composite_leg(R, wm, ms_m, img_m, args.steps, threads, args.no_cpu, step=8)
         out["mid"] = {"workload": WORKLOAD_NAMES["mid"], "value": round(st_m["segments"] / (ms_m * 1e-3) / 1e6, 2),
                       "unit": "Mpath-segments/s", "ms_per_step": round(ms_m, 3), "steps": args.steps,
                       "segments_per_step": st_m["segments"], "bvh_nodes": info_m["n_nodes"],
                       "rel_l2_vs_oracle": err_m, "qualifies": (err_m is not None and err_m <= 1e-3),
                       "rel_l2_pixels": f"{len(pm)} pixels: every 8th row and column",
                       "worst_pixel": worst_pixel(img_m, pm, ref_m) if ref_m is not None else None,
-                      "roofline": roofline_of(st_m, k_ms_m, "mid")}
+                      "roofline": roofline_of(st_m, k_ms_m, "mid"), "composite": comp_m}
     print(json.dumps(out), flush=True)
     R.close()
 

@@ -413,7 +413,7 @@ double pw_composite(const Side& nr, const Side& fr, double k, double kix, double
             mean[s] = 0.0;
             for (int j = -J; j <= J; ++j) {
                 const double bj = besselj(j, mm);
-                if (bj == 0.0) continue;
+                if (j != 0 && bj * bj < 1e-32) continue;   // orders weighing below 1e-32
                 const std::complex<double> h = H(kx + j * K * sd[s]->gx, ky + j * K * sd[s]->gy);
                 total += m.refl * bj * bj * std::norm(h);
                 if (j == 0) mean[s] = std::sqrt(m.refl) * bj * h;
