@@ -232,12 +232,13 @@ int gr_set_sensor(gr_ctx* ctx, const gr_sensor* sensor);
 int gr_set_sources(gr_ctx* ctx, const gr_source* sources, int32_t n);
 
 /* Workspace (device memory) needed by gr_trace for these options and n_lambda wavelengths:
- * a header, one float per path, the traversal-stack overflow of the uploaded scene's BVH
- * (one region per persistent lane, 3 entries per BVH level beyond the LDS part), and for one
- * launch of the persistent kernel with one wavelength per path its queued shadow rays (48 B),
- * measurement slots (4 B) and, with a learned p_w, network queries (32 B) per (path,
- * interaction), plus one byte per path (at most 52 GiB of these per launch).  Call it after
- * gr_scene_upload: the size depends on the scene and the device. */
+ * a header, one float per (sample, pixel, wavelength) record, the traversal-stack overflow of
+ * the uploaded scene's BVH (one region per persistent lane, 3 entries per BVH level beyond the
+ * LDS part), and for one launch of the persistent kernel its queued shadow rays (48 B),
+ * measurement slots (4 B, or 16 B with hero wavelengths: one float per member) and, with a
+ * learned p_w, network queries (32 B) per (path, interaction), plus one byte per path (at most
+ * 52 GiB of these per launch).  Call it after gr_scene_upload: the size depends on the scene
+ * and the device. */
 int gr_workspace_size(const gr_ctx* ctx, const gr_trace_opts* opts, int32_t n_lambda,
                       size_t* bytes);
 /* Device pointer (inside `workspace`) of the per-path contributions kept by
@@ -251,10 +252,10 @@ int gr_workspace_paths(const gr_ctx* ctx, void* workspace, float** paths_dev);
  *   workspace : device, >= gr_workspace_size bytes.
  *   image     : device float [n_lambda][height][width]; contributions are ADDED to it.
  *   stats     : optional; when given the call synchronises the stream and fills it.
- * One wavelength per path (the persistent kernel): the path kernel stores each measurement
- * value in its (path, interaction) slot and queues the measurement's shadow ray (48 B); a
- * shadow-ray kernel traces the queue in full waves and clears the slots of occluded ones, and
- * a merge sums each path's slots in depth order into its record.  Surrogate modes also queue
+ * The path kernel stores each measurement value in its (path, interaction) slot (the four
+ * members' values for hero-wavelength paths) and queues the measurement's shadow ray (48 B);
+ * a shadow-ray kernel traces the queue in full waves and clears the slots of occluded ones,
+ * and a merge sums each path's slots in depth order into its record(s).  Surrogate modes also queue
  * in-domain rough-surface measurements (32 B each) for one batched matrix-core pass, which
  * writes their slots before the shadow rays are traced.  Launches hold at most 256M paths and
  * 2^30 slots within 52 GiB of queues and slots (the workspace holds one launch's).

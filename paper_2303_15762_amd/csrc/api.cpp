@@ -137,8 +137,10 @@ struct WsLayout {
 bool hero_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_HERO) != 0; }
 bool composite_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_COMPOSITE) != 0; }
 bool aniso_of(const gr_trace_opts* o) { return (o->flags & GR_TRACE_ANISO) != 0; }
-// one wavelength per path in the persistent kernel: shadow rays go through a queue of their own
-bool shadow_queue_of(const gr_trace_opts* o) { return !hero_of(o); }
+// shadow rays go through a queue of their own (hero-wavelength paths store four member values
+// per slot)
+bool shadow_queue_of(const gr_trace_opts*) { return true; }
+uint64_t slot_values(const gr_trace_opts* o) { return hero_of(o) ? 4 : 1; }
 
 // Traversal-stack entries per lane that do not fit the LDS part.
 uint32_t overflow_entries(const gr_ctx* c, const gr_trace_opts* o) {
@@ -383,6 +385,7 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     WsLayout L;
     const uint64_t per = (uint64_t)c->sensor.width * (uint64_t)c->sensor.height * (uint64_t)nl;
     const uint64_t n = per * (uint64_t)std::max<int64_t>(o->spp_count, 0);
+    const uint64_t n_paths = hero_of(o) ? n / 4 : n;   // records per path: 4 for hero paths
     const size_t lanes =
         (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso, c->grid_comp}) * 256;
     L.records = kWsHeader;
@@ -391,14 +394,15 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     const bool defer = o->bsdf_mode != GR_BSDF_PLAIN, shq = shadow_queue_of(o);
     // bytes per (path, interaction) slot: a network query, a shadow ray, the result float (and
     // one byte per path: its stored slot count)
-    const uint64_t slot_bytes = (defer ? grw::kSurQueryBytes : 0) + (shq ? grw::kShadowQueryBytes : 0) + 4;
+    const uint64_t slot_bytes =
+        (defer ? grw::kSurQueryBytes : 0) + (shq ? grw::kShadowQueryBytes : 0) + 4 * slot_values(o);
     const uint64_t slots_max = std::min<uint64_t>(kSurSlots, kQueueBytes / slot_bytes);
     const uint64_t sur_chunk = std::min<uint64_t>(kSurChunk, slots_max / (uint64_t)std::max(o->max_depth, 1));
-    L.chunk = std::min<uint64_t>(n, sur_chunk);
+    L.chunk = std::min<uint64_t>(n_paths, sur_chunk);
     const uint64_t slots = L.chunk * (uint64_t)std::max(o->max_depth, 1);
     L.shadow = L.queue + (defer ? align256((size_t)slots * grw::kSurQueryBytes) : 0);
     L.dense = L.shadow + (shq ? align256((size_t)slots * grw::kShadowQueryBytes) : 0);
-    L.nd = L.dense + (defer || shq ? align256((size_t)slots * sizeof(float)) : 0);
+    L.nd = L.dense + (defer || shq ? align256((size_t)slots * sizeof(float) * slot_values(o)) : 0);
     L.total = L.nd + (shq ? align256((size_t)L.chunk) : 0);
     return L;
 }
@@ -608,13 +612,14 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
             if (defer)
                 GR_HIP(c, grw::launch_sur_batch(c->sur, fp8, a.sq, a.sq_count, dense, a.stats, c->grid_batch, c->stream));
             GR_HIP(c, grw::launch_shadow(a, grid, c->stream));
-            GR_HIP(c, grw::launch_shadow_merge(dense, a.snd, D, a.records, p0, pn, a.inv_spp_norm, a.stats, c->stream));
+            if (a.hero)
+                GR_HIP(c, grw::launch_hero_merge(dense, a.snd, D, a.records, p0, pn, (uint32_t)(nl / 4), (uint32_t)nl,
+                                                 a.inv_spp_norm, a.stats, c->stream));
+            else
+                GR_HIP(c, grw::launch_shadow_merge(dense, a.snd, D, a.records, p0, pn, a.inv_spp_norm, a.stats,
+                                                   c->stream));
         }
         a.n_paths = total;
-    } else {
-        // hero-wavelength paths: one launch, shadow rays traced in the path loop
-        a.path_begin = 0;
-        if (total > 0) GR_HIP(c, grw::launch_trace(a, grid, c->stream));
     }
     if (st) GR_HIP(c, hipEventRecord(ev[1], c->stream));
     if (total > 0)

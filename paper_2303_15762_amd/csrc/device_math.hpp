@@ -312,12 +312,13 @@ __device__ __noinline__ int poisson_inverse(double g, float u0) {
 // sampled component: the grating order, the rough surface's Poisson term (0 = the specular
 // delta), 0 for a smooth surface; pick_p (optional) the probability of a grating's sampled
 // order, w_j / W; off (optional, 2 floats) the rough surface's sampled transfer kappa (zero
-// otherwise; a grating's is -j K along x).
+// otherwise; a grating's is -j K along x); with off given, a rough surface's evanescent draw is
+// left to the caller, which forms the direction in double.
 // ------------------------------------------------------------------------------------------
 __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, float ci,
                                   float u0, float u1, float u2, float& kox, float& koy,
                                   float& weight, float* cache, int cache_n, int* comp = nullptr,
-                                  float* pick_p = nullptr, float* off = nullptr) {
+                                  float* pick_p = nullptr, float* off = nullptr, double g_rough = -1.0) {
     if (comp) *comp = 0;
     if (off) off[0] = off[1] = 0.0f;
     if (m.kind == MAT_SMOOTH) {
@@ -385,8 +386,11 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
         if (pick_p) *pick_p = wp / W;
         return 0;
     }
-    // rough: Poisson term by inversion of the CDF in double precision
-    const int n = poisson_inverse(4.0 * (double)k2 * (double)ci * (double)ci * (double)m.h * (double)m.h, u0);
+    // rough: Poisson term by inversion of the CDF in double precision (g_rough: the caller's
+    // double-precision Poisson parameter, when it has one)
+    const int n = poisson_inverse(g_rough >= 0.0 ? g_rough
+                                                 : 4.0 * (double)k2 * (double)ci * (double)ci * (double)m.h * (double)m.h,
+                                  u0);
     if (comp) *comp = n;
     float z1, z2;
     box_muller(u1, u2, z1, z2);
@@ -394,10 +398,12 @@ __device__ inline int sample_finf(const DMat& m, float k, float kix, float kiy, 
     kox = kix + sd * z1;
     koy = kiy + sd * z2;
     if (off) {
+        // the caller forms the new direction in double and decides evanescence there
         off[0] = sd * z1;
         off[1] = sd * z2;
+    } else if (kox * kox + koy * koy >= k2) {
+        return 1;
     }
-    if (kox * kox + koy * koy >= k2) return 1;
     weight = m.refl;
     return 0;
 }

@@ -95,8 +95,9 @@ struct TraceArgs {
     uint4* shq;                      // queued shadow rays (3 uint4 each), or null
     unsigned long long* shq_count;
     float* sdense;                   // measurement values by (path, interaction) slot
-                                     // [paths of the launch][max_depth]; a path stores the
-                                     // slots of its first snd[path] interactions
+                                     // [paths of the launch][max_depth] (four floats per slot
+                                     // for hero-wavelength paths); a path stores the slots of
+                                     // its first snd[path] interactions
     uint8_t* snd;                    // [paths of the launch]
     float* records;                  // [n_paths]
     int* ovf;                        // traversal stack overflow [ovf_n][grid * 256], or null
@@ -125,6 +126,11 @@ hipError_t launch_zero_words(uint32_t* p, uint64_t n, hipStream_t s);
 // records[p0 + i] = inv_spp_norm * sum over d < nd[i] of val[i * depth + d], i < n (fixed order)
 hipError_t launch_shadow_merge(const float* val, const uint8_t* nd, int depth, float* records, uint64_t p0,
                                uint64_t n, float inv_spp_norm, unsigned long long* stats, hipStream_t s);
+// hero-wavelength records: member j of path p0 + i gets the sum over d < nd[i] of
+// val[(i * depth + d) * 4 + j], at record ((p0 + i) / G) nl + (p0 + i) % G + j G
+hipError_t launch_hero_merge(const float* val, const uint8_t* nd, int depth, float* records, uint64_t p0,
+                             uint64_t n, uint32_t G, uint32_t nl, float inv_spp_norm, unsigned long long* stats,
+                             hipStream_t s);
 // a queued shadow ray: mean position (3 doubles), travel direction of the light, emitter
 // distance, triangle left, slot
 constexpr int kShadowQueryBytes = 48;

@@ -255,7 +255,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     // (path, interaction) slots, and a merge writes the record once visibility is known.
     // DEFER (learned p_w) queues in-domain rough measurements for the batched network, whose
     // results land in the same slots before the shadow rays are traced.
-    constexpr bool SHQ = !HERO;
+    // Hero-wavelength paths store the four members' values per slot (four floats).
+    constexpr bool SHQ = true;
 
     bool live = false, exhausted = false;
     uint64_t idx = 0, pid = 0;
@@ -269,10 +270,10 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     if constexpr (ANISO) aniso_iso(ar, 1.0f);
     // hero-wavelength members: wavenumber, beta^2, rho, T = f / p_h, R = p / p_h, estimate
     constexpr int NM = HERO ? 4 : 1;
-    float mk[NM], mb2[NM], mrho[NM], mT[NM], mR[NM], macc[NM];
+    float mk[NM], mb2[NM], mrho[NM], mT[NM], mR[NM];
     int hs = 0;
 #pragma unroll
-    for (int i = 0; i < NM; ++i) mk[i] = mb2[i] = mrho[i] = mT[i] = mR[i] = macc[i] = 0.0f;
+    for (int i = 0; i < NM; ++i) mk[i] = mb2[i] = mrho[i] = mT[i] = mR[i] = 0.0f;
     // traversal work per lane; the per-path events are flagged per lane (one bit each) and
     // counted per wave with ballots, which keeps the counts in scalar registers
     uint32_t c_nodes = 0, c_tris = 0;
@@ -338,7 +339,6 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                                 mrho[i] = 0.0f;
                                 mT[i] = 1.0f;
                                 mR[i] = 1.0f;
-                                macc[i] = 0.0f;
                                 if (tadv > 0.0f) {
                                     const float zb = tadv * 1e6f / mk[i];
                                     mrho[i] = zb / beta2;
@@ -487,6 +487,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
 
                 // Measurement by next-event estimation (eq. measurement_operator).
                 float sval = 0.0f;   // SHQ: the value for this vertex's slot
+                float hv[4] = {0.0f, 0.0f, 0.0f, 0.0f};   // HERO: the members' values
                 if (A.nsrc > 0) {
                     const uint4 rn = draw(pid, (uint32_t)depth, STREAM_NEE, A.seed);
                     const int si = min((int)(unif(rn.x) * (float)A.nsrc), A.nsrc - 1);
@@ -519,7 +520,59 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                         }
                     }
-                    if constexpr (SHQ) {
+                    if constexpr (HERO) {
+                      if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
+                        // the four members' values now (their slot holds four floats), the
+                        // visibility later (shadow_kernel clears all four)
+                        ev |= 1u << EV_SHADOW;
+                        const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
+                        // members: emitter-sampling density of om relative to the hero's
+                        // (Gaussian angular spectrum N(k u_t; 0, rc^-2 I) k^2), then the
+                        // balance-heuristic estimate of each
+                        float q[4], den = 0.0f;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            q[i] = L.kind == 0 ? 1.0f
+                                               : mk[i] * mk[i] / (k * k) *
+                                                     __expf(-0.5f * (mk[i] * mk[i] - k * k) * tt_s * L.rc_um * L.rc_um);
+                            den += mR[i] * q[i];
+                        }
+                        const float cx = dot3(om, xa), cy = dot3(om, ya);
+                        const float scale = 4.0f * L.power * (float)A.nsrc / den;
+                        // one p_w call site for the four members (a rolled loop; the member's
+                        // registers are picked by selects)
+#pragma nounroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float Ti = pick4(mT, i);
+                            if (Ti == 0.0f) continue;
+                            const float ki = pick4(mk, i), sr = 0.5f * pick4(mb2, i);
+                            const float p = pw_plain(m.kind, m.h, m.L, m.refl, ki, ki * cx, ki * cy, -ki * dx,
+                                                     -ki * dy, sr * (1.0f + dx * dx * ic2), sr * (1.0f + dy * dy * ic2),
+                                                     sr * (dx * dy * ic2), 1.0f, 0.0f);
+                            const float add = scale * Ti * pick4(q, i) * p;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                if (j == i) hv[j] = add;
+                            }
+                        }
+                        const bool want = hv[0] != 0.0f || hv[1] != 0.0f || hv[2] != 0.0f || hv[3] != 0.0f;
+                        const unsigned long long qm = __ballot(want);
+                        if (want) {
+                            const int leader = __ffsll((long long)qm) - 1;
+                            unsigned long long qb = 0;
+                            if (lane == leader) qb = atomicAdd(A.shq_count, (unsigned long long)__popcll(qm));
+                            qb = __shfl(qb, leader);
+                            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(qm >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)qm, 0u));
+                            uint4* q4 = A.shq + 3 * (qb + r);
+                            const unsigned long long px = __double_as_longlong(P.x), py = __double_as_longlong(P.y),
+                                                     pz = __double_as_longlong(P.z);
+                            q4[0] = make_uint4((uint32_t)px, (uint32_t)(px >> 32), (uint32_t)py, (uint32_t)(py >> 32));
+                            q4[1] = make_uint4((uint32_t)pz, (uint32_t)(pz >> 32), __float_as_uint(om.x), __float_as_uint(om.y));
+                            q4[2] = make_uint4(__float_as_uint(om.z), __float_as_uint(tmax_s), (uint32_t)prev, slot);
+                        }
+                      }
+                    } else if constexpr (SHQ) {
                       if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
                         // the measurement value now, its visibility later (shadow_kernel)
                         ev |= 1u << EV_SHADOW;
@@ -581,53 +634,18 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             q[2] = make_uint4(__float_as_uint(om.z), __float_as_uint(tmax_s), (uint32_t)prev, slot);
                         }
                       }
-                    } else if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
-                        // hero-wavelength paths trace their shadow rays in the path loop
-                        ev |= 1u << EV_SHADOW;
-                        RayT sray;
-                        ray_setup(sray, P, -1.0f * om);
-                        float tm = tmax_s, su, sv;
-                        const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, su, sv);
-                        if (occ < 0) {
-                            // members: emitter-sampling density of om relative to the hero's
-                            // (Gaussian angular spectrum N(k u_t; 0, rc^-2 I) k^2), then the
-                            // balance-heuristic estimate of each
-                            float q[4], den = 0.0f;
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                q[i] = L.kind == 0 ? 1.0f
-                                                   : mk[i] * mk[i] / (k * k) *
-                                                         __expf(-0.5f * (mk[i] * mk[i] - k * k) * tt_s * L.rc_um * L.rc_um);
-                                den += mR[i] * q[i];
-                            }
-                            const float cx = dot3(om, xa), cy = dot3(om, ya);
-                            const float scale = 4.0f * L.power * (float)A.nsrc / den;
-                            // one p_w call site for the four members (a rolled loop; the
-                            // member's registers are picked by selects)
-#pragma nounroll
-                            for (int i = 0; i < 4; ++i) {
-                                const float Ti = pick4(mT, i);
-                                if (Ti == 0.0f) continue;
-                                const float ki = pick4(mk, i), sr = 0.5f * pick4(mb2, i);
-                                const float p = pw_plain(m.kind, m.h, m.L, m.refl, ki, ki * cx, ki * cy, -ki * dx,
-                                                         -ki * dy, sr * (1.0f + dx * dx * ic2), sr * (1.0f + dy * dy * ic2),
-                                                         sr * (dx * dy * ic2), 1.0f, 0.0f);
-                                const float add = scale * Ti * pick4(q, i) * p;
-#pragma unroll
-                                for (int j = 0; j < 4; ++j) {
-                                    if (j == i) macc[j] += add;
-                                }
-                            }
-                        }
                     }
                 }
-                if constexpr (SHQ) {
-                    // every vertex that reaches the measurement stores its slot (zero without a
-                    // measurement; a queued network query overwrites it, an occluded shadow ray
-                    // clears it), so the merge reads the path's first slots only
+                // every vertex that reaches the measurement stores its slot (zero without a
+                // measurement; a queued network query overwrites it, an occluded shadow ray
+                // clears it), so the merge reads the path's first slots only
+                if constexpr (HERO) {
+                    float4* h4 = reinterpret_cast<float4*>(A.sdense) + ((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
+                    *h4 = make_float4(hv[0], hv[1], hv[2], hv[3]);
+                } else {
                     A.sdense[(idx - A.path_begin) * (uint64_t)A.max_depth + depth] = sval;
-                    wrote = true;
                 }
+                wrote = true;
                 if (depth + 1 >= A.max_depth) {
                     finish = true;
                 } else {
@@ -653,8 +671,17 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         }
                     }
                     const float kix_s = rcx * k * dx + rcy * k * dy, kiy_s = -rcy * k * dx + rcx * k * dy;
+                    // a rough surface's Poisson parameter (2 k cos i s)^2 in double, from the path's
+                    // wavelength and double cosine (its decision must not depend on float rounding)
+                    double g_rough = -1.0;
+                    if (cm.kind == MAT_ROUGH) {
+                        const uint32_t nw = HERO ? (nl >> 2) : nl;
+                        const uint32_t wi = (uint32_t)(pid % nw) + (HERO ? (uint32_t)hs * nw : 0u);
+                        const double kd = 6.283185307179586 / (double)A.lambda[wi];
+                        g_rough = 4.0 * kd * kd * cid * cid * (double)cm.h * (double)cm.h;
+                    }
                     if (sample_finf(cm, k, kix_s, kiy_s, ci, unif(rs.x), unif(rs.y), unif(rs.z), kox, koy, wgt,
-                                    (float*)(int*)stk, STACK, &comp_j, HERO ? &ph : nullptr, off)) {
+                                    (float*)(int*)stk, STACK, &comp_j, HERO ? &ph : nullptr, off, g_rough)) {
                         ev |= 1u << EV_EVANESCENT;
                         finish = true;
                     } else {
@@ -737,23 +764,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         }
         }   // live
         if (finish) {
-            if constexpr (HERO) {
-                // record of (sample, pixel, wavelength g + i G): (idx / G) nl + g + i G
-                const uint32_t G = nl >> 2;
-                const uint64_t rb = (idx / G) * nl + idx % G;
-#pragma unroll
-                for (int i = 0; i < NM; ++i) {
-                    float val = macc[i] * A.inv_spp_norm;
-                    if (!isfinite(val)) {
-                        ev |= 1u << EV_NONFINITE;
-                        val = 0.0f;
-                    }
-                    A.records[rb + (uint64_t)i * G] = val;
-                }
-            } else {
-                // slots the path stored: one per vertex that reached the measurement
-                A.snd[idx - A.path_begin] = (uint8_t)(depth + (wrote ? 1 : 0));
-            }
+            // slots the path stored: one per vertex that reached the measurement
+            A.snd[idx - A.path_begin] = (uint8_t)(depth + (wrote ? 1 : 0));
             live = false;
         }
 #pragma unroll
@@ -805,7 +817,10 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
             float tm = __uint_as_float(c.y), su, sv;
             const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk, A.lds_cap, ovf, ostride,
                                             c_nodes, c_tris, su, sv);
-            if (occ >= 0) A.sdense[c.w] = 0.0f;
+            if (occ >= 0) {
+                if (A.hero) reinterpret_cast<float4*>(A.sdense)[c.w] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                else A.sdense[c.w] = 0.0f;
+            }
         }
     }
     const unsigned long long s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris);
@@ -836,6 +851,44 @@ __global__ __launch_bounds__(256) void shadow_merge_kernel(const float* __restri
         records[p0 + i] = v;
     }
     const unsigned long long nb = __popcll(__ballot(bad));
+    if ((threadIdx.x & 63) == 0 && nb) atomicAdd(stats + ST_NONFINITE, nb);
+}
+
+// Records of a launch's hero-wavelength paths: member i's values summed over the path's
+// stored slots in depth order (four floats per slot) into the record of wavelength g + i G of
+// its (sample, pixel): path index p -> record (p / G) nl + p % G + i G.
+__global__ __launch_bounds__(256) void hero_merge_kernel(const float4* __restrict__ val,
+                                                         const uint8_t* __restrict__ nd, int depth,
+                                                         float* __restrict__ records, uint64_t p0, uint64_t n,
+                                                         uint32_t G, uint32_t nl, float inv_spp_norm,
+                                                         unsigned long long* stats) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned nbad = 0;
+    if (i < n) {
+        const int m = nd[i];
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+        for (int d = 0; d < m; ++d) {
+            const float4 v = val[i * depth + d];
+            s0 += v.x;
+            s1 += v.y;
+            s2 += v.z;
+            s3 += v.w;
+        }
+        const uint64_t p = p0 + i;
+        const uint64_t rb = (p / G) * nl + p % G;
+        const float sv[4] = {s0 * inv_spp_norm, s1 * inv_spp_norm, s2 * inv_spp_norm, s3 * inv_spp_norm};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = sv[j];
+            if (!isfinite(v)) {
+                ++nbad;
+                v = 0.0f;
+            }
+            records[rb + (uint64_t)j * G] = v;
+        }
+    }
+    unsigned long long nb = 0;
+    for (int b = 0; b < 4; ++b) nb += __popcll(__ballot(nbad > (unsigned)b));
     if ((threadIdx.x & 63) == 0 && nb) atomicAdd(stats + ST_NONFINITE, nb);
 }
 
@@ -923,6 +976,15 @@ hipError_t launch_shadow_merge(const float* val, const uint8_t* nd, int depth, f
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(shadow_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, nd, depth,
                        records, p0, n, inv_spp_norm, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_hero_merge(const float* val, const uint8_t* nd, int depth, float* records, uint64_t p0,
+                             uint64_t n, uint32_t G, uint32_t nl, float inv_spp_norm, unsigned long long* stats,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(hero_merge_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(val), nd, depth, records, p0, n, G, nl, inv_spp_norm, stats);
     return hipGetLastError();
 }
 

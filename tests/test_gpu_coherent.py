@@ -74,3 +74,16 @@ def test_two_point_fringe_period_and_visibility(R, sigma_mode):
     assert V == pytest.approx(Vexp, abs=0.02)
     assert abs(math.atan2(c[2], c[1])) < 0.05
     assert c[0] == pytest.approx(2.0 / zz ** 2, rel=0.01)
+
+
+@pytest.mark.parametrize("z", [0.1, 1.0, 10.0])
+def test_double_slit_all_rows_against_oracle(R, z):
+    """The whole 1024 x 64 sensor of the double slit at 0.55 um (64 samples), FP64 and
+    two-float phase, against the oracle's estimator on the same samples."""
+    case = coherent_case("slits", z_m=z, lambda_um=0.55)
+    ref = oracle.coherent_mc(case, rows=case.height)
+    for mode, tol in ((1, 1e-6), (2, 1e-4)):
+        img, _ = R.coherent(case, phase_mode=mode)
+        e = rel_l2(img.cpu().numpy(), ref)
+        print(f"slits z={z}: mode {mode} rel L2 over all {case.height} rows {e:.3e}")
+        assert e <= tol

@@ -253,3 +253,51 @@ def test_depth_limits_match_oracle(R, depth):
     print("depth", depth, "rel L2", err, "segments", st["segments"], ost["segments"])
     assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
     assert err <= RTOL_IMAGE
+
+
+@pytest.mark.parametrize("depth", [9, 64])
+def test_rough_box_deep_paths_match_oracle(R, depth):
+    """A closed cube of rough walls with the emitter inside: no path escapes, so depth 64 runs
+    every path to 64 interactions (6x the segments of depth 9) with measurements at all
+    depths.  Compared path by path: a path whose record differs by more than 1 % has taken
+    another discrete decision somewhere (an evanescent draw, a Poisson term, a grazing hit)
+    because the decision's inputs carry the float rounding of dozens of earlier interactions;
+    from there on its contributions are another path's.  Such paths must stay below 1e-3 of
+    the paths (measured: 0 at depth 9, 2 of 8,192 at depth 64), and the image of the others
+    within the plain path's 1e-3."""
+    wl = W.rough_box(width=32, height=32, spp=8, max_depth=depth)
+    R.load_workload(wl)
+    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed, keep_paths=True)
+    img, st = R.trace(wl.lambdas_um, opts)
+    rec = R.path_records(opts, 1).cpu().numpy().astype(np.float64).reshape(wl.spp, -1)
+    o, ost, paths = oracle.render(wl, keep_paths=True)
+    paths = paths[:, :, 0]
+    err = rel_l2(img.cpu().numpy(), o)
+    scale = np.abs(paths).max()
+    flipped = np.abs(rec - paths) > 1e-2 * np.maximum(np.abs(paths), 1e-6 * scale)
+    keep = ~flipped
+    e_keep = rel_l2((rec * keep).sum(0), (paths * keep).sum(0))
+    print("rough box depth", depth, "image rel L2", err, "paths with another decision", int(flipped.sum()), "of",
+          flipped.size, "image of the others", e_keep, "segments", st["segments"], ost["segments"])
+    assert ost["segments"] > (5 * 32 * 32 * 8 if depth == 64 else 0)
+    assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    assert flipped.sum() <= 1e-3 * flipped.size
+    assert e_keep <= RTOL_IMAGE
+    if depth <= 9:
+        assert err <= RTOL_IMAGE
+
+
+def test_terrain_full_frame_matches_oracle(R):
+    """The mid workload's whole 512 x 512 x 8 image (16 samples, depth 4) against the oracle's
+    whole image, in the launch configuration the benchmark times."""
+    wl = W.as_float32_inputs(W.mid_terrain())
+    g, st = _gpu_image(R, wl)
+    o, ost = oracle.render(wl)
+    err = rel_l2(g, o)
+    d2 = ((g - o) ** 2).sum(0)
+    y, x = np.unravel_index(int(np.argmax(d2)), d2.shape)
+    print("mid full frame: rel L2", err, "segments", st["segments"], ost["segments"], "worst pixel", (x, y),
+          "share of squared error", d2[y, x] / d2.sum())
+    assert st["nonfinite"] == 0
+    assert abs(st["segments"] - ost["segments"]) <= 1e-4 * ost["segments"]
+    assert err <= RTOL_IMAGE

@@ -16,6 +16,7 @@ from .scenes import (  # noqa: F401
     parallel_mirror,
     grating_relay,
     split_mirror,
+    rough_box,
     terrain_scene,
     mid_terrain,
     large_scene,

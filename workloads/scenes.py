@@ -207,6 +207,32 @@ def split_mirror(width: int = 64, height: int = 4, spp: int = 4, seed: int = 11,
     return Workload("split-mirror", scene, sensor, [src], lam, spp=spp, max_depth=1, seed=seed)
 
 
+def rough_box(width: int = 16, height: int = 16, spp: int = 4, max_depth: int = 64, seed: int = 13,
+              reflectance: float = 0.9) -> Workload:
+    """A closed 1 cm cube of Gaussian rough walls (RMS 0.05 um, correlation length 2 um,
+    reflectance 0.9) with a partially coherent 4 mm emitter inside, 4 mm above the centre and
+    facing down, seen by an orthographic sensor inside the cube looking down at 30 degrees:
+    no path escapes, so every path runs to the depth limit unless it ends evanescently, and
+    its measurements spread over all depths."""
+    h = 5e-3
+    c = np.array([[-h, -h, -h], [h, -h, -h], [h, h, -h], [-h, h, -h],
+                  [-h, -h, h], [h, -h, h], [h, h, h], [-h, h, h]], np.float64)
+    quads = [(0, 1, 2, 3), (4, 7, 6, 5), (0, 4, 5, 1), (1, 5, 6, 2), (2, 6, 7, 3), (3, 7, 4, 0)]
+    tris = np.array([t for a, b, cc, d in quads for t in ((a, b, cc), (a, cc, d))], np.int32)
+    mats = [Material(ROUGH, height_um=0.05, length_um=2.0, reflectance=reflectance)]
+    scene = Scene(verts=c, tris=tris, tri_mat=np.zeros(len(tris), np.int32), materials=mats, normals=None)
+    th = math.radians(30.0)
+    view = np.array([math.sin(th), 0.0, -math.cos(th)])
+    pitch = 2e-3 / max(width, height)
+    sensor = _ortho_sensor(np.array([-1e-3, 0.0, 3e-3]), view, np.array([0.0, 1.0, 0.0]), width, height,
+                           pitch, pitch / 4.0)
+    src = Source(GSM_AREA, dir=np.array([0.0, 0.0, -1.0]), pos=np.array([0.0, 0.0, 4e-3]),
+                 eu=np.array([2e-3, 0.0, 0.0]), ev=np.array([0.0, 2e-3, 0.0]),
+                 coherence_radius_um=5.0, power=1.0)
+    return Workload("rough-box", scene, sensor, [src], np.array([0.55]), spp=spp, max_depth=max_depth,
+                    seed=seed)
+
+
 # --------------------------------------------------------------------------------------
 # Terrain: value-noise heightfield with per-tile materials
 # --------------------------------------------------------------------------------------
