@@ -299,10 +299,12 @@ int gr_scene_boundaries(gr_ctx* c, float reach_m, int64_t* n_edges) {
     const int64_t nt = (int64_t)c->h_tri_mat.size();
     if (!grw::build_boundaries(c->h_verts.data(), c->h_tris.data(), c->h_tri_mat.data(), nt, reach_m, B))
         return fail(c, GR_E_UNSUPPORTED, "boundaries: more than 2^32 candidate entries");
-    std::vector<uint32_t> tl(2 * (size_t)nt);
+    std::vector<uint32_t> tl(4 * (size_t)nt);
     for (int64_t t = 0; t < nt; ++t) {
-        tl[2 * t] = B.first[t];
-        tl[2 * t + 1] = B.count[t];
+        tl[4 * t] = B.first[t];
+        tl[4 * t + 1] = B.count[t];
+        std::memcpy(&tl[4 * t + 2], &B.gap[t], 4);
+        tl[4 * t + 3] = 0u;
     }
     GR_HIP(c, hipSetDevice(c->device));
     free_boundaries(c);
@@ -552,7 +554,7 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
     a.composite = composite_of(o) ? 1 : 0;
     if (a.composite) {
         a.bnd.edges = static_cast<const float4*>(c->d_bedges);
-        a.bnd.tri_list = static_cast<const uint2*>(c->d_btri);
+        a.bnd.tri_list = static_cast<const uint4*>(c->d_btri);
         a.bnd.idx = static_cast<const uint32_t*>(c->d_bidx);
         a.bnd.reach_m = c->reach_m;
         a.bnd.weid_L = c->weid_L;

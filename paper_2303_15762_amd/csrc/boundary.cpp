@@ -81,6 +81,7 @@ bool build_boundaries(const float* verts, const int32_t* tris, const int32_t* tr
     out.n_edges = ne;
     out.first.assign((size_t)nt, 0u);
     out.count.assign((size_t)nt, 0u);
+    out.gap.assign((size_t)nt, 0.0f);
     if (ne == 0) return true;
     // uniform grid over the edges, hashed by cell coordinates: each edge is listed in every
     // cell that its box widened by reach touches, so a triangle within reach of it shares a
@@ -156,6 +157,11 @@ bool build_boundaries(const float* verts, const int32_t* tris, const int32_t* tr
                 }
         std::sort(cand.begin(), cand.end());
         cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        // the smallest box gap to a listed edge bounds every hit's distance from below
+        double g2 = 1e300;
+        for (uint32_t e : cand) g2 = std::min(g2, box_gap2(tb, eboxes[e]));
+        // rounded down to float, so that the bound stays a bound
+        out.gap[(size_t)t] = cand.empty() ? 0.0f : std::nextafter((float)std::sqrt(g2), 0.0f);
         if (out.idx.size() + cand.size() >= (1ull << 32)) return false;
         out.idx.insert(out.idx.end(), cand.begin(), cand.end());
         out.count[(size_t)t] = (uint32_t)cand.size();

@@ -43,6 +43,7 @@ struct BuiltBoundaries {
     std::vector<float> edges;        // [n][16]: p0, mat a (int bits), p1, mat b, third vertex of a (+pad), of b (+pad)
     std::vector<uint32_t> first;     // per triangle: first entry in idx
     std::vector<uint32_t> count;     // per triangle: number of entries
+    std::vector<float> gap;          // per triangle: a lower bound of its distance to its listed edges
     std::vector<uint32_t> idx;       // boundary edge ids, ascending per triangle
     int64_t n_edges = 0;
 };

@@ -127,8 +127,14 @@ __device__ inline float pw_composite(const DMat& near, float gnx, float gny, con
             const int J = min((int)ceilf(fabsf(mm)) + 10, 64);
 #pragma nounroll
             for (int j = -J; j <= J; ++j) {
-                const float bj = bessel_jn(abs(j), mm);
                 const float vx = kx + (float)j * K * gx, vy = ky + (float)j * K * gy;
+                // an order whose whole-plane field and half-plane field both vanish (its lobe
+                // and its boundary streak both far from kappa) adds nothing
+                const float bb = -H.ny * vx + H.nx * vy;
+                if (H.sxx * vx * vx + 2.0f * H.sxy * vx * vy + H.syy * vy * vy > 80.0f &&
+                    bb * bb * H.along + H.e0 > 80.0f && j != 0)
+                    continue;
+                const float bj = bessel_jn(abs(j), mm);
                 float g, fr, fi;
                 halfplane_fields(H, B, vx, vy, g, fr, fi);
                 const float hr = s == 0 ? g - fr : fr, hi = s == 0 ? -fi : fi;
@@ -184,10 +190,11 @@ __device__ inline float pw_composite(const DMat& near, float gnx, float gny, con
 __device__ inline bool find_boundary(const BoundaryDev& B, int tri, int mat, const d3& P, const f3& xa,
                                      const f3& ya, float sxx, float syy, float sxy, const DMat* mats, int& fmat,
                                      float& gfx, float& gfy, HalfPlane& H) {
-    const uint2 L = B.tri_list[tri];
+    const uint4 L = B.tri_list[tri];
     if (L.y == 0u) return false;
     const float lmax = 0.5f * (sxx + syy) + sqrtf(0.25f * (sxx - syy) * (sxx - syy) + sxy * sxy);
     const float rad = fminf(2.5f * sqrtf(2.0f * lmax) * 1e-6f, B.reach_m);
+    if (rad <= __uint_as_float(L.z)) return false;   // every listed edge is farther than rad
     float best_d = rad;
     int best = -1;
     for (uint32_t i = 0; i < L.y; ++i) {

@@ -60,7 +60,8 @@ constexpr int kWeidN = 16;
 struct BoundaryDev {
     const float4* edges;     // 4 float4 per boundary edge: p0 (w: material of triangle a, as int
                              // bits), p1 (w: material of triangle b), the third vertex of a, of b
-    const uint2* tri_list;   // per original triangle: (first, count) into idx
+    const uint4* tri_list;   // per original triangle: first and count into idx, a lower bound
+                             // of its distance to those edges (float bits, metres), 0
     const uint32_t* idx;     // boundary edges of the triangle's material near it, ascending
     float reach_m;           // largest boundary distance considered
     float weid_L;

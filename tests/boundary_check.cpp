@@ -1,6 +1,7 @@
 // Host-side check of libgrwave's material-boundary lists (composite interactions): for points
 // on triangles, the nearest boundary edge of the triangle's material within the reach, found
-// through the triangle's candidate list, against brute force over every boundary edge.
+// through the triangle's candidate list, against brute force over every boundary edge; and
+// the triangle's distance bound below every listed edge's distance.
 // Input (stdin): nv nt reach, nv lines "x y z", nt lines "a b c m", nq, nq lines "t u v".
 // Output: "OK n_edges n_found total_list_entries" or "FAIL reason".
 #include <cmath>
@@ -57,6 +58,7 @@ int main() {
             if (i > 0 && e <= B.idx[B.first[ti] + i - 1]) { printf("FAIL list not ascending\n"); return 0; }
             const float* r = &B.edges[16 * e];
             const double d = seg_dist(P, r, r + 4);
+            if (d < (double)B.gap[ti]) { printf("FAIL query %ld: edge %u at %g below the bound %g\n", q, e, d, (double)B.gap[ti]); return 0; }
             if (d < ld) { ld = d; lb = e; }
         }
         if (lb != bb) { printf("FAIL query %ld: list %ld brute %ld (%g %g)\n", q, lb, bb, ld, bd); return 0; }
