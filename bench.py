@@ -57,7 +57,8 @@ TRAFFIC_BYTES = {"mid": 4_553_442 * 1024, "large": 159_223_564 * 1024}
 TRAFFIC_KERNEL_HASH = "2b838df078f56641"
 KERNEL_SOURCES = ["paper_2303_15762_amd/csrc/trace.hip", "paper_2303_15762_amd/csrc/trace_core.hpp",
                   "paper_2303_15762_amd/csrc/device_math.hpp",
-                  "paper_2303_15762_amd/csrc/kernels.hpp", "paper_2303_15762_amd/csrc/composite.hpp"]
+                  "paper_2303_15762_amd/csrc/kernels.hpp", "paper_2303_15762_amd/csrc/composite.hpp",
+                  "paper_2303_15762_amd/csrc/bvh_build.cpp"]
 
 
 def kernel_hash():

@@ -14,6 +14,8 @@
 #include "../../include/grwave.h"
 #include "bvh_build.hpp"
 #include "kernels.hpp"
+
+static_assert(grw::kLdsNodes <= grw::kTopNodes, "the LDS copy must hold top-level nodes only");
 #include "surrogate.hpp"
 
 extern "C" int grw_coherent_launch(const gr_coherent_desc* d, float* image, hipStream_t stream, float* ms,

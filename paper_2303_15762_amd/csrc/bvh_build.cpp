@@ -237,6 +237,36 @@ struct Collapser {
     }
 };
 
+// Renumber the nodes so that the first kTopNodes inner nodes met breadth-first from the root
+// come first, in that order (the traversal keeps them in LDS); the rest keep their depth-first
+// order.  A node is met only after its parent, and no node after them has a child among them
+// (the breadth-first prefix holds all nodes of a level before any of the next), so child
+// indices stay above their parents'.
+void top_levels_first(std::vector<BVH4Node>& nodes) {
+    const int n = (int)nodes.size();
+    std::vector<int> bfs;
+    bfs.reserve(kTopNodes);
+    bfs.push_back(0);
+    for (size_t h = 0; h < bfs.size() && (int)bfs.size() < kTopNodes; ++h)
+        for (int i = 0; i < 4 && (int)bfs.size() < kTopNodes; ++i) {
+            const int32_t c = nodes[bfs[h]].child[i];
+            if (c >= 0 && c != kEmptyChild) bfs.push_back(c);
+        }
+    std::vector<int32_t> id(n, -1);
+    for (size_t i = 0; i < bfs.size(); ++i) id[bfs[i]] = (int32_t)i;
+    int32_t next = (int32_t)bfs.size();
+    for (int i = 0; i < n; ++i)
+        if (id[i] < 0) id[i] = next++;
+    std::vector<BVH4Node> out(n);
+    for (int i = 0; i < n; ++i) {
+        BVH4Node N = nodes[i];
+        for (int j = 0; j < 4; ++j)
+            if (N.child[j] >= 0 && N.child[j] != kEmptyChild) N.child[j] = id[N.child[j]];
+        out[id[i]] = N;
+    }
+    nodes.swap(out);
+}
+
 }  // namespace
 
 BuiltBVH build_bvh4(const float* verts, const int32_t* tris, int64_t nt) {
@@ -246,6 +276,7 @@ BuiltBVH build_bvh4(const float* verts, const int32_t* tris, int64_t nt) {
     out.nodes.reserve(B.nodes.size() / 3 + 4);
     Collapser C{B, out, 0};
     C.emit(0, 0);
+    top_levels_first(out.nodes);
     out.tri_order = B.idx;
     out.depth = C.max_depth;
     out.max_leaf = B.max_leaf_seen;

@@ -20,9 +20,13 @@ static_assert(sizeof(BVH4Node) == 128, "BVH4Node must be one 128-byte line");
 
 constexpr int kMaxLeaf = 8;
 constexpr int32_t kEmptyChild = 0x7FFFFFFF;
+// The first kTopNodes inner nodes of the tree in breadth-first order (root, its children,
+// theirs, ...) take indices 0 .. kTopNodes - 1; every other node keeps the depth-first
+// pre-order of the collapse, after them.  Every child index stays above its parent's.
+constexpr int kTopNodes = 64;
 
 struct BuiltBVH {
-    std::vector<BVH4Node> nodes;     // root at index 0
+    std::vector<BVH4Node> nodes;     // root at index 0; the top levels first (kTopNodes)
     std::vector<int32_t> tri_order;  // leaf order -> original triangle index
     int depth = 0;                   // deepest inner-node level (root = 0)
     int max_leaf = 0;

@@ -12,6 +12,10 @@ constexpr int kMaxSources = 16;
 constexpr int kMaxLambda = 64;
 // Traversal stack entries per lane kept in LDS; deeper entries go to the overflow region.
 constexpr int kLdsStack = 32;
+// BVH nodes 0 .. kLdsNodes - 1 (the builder puts the top levels there, breadth-first) are
+// copied into each block's LDS by the traversal kernels: 8 KB beside the 32 KB of stacks,
+// so that four blocks still fill the 160 KB of a compute unit.
+constexpr int kLdsNodes = 64;
 
 struct SceneDev {
     const float4* nodes;     // BVH4Node as 8 float4 each

@@ -241,6 +241,10 @@ __device__ __forceinline__ void aniso_footprint(const AnisoRay& R, const f3& d, 
 template <int STACK, bool DEFER, bool HERO, bool ANISO = false, bool COMPOSITE = false>
 __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
+    // the top levels of the BVH, read by every closest-hit query
+    __shared__ float4 lds_nodes[kLdsNodes * 8];
+    const int nln = stage_top_nodes(A.scene, lds_nodes);
+    const lds_v4f* top = (const lds_v4f*)&lds_nodes[0];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
@@ -378,7 +382,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         ray_setup(ray, o, d);
         const float tmin = 1e-7f * (1.0f + maxabs3(to_f3(o)));
         float thit = FLT_MAX, bu = 0.0f, bv = 0.0f;
-        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv);
+        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv,
+                                        top, nln);
         if (tri < 0) {
             finish = true;
         } else {
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
             } else {
                 // Tangent frame: x = grating direction (gratings), else the travel direction
                 // projected onto the surface.
-                f3 xa;
+                f3 xa = mk3(0, 0, 0);
                 bool have = false;
                 if (m.kind == MAT_GRATING) {
                     const f3 g = mk3(m.gx, m.gy, m.gz);
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 const float sr2 = 0.5f * beta2;
                 const float dx = dot3(d, xa), dy = dot3(d, ya);
                 const float ic2 = 1.0f / (ci * ci);
-                float sxx, syy, sxy;
+                float sxx = 0.0f, syy = 0.0f, sxy = 0.0f;
                 if constexpr (ANISO) {
                     aniso_footprint(ar, d, ns, xa, ya, sxx, syy, sxy);
                 } else {
@@ -478,7 +483,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 bool comp = false;
                 int fmat = 0;
                 float gfx = 1.0f, gfy = 0.0f;
-                HalfPlane hp;
+                HalfPlane hp{};
                 if constexpr (COMPOSITE) {
                     comp = find_boundary(A.bnd, prev, __float_as_int(v1.w), P, xa, ya, sxx, syy, sxy, A.scene.mats,
                                          fmat, gfx, gfy, hp);
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         int e = 0;
                         if (DEFER && m.kind == MAT_ROUGH) {
                             const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
-                            float sx[MLP_IN], slp;
+                            float sx[MLP_IN] = {}, slp = 0.0f;
                             e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sx, slp);
                             if (e == 0) ev |= 1u << EV_FALLBACK;
                             // append the query (one atomic per wave); every (path, depth) appends
@@ -655,7 +660,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     // a one-sample estimate of the mass-weighted mixture of the two kernels.  A
                     // far grating is sampled in its own frame (grating vector along x).
                     const uint4 rs = draw(pid, (uint32_t)depth, STREAM_SCATTER, A.seed);
-                    float kox, koy, wgt;
+                    float kox = 0.0f, koy = 0.0f, wgt = 0.0f;
                     int comp_j = 0;
                     float ph = 0.0f;
                     float off[2];
@@ -718,27 +723,24 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             }
                             const double fx = (double)rcx * ox - (double)rcy * oy, fy = (double)rcy * ox + (double)rcx * oy;
                             const d3 td = d3{dd.x + cid * nsd.x, dd.y + cid * nsd.y, dd.z + cid * nsd.z};
-                            d3 xd;
-                            bool hx = false;
+                            // (one candidate and one normalisation, selected without branches:
+                            // a value assigned only on some divergent paths would be carried
+                            // around the path loop)
+                            d3 t = td;
+                            double t2 = td.x * td.x + td.y * td.y + td.z * td.z;
+                            bool hx = t2 > 1e-24;
                             if (m.kind == MAT_GRATING) {
                                 const double gn = (double)m.gx * nsd.x + (double)m.gy * nsd.y + (double)m.gz * nsd.z;
-                                const d3 t = d3{m.gx - gn * nsd.x, m.gy - gn * nsd.y, m.gz - gn * nsd.z};
-                                const double t2 = t.x * t.x + t.y * t.y + t.z * t.z;
-                                if (t2 > 1e-18) {
-                                    const double r = 1.0 / sqrt(t2);
-                                    xd = d3{t.x * r, t.y * r, t.z * r};
+                                const d3 tg = d3{m.gx - gn * nsd.x, m.gy - gn * nsd.y, m.gz - gn * nsd.z};
+                                const double tg2 = tg.x * tg.x + tg.y * tg.y + tg.z * tg.z;
+                                if (tg2 > 1e-18) {
+                                    t = tg;
+                                    t2 = tg2;
                                     hx = true;
                                 }
                             }
-                            if (!hx) {
-                                const double t2 = td.x * td.x + td.y * td.y + td.z * td.z;
-                                if (t2 > 1e-24) {
-                                    const double r = 1.0 / sqrt(t2);
-                                    xd = d3{td.x * r, td.y * r, td.z * r};
-                                } else {
-                                    xd = d3{(double)xa.x, (double)xa.y, (double)xa.z};
-                                }
-                            }
+                            const double rx = hx ? 1.0 / sqrt(t2) : 0.0;
+                            const d3 xd = hx ? d3{t.x * rx, t.y * rx, t.z * rx} : d3{(double)xa.x, (double)xa.y, (double)xa.z};
                             const d3 yd = d3{nsd.y * xd.z - nsd.z * xd.y, nsd.z * xd.x - nsd.x * xd.z,
                                              nsd.x * xd.y - nsd.y * xd.x};
                             const double ik = 1.0 / (double)k;
@@ -795,6 +797,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
 template <int STACK>
 __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
     __shared__ int lds_stack[4][STACK][64];
+    __shared__ float4 lds_nodes[kLdsNodes * 8];
+    const int nln = stage_top_nodes(A.scene, lds_nodes);
+    const lds_v4f* top = (const lds_v4f*)&lds_nodes[0];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
@@ -816,7 +821,7 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
             ray_setup(sray, P, -1.0f * om);
             float tm = __uint_as_float(c.y), su, sv;
             const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk, A.lds_cap, ovf, ostride,
-                                            c_nodes, c_tris, su, sv);
+                                            c_nodes, c_tris, su, sv, top, nln);
             if (occ >= 0) {
                 if (A.hero) reinterpret_cast<float4*>(A.sdense)[c.w] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 else A.sdense[c.w] = 0.0f;

@@ -15,6 +15,18 @@ namespace grw {
 // A pointer into LDS typed as such, so that LDS accesses stay LDS instructions (a generic
 // pointer lets the compiler merge an LDS and a global access into one flat access).
 typedef __attribute__((address_space(3))) int lds_int;
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4f_t lds_v4f;
+
+// Copy BVH nodes 0 .. min(kLdsNodes, node count) - 1 into the block's LDS (8 float4 each) and
+// return how many; all threads of the block call it.
+__device__ __forceinline__ int stage_top_nodes(const SceneDev& S, float4* lds) {
+    const int n = min(kLdsNodes, (int)(S.node_bytes >> 7));
+    for (int i = threadIdx.x; i < n * 8; i += blockDim.x) lds[i] = S.nodes[i];
+    __syncthreads();
+    return n;
+}
 
 // Path positions are kept in double precision: at metre-scale coordinates one float ulp is
 // 0.06 um, and steep shading-normal gradients turn such offsets into direction errors that
@@ -160,10 +172,12 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // has found a leaf, which it parks while it keeps descending; the wave leaves the node loop once
 // every lane still in it holds a leaf, and then the lanes test their leaves together.  Node
 // and triangle code thus run on fuller waves than when every iteration does either one.
+// Nodes below nln are read from top (their LDS copy), the others from the node array.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
                                         bool any, int skip, lds_int* stk, int cap, int* ovf, size_t ostride,
-                                        uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv) {
+                                        uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv,
+                                        const lds_v4f* top, int nln) {
     constexpr int kDone = 0x7FFFFFFF;   // nothing left to visit (never a node index)
     int best = -1;
     int best_orig = 0x7FFFFFFF;
@@ -192,20 +206,32 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
     const __amdgpu_buffer_rsrc_t nb = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<float4*>(S.nodes), (short)0, (int)S.node_bytes, 0x00020000);
     const int sx = ix < 0.0f ? 16 : 0, sy = iy < 0.0f ? 48 : 32, sz = iz < 0.0f ? 80 : 64;
-    typedef float v4f_t __attribute__((ext_vector_type(4)));
-    typedef int v4i_t __attribute__((ext_vector_type(4)));
     while (cur != kDone) {
         while (cur >= 0 && cur != kDone) {
             ++n_nodes;
             const int base = cur << 7;
             const int onx = base + sx, ony = base + sy, onz = base + sz;
-            const v4f_t nx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx, 0, 0);
-            const v4f_t fx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx ^ 16, 0, 0);
-            const v4f_t ny = __builtin_amdgcn_raw_buffer_load_b128(nb, ony, 0, 0);
-            const v4f_t fy = __builtin_amdgcn_raw_buffer_load_b128(nb, ony ^ 16, 0, 0);
-            const v4f_t nz = __builtin_amdgcn_raw_buffer_load_b128(nb, onz, 0, 0);
-            const v4f_t fz = __builtin_amdgcn_raw_buffer_load_b128(nb, onz ^ 16, 0, 0);
-            const v4i_t chv = __builtin_bit_cast(v4i_t, __builtin_amdgcn_raw_buffer_load_b128(nb, base + 96, 0, 0));
+            v4f_t nx, fx, ny, fy, nz, fz;
+            v4i_t chv;
+            if (cur < nln) {
+                // the same 16-byte rows of the node's LDS copy
+                const lds_v4f* L = top + (cur << 3);
+                nx = L[sx >> 4];
+                fx = L[(sx ^ 16) >> 4];
+                ny = L[sy >> 4];
+                fy = L[(sy ^ 16) >> 4];
+                nz = L[sz >> 4];
+                fz = L[(sz ^ 16) >> 4];
+                chv = __builtin_bit_cast(v4i_t, L[6]);
+            } else {
+                nx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx, 0, 0);
+                fx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx ^ 16, 0, 0);
+                ny = __builtin_amdgcn_raw_buffer_load_b128(nb, ony, 0, 0);
+                fy = __builtin_amdgcn_raw_buffer_load_b128(nb, ony ^ 16, 0, 0);
+                nz = __builtin_amdgcn_raw_buffer_load_b128(nb, onz, 0, 0);
+                fz = __builtin_amdgcn_raw_buffer_load_b128(nb, onz ^ 16, 0, 0);
+                chv = __builtin_bit_cast(v4i_t, __builtin_amdgcn_raw_buffer_load_b128(nb, base + 96, 0, 0));
+            }
             const int4 ch = make_int4(chv.x, chv.y, chv.z, chv.w);
             const float lxa[4] = {nx.x, nx.y, nx.z, nx.w}, hxa[4] = {fx.x, fx.y, fx.z, fx.w};
             const float lya[4] = {ny.x, ny.y, ny.z, ny.w}, hya[4] = {fy.x, fy.y, fy.z, fy.w};

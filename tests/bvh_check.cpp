@@ -67,6 +67,18 @@ int main() {
     }
     for (long j = 0; j < nt; ++j)
         if (seen[j] != 1) { std::printf("FAIL triangle %ld referenced %d times\n", j, seen[j]); return 1; }
+    // the top levels come first, breadth-first: the k-th inner node met from the root, level by
+    // level and in child-slot order, has index k for k < kTopNodes
+    {
+        std::vector<int32_t> q(1, 0);
+        for (size_t h = 0; h < q.size() && (long)q.size() < kTopNodes; ++h)
+            for (int i = 0; i < 4 && (long)q.size() < kTopNodes; ++i) {
+                const int32_t c = B.nodes[q[h]].child[i];
+                if (c >= 0 && c != kEmptyChild) q.push_back(c);
+            }
+        for (size_t k = 0; k < q.size(); ++k)
+            if (q[k] != (int32_t)k) { std::printf("FAIL top node %zu at index %d\n", k, q[k]); return 1; }
+    }
     const int stack_cap = 3 * (B.depth + 1) + 1;
     // traversal replay
     long nr;
