@@ -12,8 +12,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
-def checker():
-    exe = "/tmp/grwave_bvh_check"
+def checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("bvh") / "grwave_bvh_check")
     srcs = [os.path.join(ROOT, "tests", "bvh_check.cpp"),
             os.path.join(ROOT, "paper_2303_15762_amd", "csrc", "bvh_build.cpp")]
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-o", exe] + srcs)
@@ -69,8 +69,8 @@ def test_bvh_structure_and_traversal(checker, case):
 # --------------------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
-def bchecker():
-    exe = "/tmp/grwave_boundary_check"
+def bchecker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("boundary") / "grwave_boundary_check")
     srcs = [os.path.join(ROOT, "tests", "boundary_check.cpp"),
             os.path.join(ROOT, "paper_2303_15762_amd", "csrc", "boundary.cpp")]
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-o", exe] + srcs)
