@@ -53,8 +53,8 @@ SHADOW_QUEUE_BYTES = 2 * 48 + 2 * 4   # a queued shadow ray written and read, it
 # merge kernels), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
 # size; valid only for the kernel sources it was measured on (sha256 prefix of the files
 # below).
-TRAFFIC_BYTES = {"mid": 2_903_256 * 1024, "large": 113_315_045 * 1024}
-TRAFFIC_KERNEL_HASH = "0cbd968a0e7df530"
+TRAFFIC_BYTES = {"mid": 2_902_957 * 1024, "large": 113_310_094 * 1024}
+TRAFFIC_KERNEL_HASH = "47de2e4cc294c49d"
 KERNEL_SOURCES = ["paper_2303_15762_amd/csrc/trace.hip", "paper_2303_15762_amd/csrc/trace_core.hpp",
                   "paper_2303_15762_amd/csrc/device_math.hpp",
                   "paper_2303_15762_amd/csrc/kernels.hpp", "paper_2303_15762_amd/csrc/composite.hpp",
@@ -206,6 +206,14 @@ def surrogate_leg(R, wl, img_plain, ms_plain, pix, ref, steps, args):
                       "surrogate_evals_per_step": st["surrogate_evals"],
                       "fallbacks_per_step": st["fallbacks"],
                       "frame_time_vs_plain": round(ms / ms_plain, 4)}
+        meas = {k: st["measured_" + k] for k in ("smooth", "rough", "grating")}
+    # measurements per material class: the network covers rough surfaces inside its trained
+    # domain; smooth and grating surfaces and the other rough ones keep the closed form
+    n_meas = max(1, sum(meas.values()))
+    by_class = {"measurements_per_step": meas,
+                "share_of_measurements": {k: round(v / n_meas, 4) for k, v in meas.items()},
+                "rough_in_domain_share": round(legs["bf16"]["surrogate_evals_per_step"] / max(1, meas["rough"]), 4),
+                "network_share_of_measurements": round(legs["bf16"]["surrogate_evals_per_step"] / n_meas, 4)}
     # the network alone on the matrix cores: 4M encoded queries, both operand types; and the
     # in-domain queries through gr_bsdf_eval, closed form against network
     x, _, q = S.samples(1 << 22, seed=77, with_queries=True)
@@ -240,7 +248,7 @@ def surrogate_leg(R, wl, img_plain, ms_plain, pix, ref, steps, args):
     legs["fp8"]["roofline"] = mfma["fp8"]
     n_in = legs["bf16"]["surrogate_evals_per_step"]
     cf_ms = n_in * per_query["closed_form"] * 1e-6
-    out = {"bf16": legs["bf16"], "fp8": legs["fp8"],
+    out = {"bf16": legs["bf16"], "fp8": legs["fp8"], "by_material": by_class,
            "train_s": round(t_train, 2), "train_steps": hist["step"][-1],
            "val_mse_log_pw": hist["val_loss"][-1],
            # the in-domain queries in full waves through gr_bsdf_eval: the closed form's cost the

@@ -182,6 +182,10 @@ typedef struct {
     uint64_t node_visits;       /* BVH nodes fetched (closest-hit and any-hit) */
     uint64_t tri_tests;         /* triangle tests (closest-hit and any-hit) */
     uint64_t composite;         /* interactions that met a material boundary (GR_TRACE_COMPOSITE) */
+    uint64_t measured_smooth;   /* vertices that evaluated a measurement (an emitter direction on
+                                   the lit side of the geometric and shading normals), at smooth, */
+    uint64_t measured_rough;    /* rough */
+    uint64_t measured_grating;  /* and grating surfaces; their sum is shadow_rays */
     float ms;                   /* device time of the path-tracing kernels (trace, network
                                    pass, shadow rays, record merge) */
     float ms_reduce;            /* device time of the per-pixel reduction */

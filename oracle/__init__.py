@@ -438,7 +438,7 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
         npix = pix.shape[0]
     img = np.zeros((nl, npix))
     paths = np.zeros((spp_count, npix, nl)) if keep_paths else None
-    stats = (C.c_uint64 * 5)()
+    stats = (C.c_uint64 * 8)()
     i32p = C.POINTER(C.c_int32)
     rc = L.or_trace(oscene.h, C.byref(sen), srcs, len(wl.sources), _dp(lam), nl, C.byref(op),
                     pix.ctypes.data_as(i32p) if pix is not None else None, npix, _dp(img),
@@ -446,7 +446,8 @@ def render(wl, oscene=None, pixels=None, spp_begin=0, spp_count=None, spp_norm=N
     if rc != 0:
         raise RuntimeError("oracle trace failed")
     st = dict(segments=stats[0], shadow_rays=stats[1], evanescent=stats[2], backfacing=stats[3],
-              composite=stats[4])
+              composite=stats[4], measured_smooth=stats[5], measured_rough=stats[6],
+              measured_grating=stats[7])
     if pixels is None:
         img = img.reshape(nl, wl.sensor.height, wl.sensor.width)
     if keep_paths:

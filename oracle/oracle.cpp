@@ -680,7 +680,12 @@ bool trace_ray(const SceneO& S, V3 o, V3 d, double tmin, double tmax, bool use_b
 // "Interactive Rendering": rays are traced as rays, the generalized-ray parameters are
 // carried along; measurement by next-event estimation at every interaction).
 // ------------------------------------------------------------------------------------------
-struct Stats { uint64_t segments = 0, shadow = 0, evanescent = 0, backfacing = 0, composite = 0; };
+// measured[kind]: vertices that evaluated a measurement (an emitter direction on the lit side
+// of both normals), by the material kind of the hit (0 smooth, 1 rough, 2 grating)
+struct Stats {
+    uint64_t segments = 0, shadow = 0, evanescent = 0, backfacing = 0, composite = 0;
+    uint64_t measured[3] = {0, 0, 0};
+};
 
 struct Ctx {
     const SceneO* S;
@@ -1123,6 +1128,7 @@ double trace_path(const Ctx& C, int px, int py, int64_t s, int w, Stats& st, std
             bool ok = nee_direction(L, v.P, k, unif(rn.v[1]), unif(rn.v[2]), om, tmax, tt);
             if (ok && dot(om, v.ng) < 0.0 && dot(om, v.ns) < 0.0) {
                 st.shadow++;
+                st.measured[m.kind]++;
                 Hit hs;
                 bool occ = trace_ray(S, v.P, -1.0 * om, t_eps(v.P), tmax, op.use_bvh != 0, true, hs, h.tri);
                 if (!occ) {
@@ -1222,6 +1228,7 @@ void trace_path_hero(const Ctx& C, int px, int py, int64_t s, int grp, Stats& st
             bool ok = nee_direction(L, v.P, kh, unif(rn.v[1]), unif(rn.v[2]), om, tmax, tt);
             if (ok && dot(om, v.ng) < 0.0 && dot(om, v.ns) < 0.0) {
                 st.shadow++;
+                st.measured[m.kind]++;
                 Hit hs;
                 bool occ = trace_ray(S, v.P, -1.0 * om, t_eps(v.P), tmax, op.use_bvh != 0, true, hs, h.tri);
                 if (!occ) {
@@ -1553,7 +1560,8 @@ void or_interaction(void* s, const double* ray, double k, const double* u, doubl
 // Render.  pixels: optional list of (x, y) pairs (npix of them); when null, every pixel of
 // the sensor in row-major order.  image: [nl][npix].  paths (optional):
 // [spp_count][npix][nl] per-path contributions (already divided by spp_norm).
-// stats: [segments, shadow rays, evanescent kills, backfacing kills, composite interactions].
+// stats: [segments, shadow rays, evanescent kills, backfacing kills, composite interactions,
+// measurements at smooth, rough and grating surfaces].
 int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
              const double* lambdas, int32_t nl, const or_opts* op, const int32_t* pixels,
              int64_t npix, double* image, double* paths, uint64_t* stats) {
@@ -1607,10 +1615,11 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
     std::vector<std::thread> th;
     for (int i = 0; i < nt; ++i) th.emplace_back(work, i);
     for (auto& t : th) t.join();
-    uint64_t tot[5] = {0, 0, 0, 0, 0};
+    uint64_t tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (auto& st : sts) {
         tot[0] += st.segments; tot[1] += st.shadow; tot[2] += st.evanescent; tot[3] += st.backfacing;
         tot[4] += st.composite;
+        for (int i = 0; i < 3; ++i) tot[5 + i] += st.measured[i];
     }
     if (stats) std::memcpy(stats, tot, sizeof(tot));
     return 0;

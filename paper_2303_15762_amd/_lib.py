@@ -53,8 +53,9 @@ class GrStats(C.Structure):
                 ("surrogate_evals", C.c_uint64), ("fallbacks", C.c_uint64),
                 ("evanescent", C.c_uint64), ("backfacing", C.c_uint64),
                 ("nonfinite", C.c_uint64), ("node_visits", C.c_uint64),
-                ("tri_tests", C.c_uint64), ("composite", C.c_uint64), ("ms", C.c_float),
-                ("ms_reduce", C.c_float)]
+                ("tri_tests", C.c_uint64), ("composite", C.c_uint64),
+                ("measured_smooth", C.c_uint64), ("measured_rough", C.c_uint64),
+                ("measured_grating", C.c_uint64), ("ms", C.c_float), ("ms_reduce", C.c_float)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

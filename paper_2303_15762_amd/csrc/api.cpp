@@ -649,6 +649,9 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
         st->node_visits = h[grw::ST_NODES];
         st->tri_tests = h[grw::ST_TRIS];
         st->composite = h[grw::ST_COMPOSITE];
+        st->measured_smooth = h[grw::ST_MEAS_SMOOTH];
+        st->measured_rough = h[grw::ST_MEAS_ROUGH];
+        st->measured_grating = h[grw::ST_MEAS_GRATING];
         st->ms = ms;
         st->ms_reduce = ms_r;
     }

@@ -114,8 +114,9 @@ struct TraceArgs {
 
 enum {
     ST_PATHS = 0, ST_SEGMENTS, ST_SHADOW, ST_SUR, ST_FALLBACK, ST_EVANESCENT, ST_BACKFACING,
-    ST_NONFINITE, ST_NODES, ST_TRIS, ST_COMPOSITE, ST_COUNT
+    ST_NONFINITE, ST_NODES, ST_TRIS, ST_COMPOSITE, ST_MEAS_SMOOTH, ST_MEAS_ROUGH, ST_MEAS_GRATING, ST_COUNT
 };
+static_assert(ST_COUNT <= 16, "the statistics array holds 16 counters");
 
 // Launchers (trace.hip).
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s);

@@ -281,7 +281,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     // traversal work per lane; the per-path events are flagged per lane (one bit each) and
     // counted per wave with ballots, which keeps the counts in scalar registers
     uint32_t c_nodes = 0, c_tris = 0;
-    unsigned long long w_cnt[EV_COUNT] = {};
+    // (32-bit: a launch holds at most 2^30 (path, interaction) slots, so no count of it reaches
+    // 2^31; the narrower counters leave scalar registers to the rest of the kernel)
+    uint32_t w_cnt[EV_COUNT] = {};
 
     while (true) {
         uint32_t ev = 0;
@@ -530,6 +532,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         // the four members' values now (their slot holds four floats), the
                         // visibility later (shadow_kernel clears all four)
                         ev |= 1u << EV_SHADOW;
+                        ev |= 1u << (EV_MEAS_SMOOTH + m.kind);
                         const uint32_t slot = (uint32_t)((idx - A.path_begin) * (uint64_t)A.max_depth + depth);
                         // members: emitter-sampling density of om relative to the hero's
                         // (Gaussian angular spectrum N(k u_t; 0, rc^-2 I) k^2), then the
@@ -581,6 +584,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                       if (ok && dot3(om, ng) < 0.0f && dot3(om, ns) < 0.0f) {
                         // the measurement value now, its visibility later (shadow_kernel)
                         ev |= 1u << EV_SHADOW;
+                        ev |= 1u << (EV_MEAS_SMOOTH + m.kind);
                         const float kix = k * dot3(om, xa), kiy = k * dot3(om, ya);
                         const float kox = -k * dx, koy = -k * dy;
                         const float scale = alpha * L.power * (float)A.nsrc;
@@ -771,22 +775,25 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
             live = false;
         }
 #pragma unroll
-        for (int b = 0; b < EV_COUNT; ++b) w_cnt[b] += (unsigned long long)__popcll(__ballot((ev >> b) & 1u));
+        for (int b = 0; b < EV_COUNT; ++b) w_cnt[b] += (uint32_t)__popcll(__ballot((ev >> b) & 1u));
     }
 
     const unsigned long long s8 = wave_sum(c_nodes), s9 = wave_sum(c_tris);
     if (lane == 0) {
-        atomicAdd(A.stats + ST_PATHS, w_cnt[EV_PATH]);
-        atomicAdd(A.stats + ST_SEGMENTS, w_cnt[EV_SEG]);
-        atomicAdd(A.stats + ST_SHADOW, w_cnt[EV_SHADOW]);
-        atomicAdd(A.stats + ST_EVANESCENT, w_cnt[EV_EVANESCENT]);
-        atomicAdd(A.stats + ST_BACKFACING, w_cnt[EV_BACKFACING]);
-        atomicAdd(A.stats + ST_NONFINITE, w_cnt[EV_NONFINITE]);
+        atomicAdd(A.stats + ST_PATHS, (unsigned long long)w_cnt[EV_PATH]);
+        atomicAdd(A.stats + ST_SEGMENTS, (unsigned long long)w_cnt[EV_SEG]);
+        atomicAdd(A.stats + ST_SHADOW, (unsigned long long)w_cnt[EV_SHADOW]);
+        atomicAdd(A.stats + ST_EVANESCENT, (unsigned long long)w_cnt[EV_EVANESCENT]);
+        atomicAdd(A.stats + ST_BACKFACING, (unsigned long long)w_cnt[EV_BACKFACING]);
+        atomicAdd(A.stats + ST_NONFINITE, (unsigned long long)w_cnt[EV_NONFINITE]);
         atomicAdd(A.stats + ST_NODES, s8);
         atomicAdd(A.stats + ST_TRIS, s9);
-        atomicAdd(A.stats + ST_SUR, w_cnt[EV_SUR]);
-        atomicAdd(A.stats + ST_FALLBACK, w_cnt[EV_FALLBACK]);
-        atomicAdd(A.stats + ST_COMPOSITE, w_cnt[EV_COMPOSITE]);
+        atomicAdd(A.stats + ST_SUR, (unsigned long long)w_cnt[EV_SUR]);
+        atomicAdd(A.stats + ST_FALLBACK, (unsigned long long)w_cnt[EV_FALLBACK]);
+        atomicAdd(A.stats + ST_COMPOSITE, (unsigned long long)w_cnt[EV_COMPOSITE]);
+        atomicAdd(A.stats + ST_MEAS_SMOOTH, (unsigned long long)w_cnt[EV_MEAS_SMOOTH]);
+        atomicAdd(A.stats + ST_MEAS_ROUGH, (unsigned long long)w_cnt[EV_MEAS_ROUGH]);
+        atomicAdd(A.stats + ST_MEAS_GRATING, (unsigned long long)w_cnt[EV_MEAS_GRATING]);
     }
 }
 

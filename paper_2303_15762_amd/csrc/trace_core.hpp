@@ -348,7 +348,11 @@ __device__ __forceinline__ unsigned long long wave_sum(uint32_t v) {
     return x;
 }
 
-enum { EV_PATH = 0, EV_SEG, EV_SHADOW, EV_SUR, EV_FALLBACK, EV_EVANESCENT, EV_BACKFACING, EV_NONFINITE, EV_COMPOSITE, EV_COUNT };
+// EV_MEAS_SMOOTH + kind: a vertex that evaluated a measurement at a surface of that kind
+enum {
+    EV_PATH = 0, EV_SEG, EV_SHADOW, EV_SUR, EV_FALLBACK, EV_EVANESCENT, EV_BACKFACING, EV_NONFINITE, EV_COMPOSITE,
+    EV_MEAS_SMOOTH, EV_MEAS_ROUGH, EV_MEAS_GRATING, EV_COUNT
+};
 
 // bfloat16 pair (a in the low half), rounded to nearest even as the network's input stage does.
 __device__ __forceinline__ uint32_t bf16_pair(float a, float b) {

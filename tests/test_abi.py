@@ -35,7 +35,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(L.GrSensor) == 64
     assert C.sizeof(L.GrSource) == 60
     assert C.sizeof(L.GrTraceOpts) == 56
-    assert C.sizeof(L.GrStats) == 96
+    assert C.sizeof(L.GrStats) == 120
     assert C.sizeof(L.GrSceneInfo) == 40
 
 

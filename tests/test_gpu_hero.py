@@ -61,6 +61,9 @@ def test_hero_terrain_small_ragged_matches_oracle(R):
     assert st["paths"] == 41 * 29 * 16 * 2
     assert st["nonfinite"] == 0
     assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    for kind in ("smooth", "rough", "grating"):
+        key = "measured_" + kind
+        assert ost[key] > 0 and abs(st[key] - ost[key]) <= 1e-3 * ost[key] + 2, (key, st[key], ost[key])
     assert e <= RTOL_IMAGE
     # records: [s, y, x, lambda] on the GPU, [s, pixel, lambda] in the oracle
     opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed,

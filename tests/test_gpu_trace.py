@@ -47,6 +47,9 @@ def test_tiny_grating_matches_oracle(R):
     assert st["paths"] == 32 * 32 * 8
     assert st["segments"] == ost["segments"]
     assert st["shadow_rays"] == ost["shadow_rays"]
+    # one grating: every measurement is counted in its class
+    assert st["measured_grating"] == ost["measured_grating"] == st["shadow_rays"] > 0
+    assert st["measured_smooth"] == st["measured_rough"] == 0
     assert rel_l2(g, o) <= 1e-5
     # interior pixel values agree one by one
     np.testing.assert_allclose(g[0, 4:28, 4:28], o[0, 4:28, 4:28], rtol=1e-5)
@@ -124,6 +127,11 @@ def test_terrain_small_ragged_matches_oracle(R):
     print("terrain 41x29: rel L2", e, st, ost)
     assert st["paths"] == 41 * 29 * 16 * 8
     assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    # measurements per material class (smooth, rough and grating tiles)
+    for kind in ("smooth", "rough", "grating"):
+        key = "measured_" + kind
+        assert ost[key] > 0 and abs(st[key] - ost[key]) <= 1e-3 * ost[key] + 2, (key, st[key], ost[key])
+    assert st["measured_smooth"] + st["measured_rough"] + st["measured_grating"] == st["shadow_rays"]
     assert e <= RTOL_IMAGE
 
 

@@ -248,3 +248,31 @@ def test_rough_pw_matches_monte_carlo_over_surfaces():
         ref = oracle.pw(1, s_um, ell, k, (0.0, 0.0), (kx, 0.0), S)
         assert se < 0.06 * ref
         assert abs(mc - ref) <= 4.0 * se, (kx, mc, ref, se)
+
+
+# --------------------------------------------------------------------------------------
+# Measurements counted per material class
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("left,right", [(W.SMOOTH, W.ROUGH), (W.GRATING, W.SMOOTH), (W.ROUGH, W.GRATING)])
+def test_measurements_are_counted_by_the_material_hit(left, right):
+    """Split mirror: every path meets the surface once at normal incidence and measures the
+    plane wave there, so the count of each class is the number of paths landing on its half:
+    pixels 0-31 of each 64-pixel row see x < 0, pixels 32-63 see x > 0."""
+    def mat(kind):
+        return W.Material(kind, height_um=0.05 if kind != W.SMOOTH else 0.0, length_um=2.0,
+                          gdir=(0.0, 1.0, 0.0), reflectance=0.5)
+    wl = W.split_mirror(width=64, height=4, spp=4, left=mat(left), right=mat(right))
+    _, st = oracle.render(wl)
+    names = {W.SMOOTH: "measured_smooth", W.ROUGH: "measured_rough", W.GRATING: "measured_grating"}
+    half = 32 * 4 * 4
+    assert st[names[left]] == half and st[names[right]] == half
+    assert sum(st[n] for n in names.values()) == 2 * half == st["shadow_rays"]
+
+
+def test_measurement_classes_add_up_on_terrain():
+    wl = _terrain(4, False, width=24, height=16, spp=4)
+    _, st = oracle.render(wl)
+    parts = [st["measured_smooth"], st["measured_rough"], st["measured_grating"]]
+    print("terrain measurements by class", parts, st["shadow_rays"])
+    assert sum(parts) == st["shadow_rays"] and min(parts) > 0
