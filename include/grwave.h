@@ -342,6 +342,12 @@ int gr_mlp_forward(gr_ctx* ctx, const float* params, const float* x, int64_t n, 
  * float [13249], overwritten; deterministic) and the loss into loss_dev (device float [1]). */
 int gr_mlp_backward(gr_ctx* ctx, const float* params, const float* x, const float* target,
                     int64_t n, void* workspace, float* grad, float* loss_dev);
+/* The network's activation, GELU in its tanh form x / (1 + 2^(x (a + b x^2))) with
+ * a = -2 sqrt(2/pi) log2(e), b = 0.044715 a, and its derivative, elementwise in float as the
+ * forward and backward kernels compute them (for checking them on their own): y[i] = GELU(x[i]),
+ * dy[i] = GELU'(x[i]), i < n.  x, y, dy: device float [n] (n = 0 does nothing).  Asynchronous
+ * on the context's stream. */
+int gr_mlp_activation(gr_ctx* ctx, const float* x, int64_t n, float* y, float* dy);
 /* Adam (Kingma & Ba, bias-corrected) update of params in place; m, v device float [13249]
  * moments (start at zero); step t >= 1. */
 int gr_adam_step(gr_ctx* ctx, float* params, const float* grad, float* m, float* v, int32_t t,

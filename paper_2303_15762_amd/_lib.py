@@ -100,6 +100,7 @@ SIGNATURES = [
     ("gr_mlp_workspace_size", C.c_int, [C.c_int64, C.POINTER(C.c_size_t)]),
     ("gr_mlp_forward", C.c_int, [_vp, _fp, _fp, C.c_int64, C.c_int32, _vp, _fp]),
     ("gr_mlp_backward", C.c_int, [_vp, _fp, _fp, _fp, C.c_int64, _vp, _fp, _fp]),
+    ("gr_mlp_activation", C.c_int, [_vp, _fp, C.c_int64, _fp, _fp]),
     ("gr_adam_step", C.c_int, [_vp, _fp, _fp, _fp, _fp, C.c_int32, C.c_float, C.c_float,
                                C.c_float, C.c_float]),
     ("gr_set_surrogate", C.c_int, [_vp, _fp, _fp]),

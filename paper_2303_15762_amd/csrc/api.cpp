@@ -748,6 +748,15 @@ int gr_mlp_backward(gr_ctx* c, const float* params, const float* x, const float*
     return GR_OK;
 }
 
+int gr_mlp_activation(gr_ctx* c, const float* x, int64_t n, float* y, float* dy) {
+    if (!c) return GR_E_INVALID;
+    if (n < 0 || n > ((int64_t)1 << 40) || (n > 0 && (!x || !y || !dy)))
+        return fail(c, GR_E_INVALID, "mlp_activation: arguments");
+    GR_HIP(c, hipSetDevice(c->device));
+    GR_HIP(c, grw::activation(x, n, y, dy, c->stream));
+    return GR_OK;
+}
+
 int gr_adam_step(gr_ctx* c, float* p, const float* g, float* m, float* v, int32_t t, float lr, float b1, float b2,
                  float eps) {
     if (!c) return GR_E_INVALID;

@@ -573,6 +573,23 @@ hipError_t mlp_backward(const float* params, const float* x, const float* t, int
     return hipGetLastError();
 }
 
+// The network's activation and its derivative, elementwise, as the forward and backward
+// kernels compute them.
+__global__ __launch_bounds__(256) void activation_kernel(const float* __restrict__ x, int64_t n,
+                                                         float* __restrict__ y, float* __restrict__ dy) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float v = x[i];
+    y[i] = gelu_f(v);
+    dy[i] = gelu_grad_f(v);
+}
+
+hipError_t activation(const float* x, int64_t n, float* y, float* dy, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(activation_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, y, dy);
+    return hipGetLastError();
+}
+
 hipError_t adam(float* p, const float* g, float* m, float* v, int t, float lr, float b1, float b2, float eps,
                 hipStream_t s) {
     const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);

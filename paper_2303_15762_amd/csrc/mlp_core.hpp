@@ -54,10 +54,11 @@ __device__ __forceinline__ float gelu_gate(float x) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a));
 }
 __device__ __forceinline__ float gelu_f(float x) { return x * gelu_gate(x); }
-// d/dx [x s] = s + x s (1 - s) 2 y', y' = sqrt(2/pi) (1 + 3 * 0.044715 x^2)
+// d/dx [x s] = s + x s (1 - s) 2 y', y' = sqrt(2/pi) (1 + 3 * 0.044715 x^2).  x^2 is capped so
+// that y' stays finite where s (1 - s) is 0 (|x| beyond 1e15; uncapped, 0 * inf would give NaN).
 __device__ __forceinline__ float gelu_grad_f(float x) {
     const float sg = gelu_gate(x);
-    return sg + x * sg * (1.0f - sg) * (2.0f * 0.7978845608028654f) * fmaf(0.134145f, x * x, 1.0f);
+    return sg + x * sg * (1.0f - sg) * (2.0f * 0.7978845608028654f) * fmaf(0.134145f, fminf(x * x, 1e30f), 1.0f);
 }
 
 // Round-to-nearest-even float -> bfloat16 (v_cvt_pk_bf16_f32 on gfx950).

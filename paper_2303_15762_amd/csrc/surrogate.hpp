@@ -28,6 +28,8 @@ size_t mlp_workspace_bytes(int64_t n);
 hipError_t mlp_forward(const float* params, const float* x, int64_t n, bool fp8, void* ws, float* y, hipStream_t s);
 hipError_t mlp_backward(const float* params, const float* x, const float* t, int64_t n, void* ws, float* grad,
                         float* loss, hipStream_t s);
+// y[i] = GELU(x[i]), dy[i] = GELU'(x[i]) for i < n (the kernels' float forms)
+hipError_t activation(const float* x, int64_t n, float* y, float* dy, hipStream_t s);
 hipError_t adam(float* p, const float* g, float* m, float* v, int t, float lr, float b1, float b2, float eps,
                 hipStream_t s);
 hipError_t surrogate_samples(int64_t n, uint64_t seed, const float* domain, float* x, float* y, float* q,

@@ -98,6 +98,15 @@ class Surrogate:
                     "gr_mlp_backward")
         return grad, loss
 
+    def activation(self, x):
+        """The network's GELU and its derivative at x (device float), as the kernels compute them."""
+        tt = self.torch
+        y = tt.empty_like(x)
+        dy = tt.empty_like(x)
+        self._check(self.lib.gr_mlp_activation(self.R.h, _fp(x), int(x.numel()), _fp(y), _fp(dy)),
+                    "gr_mlp_activation")
+        return y, dy
+
     def adam(self, params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self._check(self.lib.gr_adam_step(self.R.h, _fp(params), _fp(grad), _fp(m), _fp(v), int(step),
                                           float(lr), float(b1), float(b2), float(eps)), "gr_adam_step")

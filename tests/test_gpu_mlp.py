@@ -170,3 +170,47 @@ def test_training_reduces_loss(env):
     p, hist = S.train(n_train=1 << 18, batch=8192, steps=300, lr=2e-3, log_every=100)
     print(hist)
     assert hist["val_loss"][-1] < 0.1 * hist["val_loss"][0]
+
+
+def _activation_check(x, y, dy):
+    """Device GELU values y and derivatives dy at float32 points x against the oracle's FP64
+    forms.  The oracle's 1 + tanh cancels for x below about -3 (its relative accuracy there is
+    1e-16 / (1 + tanh)), so values whose gate is below 1e-6 are compared absolutely.  Returns
+    the largest relative errors (gate >= 1e-6) of GELU and of its derivative."""
+    xd = x.astype(np.float64)
+    ry = omlp.gelu(xd)
+    rdy = omlp.gelu_grad(xd)
+    # |a|, the exponent of the device's 2^a, capped where it no longer matters
+    a = np.minimum(np.abs(xd * (2.0 * math.sqrt(2.0 / math.pi) / math.log(2.0)) * (1.0 + 0.044715 * xd * xd)), 200.0)
+    gate = np.where(xd != 0.0, ry / np.where(xd != 0.0, xd, 1.0), 0.5)
+    rel_zone = (gate >= 1e-6) & (xd != 0.0)
+    rel = np.abs(y[rel_zone] - ry[rel_zone]) / np.abs(ry[rel_zone])
+    # the exponent's three float roundings move 2^a by up to ln2 |a| 3 2^-24 relatively, plus a
+    # few ulps of exp2, reciprocal and products
+    assert np.all(rel <= 1.3e-7 * a[rel_zone] + 6e-7), float(rel.max())
+    assert np.all(np.abs(y[~rel_zone] - ry[~rel_zone]) <= 1e-11 * np.maximum(1.0, np.abs(xd[~rel_zone])))
+    # the derivative crosses zero near x = -0.75: compared against max(1, |GELU'|)
+    errd = np.abs(dy - rdy) / np.maximum(1.0, np.abs(rdy))
+    assert np.all(errd <= 1.3e-7 * a + 1e-6), float(errd.max())
+    return float(rel.max()), float(errd.max())
+
+
+def test_activation_matches_oracle(env):
+    """The kernels' GELU (tanh form through one exp2 and one reciprocal) and its derivative, in
+    float, against the oracle's FP64 forms on a dense grid, and saturation at large |x|."""
+    R, S, torch = env
+    x = np.linspace(-12.0, 12.0, 240001).astype(np.float32)
+    y, dy = S.activation(torch.tensor(x, device=R.dev))
+    y = y.cpu().numpy().astype(np.float64)
+    dy = dy.cpu().numpy().astype(np.float64)
+    assert np.all(np.isfinite(y)) and np.all(np.isfinite(dy))
+    e, ed = _activation_check(x, y, dy)
+    core = np.abs(x) <= 4.0
+    ec, edc = _activation_check(x[core], y[core], dy[core])
+    print("gelu max rel error", e, "(|x| <= 4:", ec, ") derivative", ed, "(|x| <= 4:", edc, ")")
+    big = np.array([-1e20, -1e4, -50.0, 50.0, 1e4, 1e20], np.float32)
+    yb, dyb = S.activation(torch.tensor(big, device=R.dev))
+    yb = yb.cpu().numpy()
+    dyb = dyb.cpu().numpy()
+    assert np.array_equal(yb[big > 0], big[big > 0]) and np.all(yb[big < 0] == 0.0)
+    assert np.all(dyb[big > 0] == 1.0) and np.all(dyb[big < 0] == 0.0)
