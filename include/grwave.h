@@ -150,9 +150,11 @@ enum {
  *                          gr_pw_composite_eval) and the continuation samples the far side's
  *                          unwindowed kernel with the probability of the window's intensity mass
  *                          beyond the boundary, else the near side's.  Needs gr_scene_boundaries
- *                          (else GR_E_NO_SCENE); scalar rays, the closed-form p_w and one
- *                          wavelength per path only (else GR_E_UNSUPPORTED).  Other bits are
- *                          invalid. */
+ *                          (else GR_E_NO_SCENE); scalar rays and one wavelength per path only
+ *                          (else GR_E_UNSUPPORTED).  With a surrogate bsdf_mode the composite
+ *                          measurements keep the closed form (the network holds one material's
+ *                          p_w) and the other rough ones in the trained domain go to the
+ *                          network.  Other bits are invalid. */
 typedef struct {
     int64_t spp_begin;
     int64_t spp_count;

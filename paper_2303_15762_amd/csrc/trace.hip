@@ -592,7 +592,9 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                         // e: 0 closed form, 1 queued for the network, 2 more than 8 lobe widths
                         // from the lobe (p_w taken as 0)
                         int e = 0;
-                        if (DEFER && m.kind == MAT_ROUGH) {
+                        // (a composite interaction keeps the closed form: the network knows one
+                        // material's p_w only)
+                        if (DEFER && m.kind == MAT_ROUGH && !(COMPOSITE && comp)) {
                             const SurDomain D{A.sur.gmin, A.sur.gmax, A.sur.smin, A.sur.smax};
                             float sx[MLP_IN] = {}, slp = 0.0f;
                             e = sur_encode(D, k, kix, kiy, kox, koy, sxx, syy, sxy, m.h, m.L, sx, slp);
@@ -937,14 +939,16 @@ static int grid_for(int device) {
 }
 
 int trace_grid_size(int device, bool sur, bool hero, bool aniso, bool composite) {
-    if (composite) return grid_for<false, false, false, true>(device);
+    if (composite) return sur ? grid_for<true, false, false, true>(device) : grid_for<false, false, false, true>(device);
     if (aniso) return grid_for<false, false, true>(device);
     if (hero) return grid_for<false, true>(device);
     return sur ? grid_for<true, false>(device) : grid_for<false, false>(device);
 }
 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.composite)
+    if (a.composite && a.bsdf_mode != 0)
+        hipLaunchKernelGGL((trace_kernel<kLdsStack, true, false, false, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (a.composite)
         hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.aniso) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.hero) hipLaunchKernelGGL((trace_kernel<kLdsStack, false, true>), dim3(grid), dim3(256), 0, s, a);
