@@ -1568,7 +1568,7 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
     if (!s || !sen || !op || nl <= 0 || op->spp_count < 0 || op->max_depth < 0) return -1;
     if (op->hero && nl % 4 != 0) return -1;
     if (op->hero && op->aniso) return -1;   // hero paths carry scalar beta, rho
-    if (op->composite && (op->hero || op->aniso || !((const SceneO*)s)->have_bedges)) return -1;
+    if (op->composite && (op->hero || !((const SceneO*)s)->have_bedges)) return -1;
     const SceneO* S = (const SceneO*)s;
     if (!pixels) npix = (int64_t)sen->width * sen->height;
     Ctx C{S, sen, src, nsrc, lambdas, nl, op};

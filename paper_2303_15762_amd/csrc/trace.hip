@@ -939,6 +939,7 @@ static int grid_for(int device) {
 }
 
 int trace_grid_size(int device, bool sur, bool hero, bool aniso, bool composite) {
+    if (composite && aniso) return grid_for<false, false, true, true>(device);
     if (composite) return sur ? grid_for<true, false, false, true>(device) : grid_for<false, false, false, true>(device);
     if (aniso) return grid_for<false, false, true>(device);
     if (hero) return grid_for<false, true>(device);
@@ -946,7 +947,9 @@ int trace_grid_size(int device, bool sur, bool hero, bool aniso, bool composite)
 }
 
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
-    if (a.composite && a.bsdf_mode != 0)
+    if (a.composite && a.aniso)
+        hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, true, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (a.composite && a.bsdf_mode != 0)
         hipLaunchKernelGGL((trace_kernel<kLdsStack, true, false, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.composite)
         hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, false, true>), dim3(grid), dim3(256), 0, s, a);

@@ -103,17 +103,20 @@ def test_pw_composite_matches_oracle(R):
     assert np.all(err <= 2e-4 * ref + 1e-6 * peak)
 
 
-def test_split_mirror_paths_match_oracle(R):
+@pytest.mark.parametrize("aniso", [False, True])
+def test_split_mirror_paths_match_oracle(R, aniso):
     """Two smooth mirrors at a straight boundary, normal incidence: per-path records against
-    the oracle (which is pinned by the closed form of the same scene)."""
+    the oracle (which is pinned by the closed form of the same scene), scalar and anisotropic
+    rays."""
     wl = W.split_mirror(width=64, height=2, spp=4)
     R.load_workload(wl)
     n = R.boundaries(2e-3)
     assert n == 1
-    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=1, seed=wl.seed, keep_paths=True, composite=True)
+    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=1, seed=wl.seed, keep_paths=True, composite=True,
+                  aniso=aniso)
     _, st = R.trace(wl.lambdas_um, opts)
     rec = R.path_records(opts, 1).cpu().numpy().astype(np.float64)
-    img, ost, paths = oracle.render(wl, composite=True, reach_m=2e-3, keep_paths=True)
+    img, ost, paths = oracle.render(wl, composite=True, reach_m=2e-3, keep_paths=True, aniso=aniso)
     print("split mirror: composite", st["composite"], ost["composite"])
     assert st["composite"] == ost["composite"] > 0
     np.testing.assert_allclose(rec.reshape(wl.spp, -1, 1), paths, rtol=2e-5, atol=0)
@@ -206,17 +209,37 @@ def test_terrain_rr_two_sources_depth6(R):
     assert e <= 1e-3
 
 
-def test_terrain_low_resolution_wide_footprints(R):
+@pytest.mark.parametrize("aniso", [False, True])
+def test_terrain_low_resolution_wide_footprints(R, aniso):
     """41 x 29 pixels over the whole terrain: footprints of ~1 mm, every boundary within the
-    2 mm reach."""
+    2 mm reach; scalar and anisotropic rays (the latter's footprints sheared by the oblique
+    reflections before they meet a boundary)."""
     wl = W.as_float32_inputs(W.mid_terrain(width=41, height=29, spp=8, n_lambda=4))
     R.load_workload(wl)
     R.boundaries(2e-3)
-    img, st = R.render_workload(wl, composite=True)
+    img, st = R.render_workload(wl, composite=True, aniso=aniso)
     g = img.cpu().numpy().astype(np.float64)
-    o, ost = oracle.render(wl, composite=True, reach_m=2e-3)
+    o, ost = oracle.render(wl, composite=True, reach_m=2e-3, aniso=aniso)
     e = rel_l2(g, o)
-    print("terrain 41x29 composite: rel L2", e, st["composite"], ost["composite"])
+    print("terrain 41x29 composite (aniso %s): rel L2" % aniso, e, st["composite"], ost["composite"], st["nonfinite"])
+    assert st["nonfinite"] == 0
+    assert abs(st["composite"] - ost["composite"]) <= 1e-3 * ost["composite"] + 2
+    assert e <= 1e-3
+
+
+def test_terrain_window_aniso_matches_oracle(R):
+    """Anisotropic rays with composite interactions on a full-resolution window over tile
+    boundaries (16 samples, 8 wavelengths, depth 4)."""
+    wl = _terrain_window(230, 230)
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    img, st = R.render_workload(wl, composite=True, aniso=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, composite=True, reach_m=2e-3, aniso=True)
+    e = rel_l2(g, o)
+    print("terrain window aniso composite: rel L2", e, "composite", st["composite"], ost["composite"])
+    assert ost["composite"] > 1000
+    assert abs(st["composite"] - ost["composite"]) <= 1e-3 * ost["composite"] + 2
     assert e <= 1e-3
 
 

@@ -366,18 +366,21 @@ def test_split_mirror_composite_geometry_and_side_choice():
     assert r["composite"]
 
 
+@pytest.mark.parametrize("aniso", [False, True])
 @pytest.mark.parametrize("reach_m", [2e-3, 60e-6])
-def test_split_mirror_per_path_closed_form(reach_m):
+def test_split_mirror_per_path_closed_form(reach_m, aniso):
     """Two smooth mirrors (reflectance a_l = 1, a_r = 0.25) meeting at x = 0, normal incidence,
     light at the mirror direction (kappa = 0).  At kappa = 0 the far half-plane's field is half
     the whole window's times erfc(c / (2 s)) (s: the window's intensity std), so a path that
     meets the surface at distance c from the boundary measures
         p_w = (2 s^2 / pi) [sqrt(a_near) (1 - E) + sqrt(a_far) E]^2,  E = erfc(c / (2 s)) / 2,
     inside min(2.5 beta, reach) of the boundary and a_near 2 s^2 / pi beyond it.  The hit point
-    of each path is its pixel position plus the source draw's first two uniforms."""
+    of each path is its pixel position plus the source draw's first two uniforms.  An
+    anisotropic ray (its second moments carried as matrices) starts isotropic and stays so along
+    the axis, so it meets the same closed form."""
     wl = W.split_mirror(width=64, height=2, spp=4)
     k = K550
-    img, st, paths = oracle.render(wl, composite=True, reach_m=reach_m, keep_paths=True)
+    img, st, paths = oracle.render(wl, composite=True, reach_m=reach_m, keep_paths=True, aniso=aniso)
     s2 = _propagated_sigma2(wl.sensor.sigma_m, 0.01, k)
     s = math.sqrt(s2)
     rad = min(2.5 * math.sqrt(2.0 * s2) * 1e-6, reach_m)
