@@ -89,6 +89,7 @@ def lib():
             L.or_sample.argtypes = [C.c_int] + [C.c_double] * 12 + [dp]
             L.or_sample.restype = C.c_int
             L.or_hero_step_batch.argtypes = [C.c_int] + [C.c_double] * 10 + [dp, C.c_int64, dp]
+            L.or_hero_composite_step_batch.argtypes = [dp, dp] + [C.c_double] * 7 + [dp, C.c_int64, dp]
             L.or_scene_create.argtypes = [dp, C.c_int64, dp, C.POINTER(C.c_int32), C.c_int64,
                                           C.POINTER(C.c_int32), C.POINTER(OrMaterial), C.c_int32]
             L.or_scene_create.restype = C.c_void_p
@@ -229,6 +230,21 @@ def hero_step(kind, h, L, kh, kc, ui, ci, U, g=(1.0, 0.0), refl=1.0):
     lib().or_hero_step_batch(int(kind), float(h), float(L), float(refl), float(kh), float(kc),
                              float(ui[0]), float(ui[1]), float(ci), float(g[0]), float(g[1]),
                              _dp(U), U.shape[0], _dp(out))
+    return out
+
+
+def hero_composite_step(near, far, mass_h, mass_c, kh, kc, ui, ci, U):
+    """Hero-wavelength continuation step at a composite interaction for uniforms U [n, 4] (the
+    sampler's three and the side choice).  near / far: (kind, h, L, refl, gx, gy) with the
+    grating direction in the frame; mass_h, mass_c: the hero's and the companion's far masses.
+    Returns [n, 6]: (kox, koy, f_h / p_h, f_c / p_h, p_c / p_h, class of the sampled direction:
+    0 specular, 1 rough lobe, 2 dispersive grating order); NaN rows end the path."""
+    U = np.ascontiguousarray(U, np.float64).reshape(-1, 4)
+    out = np.empty((U.shape[0], 6))
+    nm = np.ascontiguousarray(near, np.float64)
+    fm = np.ascontiguousarray(far, np.float64)
+    lib().or_hero_composite_step_batch(_dp(nm), _dp(fm), float(mass_h), float(mass_c), float(kh), float(kc),
+                                       float(ui[0]), float(ui[1]), float(ci), _dp(U), U.shape[0], _dp(out))
     return out
 
 

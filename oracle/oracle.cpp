@@ -527,6 +527,77 @@ void finf_companion(const Mat& m, double kh, double kc, double ux, double uy, do
     f_ph = m.refl * p_ph;
 }
 
+// Companion ratios at a composite interaction of a hero-wavelength path (reading R31).  The
+// continuation samples the near side's unwindowed kernel with probability 1 - m and the far
+// side's with probability m (the window's intensity mass beyond the boundary), so over the
+// outgoing direction member i meets the mixture (1 - m_i) f_near + m_i f_far, and the hero
+// samples (1 - m_h) p_near + m_h p_far at its own wavenumber.  The sampled direction falls in
+// one of three classes, and only components of that class have mass there:
+//   specular : the mirror direction (smooth; a rough surface's term 0, probability e^-g; a
+//              grating's order 0, probability J_0(m_0)^2 / W): shared by every wavelength;
+//   lobe     : a rough surface's terms n >= 1 (a density over u_o, rough_lobe_density);
+//   order    : a grating order j != 0 of the sampled side, whose direction moves with the
+//              wavelength: the hero's alone.
+// mass[i]: member i's far mass; far_chosen: the side the hero sampled; comp: the sampled
+// component (sample_finf); (ux, uy): incident tangential direction and (dux, duy) = u_o - u_i,
+// both in the near side's frame.  f_ph[i] = f_i / p_h, p_ph[i] = p_i / p_h (1 for the hero).
+void composite_companions(const Side& near, const Side& far, bool far_chosen, const double mass[4],
+                          const double k[4], int hi, double ux, double uy, double ci, double dux, double duy,
+                          int comp, double f_ph[4], double p_ph[4]) {
+    const Side& cs = far_chosen ? far : near;
+    const Mat& cm = *cs.m;
+    const int cls = (cm.kind == 0 || comp == 0) ? 0 : (cm.kind == 1 ? 1 : 2);   // specular, lobe, order
+    const double du2 = dux * dux + duy * duy;
+    const Side* sides[2] = {&near, &far};
+    double f[4], p[4];
+    for (int i = 0; i < 4; ++i) {
+        const double a[2] = {1.0 - mass[i], mass[i]};
+        f[i] = 0.0;
+        p[i] = 0.0;
+        if (cls == 2) {
+            if (i != hi) continue;
+            double W, w0;
+            grating_weights(cm, k[i], k[i] * ux, k[i] * uy, ci, cs.gx, cs.gy, W, w0);
+            const double K = 2.0 * kPi / cm.L;
+            const double ox = k[i] * ux - comp * K * cs.gx, oy = k[i] * uy - comp * K * cs.gy;
+            const double no = (ox * ox + oy * oy) / (k[i] * k[i]);
+            const double bj = besselj(comp, k[i] * cm.h * (ci + std::sqrt(std::max(0.0, 1.0 - no))));
+            const double as = a[far_chosen ? 1 : 0];
+            p[i] = W > 0.0 ? as * bj * bj / W : 0.0;
+            f[i] = as * cm.refl * bj * bj;
+            continue;
+        }
+        for (int sd = 0; sd < 2; ++sd) {
+            const Mat& M = *sides[sd]->m;
+            double ps = 0.0, fs = 0.0;
+            if (cls == 0) {
+                if (M.kind == 0) {
+                    ps = 1.0;
+                    fs = M.refl;
+                } else if (M.kind == 1) {
+                    ps = std::exp(-4.0 * k[i] * k[i] * ci * ci * M.h * M.h);
+                    fs = M.refl * ps;
+                } else {
+                    double W, w0;
+                    grating_weights(M, k[i], k[i] * ux, k[i] * uy, ci, sides[sd]->gx, sides[sd]->gy, W, w0);
+                    ps = W > 0.0 ? w0 / W : 0.0;
+                    fs = M.refl * w0;
+                }
+            } else if (M.kind == 1) {
+                ps = rough_lobe_density(M, k[i], ci, du2);
+                fs = M.refl * ps;
+            }
+            p[i] += a[sd] * ps;
+            f[i] += a[sd] * fs;
+        }
+    }
+    const double ph = p[hi];
+    for (int i = 0; i < 4; ++i) {
+        f_ph[i] = ph > 0.0 ? f[i] / ph : 0.0;
+        p_ph[i] = ph > 0.0 ? p[i] / ph : 0.0;
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Geometry: FP64 Moller-Trumbore intersection, a median-split binary BVH, and brute force.
 // Closest hit: smallest t > eps; equal t resolved to the lower triangle index.
@@ -1218,6 +1289,26 @@ void trace_path_hero(const Ctx& C, int px, int py, int64_t s, int grp, Stats& st
         if (!make_vertex(S, o, d, h, v)) { st.backfacing++; break; }
         const Mat& m = *v.m;
         const double gx = 1.0, gy = 0.0;
+        // Composite interaction (reading R31): the boundary is found with the hero's footprint;
+        // each member's window is the hero's scaled by its beta^2 (same frame and stretch), so
+        // its far mass is erfc(c / sqrt(2 n^T S_i n)) / 2.
+        Side near_side{&m, gx, gy}, far_side{&m, gx, gy};
+        double bnx = 0.0, bny = 0.0, bc = 0.0, mass[4] = {0.0, 0.0, 0.0, 0.0};
+        bool comp = false;
+        if (op.composite) {
+            double sxx, syy, sxy, mf;
+            footprint(v, beta2[hi], sxx, syy, sxy);
+            comp = composite_at(S, v, S.mat[h.tri], sxx, syy, sxy, op.reach_m, far_side, bnx, bny, bc, mf);
+            if (comp) {
+                st.composite++;
+                for (int i = 0; i < 4; ++i) {
+                    double ixx, iyy, ixy;
+                    footprint(v, beta2[i], ixx, iyy, ixy);
+                    const double snn = bnx * bnx * ixx + 2.0 * bnx * bny * ixy + bny * bny * iyy;
+                    mass[i] = 0.5 * std::erfc(bc / std::sqrt(2.0 * snn));
+                }
+            }
+        }
 
         U4 rn = draw(pid, depth, STREAM_NEE, op.seed);
         if (C.nsrc > 0) {
@@ -1245,8 +1336,11 @@ void trace_path_hero(const Ctx& C, int px, int py, int64_t s, int grp, Stats& st
                         if (T[i] == 0.0) continue;
                         double sxx, syy, sxy;
                         footprint(v, beta2[i], sxx, syy, sxy);
-                        double p = pw_eval(m, k[i], k[i] * dot(om, v.xa), k[i] * dot(om, v.ya), -k[i] * v.dx,
-                                           -k[i] * v.dy, sxx, syy, sxy, gx, gy);
+                        const double kix = k[i] * dot(om, v.xa), kiy = k[i] * dot(om, v.ya);
+                        const double kox = -k[i] * v.dx, koy = -k[i] * v.dy;
+                        double p = comp ? pw_composite(near_side, far_side, k[i], kix, kiy, kox, koy, sxx, syy, sxy,
+                                                       bnx, bny, bc)
+                                        : pw_eval(m, k[i], kix, kiy, kox, koy, sxx, syy, sxy, gx, gy);
                         out[i] += 4.0 * T[i] * q[i] * L.power * p * (double)C.nsrc / den;
                     }
                 }
@@ -1255,23 +1349,37 @@ void trace_path_hero(const Ctx& C, int px, int py, int64_t s, int grp, Stats& st
         if (depth + 1 >= op.max_depth) break;
 
         U4 rs = draw(pid, depth, STREAM_SCATTER, op.seed);
+        // at a composite interaction the hero's side as in trace_path (word 3 of the NEE draw,
+        // the hero's far mass)
+        const bool far_chosen = comp && !(unif(rn.v[3]) < 1.0 - mass[hi]);
+        const Side& cs = far_chosen ? far_side : near_side;
         double kix = kh * v.dx, kiy = kh * v.dy, kox, koy, wgt;
-        int ev, comp;
-        if (!sample_finf(m, kh, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), gx, gy,
-                         kox, koy, wgt, ev, &comp)) {
+        int ev, cj;
+        if (!sample_finf(*cs.m, kh, kix, kiy, v.ci, unif(rs.v[0]), unif(rs.v[1]), unif(rs.v[2]), cs.gx, cs.gy,
+                         kox, koy, wgt, ev, &cj)) {
             st.evanescent += ev;
             break;
         }
-        for (int i = 0; i < 4; ++i) {
-            if (i == hi) {
-                T[i] *= wgt;
-                continue;
+        if (comp) {
+            double f_ph[4], p_ph[4];
+            composite_companions(near_side, far_side, far_chosen, mass, k, hi, v.dx, v.dy, v.ci, (kox - kix) / kh,
+                                 (koy - kiy) / kh, cj, f_ph, p_ph);
+            for (int i = 0; i < 4; ++i) {
+                T[i] *= f_ph[i];
+                R[i] *= p_ph[i];
             }
-            double f_ph, p_ph;
-            finf_companion(m, kh, k[i], v.dx, v.dy, v.ci, (kox - kix) / kh, (koy - kiy) / kh, comp, gx, gy,
-                           f_ph, p_ph);
-            T[i] *= f_ph;
-            R[i] *= p_ph;
+        } else {
+            for (int i = 0; i < 4; ++i) {
+                if (i == hi) {
+                    T[i] *= wgt;
+                    continue;
+                }
+                double f_ph, p_ph;
+                finf_companion(m, kh, k[i], v.dx, v.dy, v.ci, (kox - kix) / kh, (koy - kiy) / kh, cj, gx, gy,
+                               f_ph, p_ph);
+                T[i] *= f_ph;
+                R[i] *= p_ph;
+            }
         }
         if (op.rr_enable && depth + 1 >= 2) {
             if (!((rs.v[3] >> 8) < op.rr_threshold24)) break;
@@ -1364,6 +1472,42 @@ void or_hero_step_batch(int kind, double h, double L, double refl, double kh, do
         o[2] = w;
         o[3] = f_ph;
         o[4] = p_ph;
+    }
+}
+
+// One hero-wavelength continuation step at a composite interaction for uniforms u [n][4] (the
+// sampler's three, then the side choice): sides near / far given by their fields (kind, h, L,
+// refl, grating direction in the frame), far masses mass_h (hero) and mass_c (companion).
+// out [n][6]: (kox, koy, f_h / p_h, f_c / p_h, p_c / p_h, class of the sampled direction: 0
+// specular, 1 rough lobe, 2 dispersive grating order); NaN rows end the path.
+void or_hero_composite_step_batch(const double* near_m, const double* far_m, double mass_h, double mass_c, double kh,
+                                  double kc, double ux, double uy, double ci, const double* u, int64_t n,
+                                  double* out) {
+    const Mat mn{(int)near_m[0], near_m[1], near_m[2], near_m[3], {1, 0, 0}};
+    const Mat mf{(int)far_m[0], far_m[1], far_m[2], far_m[3], {1, 0, 0}};
+    const Side near{&mn, near_m[4], near_m[5]}, far{&mf, far_m[4], far_m[5]};
+    const double k[4] = {kh, kc, kc, kc}, mass[4] = {mass_h, mass_c, mass_c, mass_c};
+    for (int64_t i = 0; i < n; ++i) {
+        const double* ui = u + 4 * i;
+        double* o = out + 6 * i;
+        const bool far_chosen = !(ui[3] < 1.0 - mass_h);
+        const Side& cs = far_chosen ? far : near;
+        double kox, koy, w;
+        int ev, comp;
+        if (!sample_finf(*cs.m, kh, kh * ux, kh * uy, ci, ui[0], ui[1], ui[2], cs.gx, cs.gy, kox, koy, w, ev,
+                         &comp)) {
+            for (int j = 0; j < 6; ++j) o[j] = std::nan("");
+            continue;
+        }
+        double f_ph[4], p_ph[4];
+        composite_companions(near, far, far_chosen, mass, k, 0, ux, uy, ci, kox / kh - ux, koy / kh - uy, comp, f_ph,
+                             p_ph);
+        o[0] = kox;
+        o[1] = koy;
+        o[2] = f_ph[0];
+        o[3] = f_ph[1];
+        o[4] = p_ph[1];
+        o[5] = (cs.m->kind == 0 || comp == 0) ? 0.0 : (cs.m->kind == 1 ? 1.0 : 2.0);
     }
 }
 
@@ -1568,7 +1712,7 @@ int or_trace(void* s, const or_sensor* sen, const or_source* src, int32_t nsrc,
     if (!s || !sen || !op || nl <= 0 || op->spp_count < 0 || op->max_depth < 0) return -1;
     if (op->hero && nl % 4 != 0) return -1;
     if (op->hero && op->aniso) return -1;   // hero paths carry scalar beta, rho
-    if (op->composite && (op->hero || !((const SceneO*)s)->have_bedges)) return -1;
+    if (op->composite && !((const SceneO*)s)->have_bedges) return -1;
     const SceneO* S = (const SceneO*)s;
     if (!pixels) npix = (int64_t)sen->width * sen->height;
     Ctx C{S, sen, src, nsrc, lambdas, nl, op};

@@ -405,3 +405,114 @@ def test_split_mirror_per_path_closed_form(reach_m, aniso):
                 got = paths[sl, y * W_ + x, 0] * wl.spp
                 assert abs(got - ref) <= 1e-9 * ref, (x, y, sl, xw, got, ref)
     assert st["composite"] == n_comp > 0
+
+
+# --------------------------------------------------------------------------------------
+# Composite interactions on hero-wavelength paths (reading R31)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("reach_m", [2e-3, 60e-6])
+def test_hero_split_mirror_per_path_closed_form(reach_m):
+    """Hero-wavelength paths on the split mirror, four wavelengths per path: at the single
+    vertex every member measures its own composite p_w (the closed form of
+    test_split_mirror_per_path_closed_form with that member's window s_i), and the balance
+    heuristic's weights are 1 there (T = R = 1, plane wave), so each member's record is its
+    closed form.  The boundary is detected with the hero's window: min(2.5 beta_h, reach)."""
+    wl = W.split_mirror(width=64, height=2, spp=4, n_lambda=4)
+    img, st, paths = oracle.render(wl, composite=True, reach_m=reach_m, keep_paths=True, hero=True)
+    W_, H_ = wl.sensor.width, wl.sensor.height
+    ks = [2.0 * math.pi / lam for lam in wl.lambdas_um]
+    s2 = [_propagated_sigma2(wl.sensor.sigma_m, 0.01, k) for k in ks]
+    n_comp = 0
+    for sl in range(wl.spp):
+        for y in range(H_):
+            for x in range(W_):
+                pid = ((sl * H_ + y) * W_ + x) * 1 + 0          # one rotation group
+                r = oracle.philox(np.array([[pid & 0xFFFFFFFF, pid >> 32, 0, 0]], np.uint32),
+                                  np.array([wl.seed & 0xFFFFFFFF, wl.seed >> 32], np.uint32))[0]
+                u0 = (int(r[0]) >> 8) / 16777216.0
+                hs = int(r[3]) >> 30
+                xw = wl.sensor.origin[0] + (x + u0) * wl.sensor.pitch_m * wl.sensor.axis_u[0]
+                a_n, a_f = (1.0, 0.25) if xw < 0 else (0.25, 1.0)
+                c_m = abs(xw)
+                rad = min(2.5 * math.sqrt(2.0 * s2[hs]) * 1e-6, reach_m)
+                comp = c_m < rad
+                n_comp += comp
+                for i in range(4):
+                    if comp:
+                        E = 0.5 * math.erfc(c_m * 1e6 / (2.0 * math.sqrt(s2[i])))
+                        ref = 2.0 * s2[i] / math.pi * (math.sqrt(a_n) * (1 - E) + math.sqrt(a_f) * E) ** 2
+                    else:
+                        ref = a_n * 2.0 * s2[i] / math.pi
+                    got = paths[sl, y * W_ + x, i] * wl.spp
+                    assert abs(got - ref) <= 1e-9 * ref, (x, y, sl, i, hs, got, ref)
+    assert st["composite"] == n_comp > 0
+
+
+def test_hero_composite_unbiased_on_terrain():
+    """Hero-wavelength paths with composite interactions against one-wavelength paths with
+    them (pinned above) on the whole terrain at 41 x 29 pixels, where the ~1 mm footprints put
+    most interactions within reach of a boundary: the per-wavelength totals agree within their
+    Monte Carlo error (the companions' mixture densities, the members' far masses and the side
+    choice all enter)."""
+    wl = W.as_float32_inputs(W.mid_terrain(width=41, height=29, spp=64, n_lambda=8))
+    sc = oracle.OracleScene(wl.scene)
+    sc.boundaries(2e-3)
+    _, sa, pa = oracle.render(wl, oscene=sc, composite=True, reach_m=2e-3, keep_paths=True)
+    _, sb, pb = oracle.render(wl, oscene=sc, composite=True, reach_m=2e-3, keep_paths=True, hero=True)
+    print("composite interactions: one-wavelength", sa["composite"], "hero", sb["composite"])
+    assert sb["composite"] > 0.2 * sb["segments"]
+    zs = []
+    for w in range(len(wl.lambdas_um)):
+        xa, xb = pa[:, :, w].sum(1), pb[:, :, w].sum(1)      # per-sample totals (independent)
+        se = math.sqrt(wl.spp * (xa.var(ddof=1) + xb.var(ddof=1)))
+        zs.append((xb.sum() - xa.sum()) / se)
+    print("hero vs one-wavelength composite paths, z per wavelength:", np.round(zs, 2))
+    assert np.all(np.abs(zs) < 4.5)
+
+
+_SMOOTH = (0, 0.0, 1.0, 0.9, 1.0, 0.0)
+_ROUGH_A = (1, 0.06, 2.0, 0.8, 1.0, 0.0)
+_ROUGH_B = (1, 0.15, 4.0, 0.7, 1.0, 0.0)
+_GRATING_A = (2, 0.08, 2.0, 0.85, 1.0, 0.0)
+_GRATING_B = (2, 0.05, 1.2, 0.9, 0.6, 0.8)
+
+
+@pytest.mark.parametrize("near,far", [(_SMOOTH, _ROUGH_A), (_ROUGH_A, _ROUGH_B), (_GRATING_A, _ROUGH_B),
+                                      (_SMOOTH, _GRATING_B), (_GRATING_A, _GRATING_B), (_ROUGH_B, _SMOOTH)])
+def test_hero_composite_step_importance_identity(near, far):
+    """One continuation step at a composite interaction, hero and companion with different
+    wavenumbers and far masses: the companion's ratios f_c / p_h and p_c / p_h, averaged over
+    the hero's samples (side choice included), reproduce the averages over the companion's own
+    mixture sampling, for Gaussian test functions of the outgoing direction centred on the
+    specular direction, on a lobe, and off it.  The identity covers the classes the members
+    share, the specular direction and the rough lobes: a grating's orders j != 0 move with the
+    wavelength, so the hero never samples the companion's (those are covered when the
+    companion is the hero), and the companion's own samples of them are left out."""
+    rng = np.random.default_rng(sum(int(v * 100) for v in near + far))
+    n = 200000
+    kh, kc = 2 * math.pi / 0.45, 2 * math.pi / 0.65
+    th = 0.45
+    ui, ci = (math.sin(th), 0.0), math.cos(th)
+    mh, mc = 0.3, 0.45
+    a = oracle.hero_composite_step(near, far, mh, mc, kh, kc, ui, ci, rng.random((n, 4)))
+    b = oracle.hero_composite_step(near, far, mc, mc, kc, kc, ui, ci, rng.random((n, 4)))
+    ma, mb = np.isfinite(a[:, 0]), np.isfinite(b[:, 0])
+    mb = mb & (np.nan_to_num(b[:, 5], nan=2.0) != 2.0)        # the companion's shared classes
+    assert np.any(a[ma, 5] == 0.0)
+    for cx, w in [(0.0, 0.02), (0.0, 0.1), (0.1, 0.1), (0.3, 0.2), (-0.2, 0.15)]:
+        def phi(r, k, m):
+            ux = np.where(m, r[:, 0], 0.0) / k - ui[0] - cx
+            uy = np.where(m, r[:, 1], 0.0) / k
+            return np.where(m, np.exp(-(ux ** 2 + uy ** 2) / (2 * w * w)), 0.0)
+        pa, pb = phi(a, kh, ma), phi(b, kc, mb)
+        for xa, xb in ((np.where(ma, a[:, 3], 0) * pa, np.where(mb, b[:, 2], 0) * pb),    # f
+                       (np.where(ma, a[:, 4], 0) * pa, pb)):                               # p
+            se = math.hypot(xa.std(), xb.std()) / math.sqrt(n)
+            z = (xa.mean() - xb.mean()) / max(se, 1e-300)
+            assert abs(z) < 5.0 or abs(xa.mean() - xb.mean()) <= 1e-12, (cx, w, xa.mean(), xb.mean(), z)
+    # a companion identical to the hero (same wavenumber and far mass) has the hero's own
+    # weight f_h / p_h and density ratio 1 in the shared classes
+    c = oracle.hero_composite_step(near, far, mh, mh, kh, kh, ui, ci, rng.random((n, 4)))
+    mcm = np.isfinite(c[:, 0]) & (np.nan_to_num(c[:, 5], nan=2.0) != 2.0)
+    assert np.allclose(c[mcm, 2], c[mcm, 3], rtol=1e-12) and np.allclose(c[mcm, 4], 1.0, rtol=1e-12)
