@@ -150,9 +150,11 @@ enum {
  *                          gr_pw_composite_eval) and the continuation samples the far side's
  *                          unwindowed kernel with the probability of the window's intensity mass
  *                          beyond the boundary, else the near side's.  Needs gr_scene_boundaries
- *                          (else GR_E_NO_SCENE); one wavelength per path only (else
- *                          GR_E_UNSUPPORTED); with GR_TRACE_ANISO the footprint is the
- *                          anisotropic ray's.  With a surrogate bsdf_mode the composite
+ *                          (else GR_E_NO_SCENE).  With GR_TRACE_ANISO the footprint is the
+ *                          anisotropic ray's; with GR_TRACE_HERO the boundary is found with the
+ *                          hero's window, each member measures with its own window and the
+ *                          companions' ratios follow the sides' mixture (reading R31).  With
+ *                          a surrogate bsdf_mode the composite
  *                          measurements keep the closed form (the network holds one material's
  *                          p_w) and the other rough ones in the trained domain go to the
  *                          network.  Other bits are invalid. */

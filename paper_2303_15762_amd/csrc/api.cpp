@@ -49,6 +49,7 @@ struct gr_ctx {
     int grid_comp = 0;
     int grid_sur_comp = 0;
     int grid_aniso_comp = 0;
+    int grid_hero_comp = 0;
     int grid_batch = 0;              // blocks of the batched network pass
     // host copies of the mesh (material boundaries are found on request)
     std::vector<float> h_verts;
@@ -281,13 +282,14 @@ int gr_scene_upload(gr_ctx* c, const float* verts, int64_t nv, const float* norm
     c->grid_comp = grw::trace_grid_size(c->device, false, false, false, true);
     c->grid_sur_comp = grw::trace_grid_size(c->device, true, false, false, true);
     c->grid_aniso_comp = grw::trace_grid_size(c->device, false, false, true, true);
+    c->grid_hero_comp = grw::trace_grid_size(c->device, false, true, false, true);
     {
         int ncu = 0;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) ncu = 0;
         c->grid_batch = 4 * std::max(ncu, 1);
     }
     if (c->grid_plain <= 0 || c->grid_sur <= 0 || c->grid_hero <= 0 || c->grid_aniso <= 0 || c->grid_comp <= 0 ||
-        c->grid_sur_comp <= 0 || c->grid_aniso_comp <= 0) {
+        c->grid_sur_comp <= 0 || c->grid_aniso_comp <= 0 || c->grid_hero_comp <= 0) {
         free_scene(c);
         return fail(c, GR_E_DEVICE, "scene: occupancy query failed");
     }
@@ -397,7 +399,7 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     const uint64_t n_paths = hero_of(o) ? n / 4 : n;   // records per path: 4 for hero paths
     const size_t lanes =
         (size_t)std::max({c->grid_plain, c->grid_sur, c->grid_hero, c->grid_aniso, c->grid_comp, c->grid_sur_comp,
-                                   c->grid_aniso_comp}) * 256;
+                                   c->grid_aniso_comp, c->grid_hero_comp}) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
     L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
@@ -475,8 +477,6 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
     if (o->flags &
         ~(GR_TRACE_KEEP_PATHS | GR_TRACE_SHORT_LDS_STACK | GR_TRACE_HERO | GR_TRACE_ANISO | GR_TRACE_COMPOSITE))
         return fail(c, GR_E_INVALID, "trace: flags");
-    if (composite_of(o) && hero_of(o))
-        return fail(c, GR_E_UNSUPPORTED, "trace: composite interactions with one wavelength per path only");
     if (aniso_of(o) && (hero_of(o) || o->bsdf_mode != GR_BSDF_PLAIN))
         return fail(c, GR_E_UNSUPPORTED,
                     "trace: anisotropic rays with the closed-form p_w and one wavelength per path only");
@@ -599,7 +599,7 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
 
     GR_HIP(c, hipSetDevice(c->device));
     const int grid = defer ? (a.composite ? c->grid_sur_comp : c->grid_sur)
-                           : (a.hero ? c->grid_hero
+                           : (a.hero ? (a.composite ? c->grid_hero_comp : c->grid_hero)
                                      : (a.aniso ? (a.composite ? c->grid_aniso_comp : c->grid_aniso)
                                                 : (a.composite ? c->grid_comp : c->grid_plain)));
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};

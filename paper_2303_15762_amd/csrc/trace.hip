@@ -120,6 +120,113 @@ __device__ inline void hero_continuation(const DMat& m, float kh, const float (&
     }
 }
 
+// The members' ratios at a composite interaction (reading R31): the hero sampled the side
+// far_chosen (probability its far mass) and then that side's kernel, so member i meets the
+// mixture (1 - m_i) f_near + m_i f_far and the hero's density is (1 - m_h) p_near + m_h p_far.
+// The sampled direction is of one class, and only that class's components count: specular
+// (smooth, a rough surface's term 0 with probability e^-g, a grating's order 0 with
+// probability J_0(m_0)^2 / W: shared by every wavelength), a rough lobe (terms n >= 1, a density
+// over u_o), or a grating order j != 0 of the sampled side (dispersive: the hero's alone, whose
+// ratio is then its sampler's weight).  Member i's window is the hero's scaled by its beta^2,
+// so its far mass is erfc(c / sqrt(2 snn_i)) / 2 with snn_i = snn_h beta_i^2 / beta_h^2.
+// (kix, kiy): the hero's incident tangential wavevector and (kox, koy) the sampled one, both in
+// the near side's frame; (gfx, gfy): a far grating's direction in that frame.
+__device__ inline void hero_composite_continuation(const DMat& m, const DMat& fm, float gfx, float gfy,
+                                                   bool far_chosen, float snn_h, float c, const float (&mb2)[4],
+                                                   float kh, const float (&mk)[4], int hs, float kix, float kiy,
+                                                   float ci, float kox, float koy, int comp, float wgt,
+                                                   float (&T)[4], float (&R)[4]) {
+    const DMat& cm = far_chosen ? fm : m;
+    if (cm.kind == MAT_GRATING && comp != 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (i == hs) {
+                T[i] *= wgt;
+            } else {
+                T[i] = 0.0f;
+                R[i] = 0.0f;
+            }
+        }
+    } else {
+        const bool spec = cm.kind == MAT_SMOOTH || comp == 0;
+        const float ux = kix / kh, uy = kiy / kh;
+        const float du2 = ((kox - kix) * (kox - kix) + (koy - kiy) * (koy - kiy)) / (kh * kh);
+        const float b2h = pick4(mb2, hs);
+        float f[4] = {0.0f, 0.0f, 0.0f, 0.0f}, p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma nounroll
+        for (int i = 0; i < 4; ++i) {
+            const float ki = pick4(mk, i);
+            const float snn = snn_h * pick4(mb2, i) / b2h;
+            const float af = 0.5f * erfcf(c * rsqrtf(snn) * 0.70710678118654752f);
+            float fi = 0.0f, pi = 0.0f;
+#pragma nounroll
+            for (int sd = 0; sd < 2; ++sd) {
+                const DMat& M = sd == 0 ? m : fm;
+                const float a = sd == 0 ? 1.0f - af : af;
+                float ps = 0.0f, fs = 0.0f;
+                if (spec) {
+                    if (M.kind == MAT_SMOOTH) {
+                        ps = 1.0f;
+                        fs = M.refl;
+                    } else if (M.kind == MAT_ROUGH) {
+                        ps = __expf(-4.0f * ki * ki * ci * ci * M.h * M.h);
+                        fs = M.refl * ps;
+                    } else {
+                        // the grating's own frame (its direction along x): the far side's rotated
+                        const float rx = sd == 0 ? 1.0f : gfx, ry = sd == 0 ? 0.0f : gfy;
+                        float W, w0;
+                        grating_weights(M, ki, ki * (rx * ux + ry * uy), ki * (-ry * ux + rx * uy), ci, W, w0);
+                        ps = W > 0.0f ? w0 / W : 0.0f;
+                        fs = M.refl * w0;
+                    }
+                } else if (M.kind == MAT_ROUGH) {
+                    ps = rough_lobe_density(ki, ci, M.h, M.L, du2);
+                    fs = M.refl * ps;
+                }
+                pi += a * ps;
+                fi += a * fs;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j == i) {
+                    f[j] = fi;
+                    p[j] = pi;
+                }
+            }
+        }
+        const float ph = pick4(p, hs);
+        if (ph > 0.0f) {
+            const float iph = 1.0f / ph;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                T[i] *= f[i] * iph;
+                R[i] = i == hs ? R[i] : R[i] * p[i] * iph;
+            }
+        } else {
+            // the hero's density underflows FP32 (a far lobe tail): the hero keeps its sampler's
+            // weight and the companions are dropped, as in hero_continuation
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (i == hs) {
+                    T[i] *= wgt;
+                } else {
+                    T[i] = 0.0f;
+                    R[i] = 0.0f;
+                }
+            }
+        }
+    }
+    float rmax = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) rmax = fmaxf(rmax, R[i]);
+    const float inv = rmax > 0.0f ? 1.0f / rmax : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        T[i] *= inv;
+        R[i] *= inv;
+    }
+}
+
 // DEFER: rough-surface measurements inside the learned model's domain are not evaluated here;
 // their encoded queries go to a queue that one batched matrix-core kernel evaluates after the
 // trace (its results are added to the path records in a fixed order).
@@ -470,7 +577,10 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 const f3 ya = cross3(ns, xa);
                 // Footprint on the surface: beam variance beta^2/2, stretched by 1/cos along
                 // the plane of incidence.
-                const float sr2 = 0.5f * beta2;
+                // (hero paths: the hero's own window, for the boundary search)
+                float b2w = beta2;
+                if constexpr (HERO) b2w = pick4(mb2, hs);
+                const float sr2 = 0.5f * b2w;
                 const float dx = dot3(d, xa), dy = dot3(d, ya);
                 const float ic2 = 1.0f / (ci * ci);
                 float sxx = 0.0f, syy = 0.0f, sxy = 0.0f;
@@ -554,9 +664,18 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             const float Ti = pick4(mT, i);
                             if (Ti == 0.0f) continue;
                             const float ki = pick4(mk, i), sr = 0.5f * pick4(mb2, i);
-                            const float p = pw_plain(m.kind, m.h, m.L, m.refl, ki, ki * cx, ki * cy, -ki * dx,
-                                                     -ki * dy, sr * (1.0f + dx * dx * ic2), sr * (1.0f + dy * dy * ic2),
-                                                     sr * (dx * dy * ic2), 1.0f, 0.0f);
+                            const float fxx = sr * (1.0f + dx * dx * ic2), fyy = sr * (1.0f + dy * dy * ic2),
+                                        fxy = sr * (dx * dy * ic2);
+                            float p;
+                            if (COMPOSITE && comp) {
+                                // the member's own window against the boundary the hero found
+                                const HalfPlane Hi = make_halfplane(fxx, fyy, fxy, hp.nx, hp.ny, hp.c);
+                                p = pw_composite(m, 1.0f, 0.0f, A.scene.mats[fmat], gfx, gfy, ki, ki * cx, ki * cy,
+                                                 -ki * dx, -ki * dy, Hi, A.bnd);
+                            } else {
+                                p = pw_plain(m.kind, m.h, m.L, m.refl, ki, ki * cx, ki * cy, -ki * dx, -ki * dy, fxx,
+                                             fyy, fxy, 1.0f, 0.0f);
+                            }
                             const float add = scale * Ti * pick4(q, i) * p;
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
@@ -672,8 +791,10 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     float off[2];
                     DMat cm = m;
                     float rcx = 1.0f, rcy = 0.0f;   // the sampled side's grating direction
+                    bool far_chosen = false;
                     if constexpr (COMPOSITE) {
                         if (comp && !(unif(draw(pid, (uint32_t)depth, STREAM_NEE, A.seed).w) < 1.0f - hp.mass_far)) {
+                            far_chosen = true;
                             cm = A.scene.mats[fmat];
                             if (cm.kind == MAT_GRATING) {
                                 rcx = gfx;
@@ -702,7 +823,12 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                             koy = oy;
                         }
                         if constexpr (HERO) {
-                            hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp_j, ph, mT, mR);
+                            if (COMPOSITE && comp)
+                                hero_composite_continuation(m, A.scene.mats[fmat], gfx, gfy, far_chosen, hp.snn, hp.c,
+                                                            mb2, k, mk, hs, k * dx, k * dy, ci, kox, koy, comp_j, wgt,
+                                                            mT, mR);
+                            else
+                                hero_continuation(m, k, mk, hs, k * dx, k * dy, ci, kox, koy, wgt, comp_j, ph, mT, mR);
                         } else {
                             alpha *= wgt;
                         }
@@ -940,6 +1066,7 @@ static int grid_for(int device) {
 
 int trace_grid_size(int device, bool sur, bool hero, bool aniso, bool composite) {
     if (composite && aniso) return grid_for<false, false, true, true>(device);
+    if (composite && hero) return grid_for<false, true, false, true>(device);
     if (composite) return sur ? grid_for<true, false, false, true>(device) : grid_for<false, false, false, true>(device);
     if (aniso) return grid_for<false, false, true>(device);
     if (hero) return grid_for<false, true>(device);
@@ -949,6 +1076,8 @@ int trace_grid_size(int device, bool sur, bool hero, bool aniso, bool composite)
 hipError_t launch_trace(const TraceArgs& a, int grid, hipStream_t s) {
     if (a.composite && a.aniso)
         hipLaunchKernelGGL((trace_kernel<kLdsStack, false, false, true, true>), dim3(grid), dim3(256), 0, s, a);
+    else if (a.composite && a.hero)
+        hipLaunchKernelGGL((trace_kernel<kLdsStack, false, true, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.composite && a.bsdf_mode != 0)
         hipLaunchKernelGGL((trace_kernel<kLdsStack, true, false, false, true>), dim3(grid), dim3(256), 0, s, a);
     else if (a.composite)

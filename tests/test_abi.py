@@ -112,12 +112,12 @@ def test_trace_rejects_before_device_use(ctx):
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
     o.flags = L.GR_TRACE_HERO | L.GR_TRACE_ANISO
     assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
-    # composite interactions: one wavelength per path only (scalar or anisotropic rays,
-    # closed-form or learned p_w), and only after gr_scene_boundaries
-    for flags, mode in ((L.GR_TRACE_COMPOSITE | L.GR_TRACE_HERO, 0), (L.GR_TRACE_COMPOSITE | L.GR_TRACE_HERO, 1)):
-        o.flags, o.bsdf_mode = flags, mode
-        assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
-        assert b"composite" in lib.gr_last_error(h)
+    # composite interactions (scalar, anisotropic or hero-wavelength rays, closed-form or
+    # learned p_w where the rays allow it) only after gr_scene_boundaries
+    o.flags, o.bsdf_mode = L.GR_TRACE_COMPOSITE | L.GR_TRACE_HERO, 1     # hero paths: closed form only
+    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -5
+    o.bsdf_mode = 0
+    assert lib.gr_trace(h, lam4, 4, C.byref(o), C.c_void_p(4096), 1 << 20, dummy, None) == -2
     for flags, mode in ((L.GR_TRACE_COMPOSITE, 0), (L.GR_TRACE_COMPOSITE, 1),
                         (L.GR_TRACE_COMPOSITE | L.GR_TRACE_ANISO, 0)):
         o.flags, o.bsdf_mode = flags, mode

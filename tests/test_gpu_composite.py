@@ -273,3 +273,45 @@ def test_boundaries_replace_and_count(R):
     n2 = R.boundaries(0.5e-3)
     osc = oracle.OracleScene(wl.scene)
     assert n1 == n2 == osc.boundaries()
+
+
+# --------------------------------------------------------------------------------------
+# Composite interactions on hero-wavelength paths (GR_TRACE_COMPOSITE | GR_TRACE_HERO)
+# --------------------------------------------------------------------------------------
+
+def test_hero_split_mirror_paths_match_oracle(R):
+    """Hero paths over the split mirror, four wavelengths per path: per-member records against
+    the oracle (pinned by the per-member closed form of the same scene)."""
+    wl = W.split_mirror(width=64, height=2, spp=4, n_lambda=4)
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    opts = R.opts(spp_count=wl.spp, spp_norm=wl.spp, max_depth=1, seed=wl.seed, keep_paths=True, composite=True,
+                  hero=True)
+    _, st = R.trace(wl.lambdas_um, opts)
+    rec = R.path_records(opts, 4).cpu().numpy().astype(np.float64)
+    img, ost, paths = oracle.render(wl, composite=True, reach_m=2e-3, keep_paths=True, hero=True)
+    print("hero split mirror: composite", st["composite"], ost["composite"])
+    assert st["composite"] == ost["composite"] > 0
+    np.testing.assert_allclose(rec.reshape(wl.spp, -1, 4), paths, rtol=2e-5, atol=0)
+
+
+@pytest.mark.parametrize("view", ["window", "low_resolution"])
+def test_hero_terrain_matches_oracle(R, view):
+    """Hero paths with composite interactions on the terrain: a full-resolution window over
+    tile boundaries (16 samples, 8 wavelengths, depth 4) and the whole terrain at 41 x 29 (wide
+    footprints, boundaries within reach of most hits), against the oracle's image."""
+    wl = (_terrain_window(230, 230) if view == "window"
+          else W.as_float32_inputs(W.mid_terrain(width=41, height=29, spp=16, n_lambda=8)))
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    img, st = R.render_workload(wl, composite=True, hero=True)
+    g = img.cpu().numpy().astype(np.float64)
+    o, ost = oracle.render(wl, composite=True, reach_m=2e-3, hero=True)
+    e = rel_l2(g, o)
+    print("hero composite %s: rel L2" % view, e, "composite", st["composite"], ost["composite"], "nonfinite",
+          st["nonfinite"])
+    assert st["nonfinite"] == 0
+    assert ost["composite"] > 1000
+    assert abs(st["composite"] - ost["composite"]) <= 1e-3 * ost["composite"] + 2
+    assert abs(st["segments"] - ost["segments"]) <= 1e-3 * ost["segments"]
+    assert e <= 1e-3
