@@ -72,6 +72,20 @@ def test_noalloc_hero_and_accumulation(R):
     assert np.linalg.norm(a - f) <= 1e-5 * np.linalg.norm(f)
 
 
+@pytest.mark.parametrize("mode", ["scalar", "hero", "aniso"])
+def test_noalloc_composite_interactions(R, mode):
+    """Composite interactions (the scene's material boundaries read by the kernels) through the
+    static workspace, scalar, hero-wavelength and anisotropic rays, bit for bit against
+    gr_trace."""
+    wl = W.mid_terrain(width=24, height=16, spp=8, n_lambda=8)
+    R.load_workload(wl)
+    R.boundaries(2e-3)
+    print("noalloc: composite interactions 24x16, 8 spp,", mode, flush=True)
+    ref, img, _ = _both(R, wl, 8, composite=True, hero=mode == "hero", aniso=mode == "aniso")
+    assert np.array_equal(ref, img)
+    assert float(np.abs(ref).sum()) > 0.0
+
+
 def test_noalloc_rejects_oversized(R):
     import torch
     wl = W.mid_terrain(width=256, height=256, spp=16, n_lambda=8)
