@@ -121,7 +121,7 @@ constexpr int kMaxStack = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack; }
+int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack / 2; }
 
 // The learned-p_w path renders in launches of at most this many paths: each launch queues at
 // most one query per path and interaction (32 B) and owns one result float per slot.  Each
@@ -402,7 +402,7 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
                                    c->grid_aniso_comp, c->grid_hero_comp}) * 256;
     L.records = kWsHeader;
     L.ovf = L.records + align256((size_t)n * sizeof(float));
-    L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * sizeof(int));
+    L.queue = L.ovf + align256(lanes * overflow_entries(c, o) * 2 * sizeof(int));
     const bool defer = o->bsdf_mode != GR_BSDF_PLAIN, shq = shadow_queue_of(o);
     // bytes per (path, interaction) slot: a network query, a shadow ray, the result float (and
     // one byte per path: its stored slot count)

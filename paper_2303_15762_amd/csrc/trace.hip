@@ -355,9 +355,12 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
+    // the traversal's (child, key) pairs over the same wave-private region (the shading code
+    // uses the lane's column of it as a cache between traversals)
+    lds_v2i* stk2 = (lds_v2i*)&lds_stack[wv][0][0] + lane;
     // this wave's slice of the traversal-stack overflow (uniform; the lane adds its id)
     const size_t ostride = (size_t)gridDim.x * 256;
-    int* ovf = A.ovf ? A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
+    v2i_t* ovf = A.ovf ? (v2i_t*)A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
 
     const SensorDev& sen = A.sensor;
     const uint32_t Wd = (uint32_t)sen.W, Hd = (uint32_t)sen.H, nl = (uint32_t)A.nl;
@@ -491,7 +494,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         ray_setup(ray, o, d);
         const float tmin = 1e-7f * (1.0f + maxabs3(to_f3(o)));
         float thit = FLT_MAX, bu = 0.0f, bv = 0.0f;
-        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv,
+        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk2, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv,
                                         top, nln);
         if (tri < 0) {
             finish = true;
@@ -937,9 +940,10 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
     const lds_v4f* top = (const lds_v4f*)&lds_nodes[0];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    lds_int* stk = (lds_int*)&lds_stack[wv][0][lane];
+    // the traversal's (child, key) pairs over the wave-private region
+    lds_v2i* stk2 = (lds_v2i*)&lds_stack[wv][0][0] + lane;
     const size_t ostride = (size_t)gridDim.x * 256;
-    int* ovf = A.ovf ? A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
+    v2i_t* ovf = A.ovf ? (v2i_t*)A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
     const uint64_t n = *A.shq_count;
     uint32_t c_nodes = 0, c_tris = 0;
     for (uint64_t base = ((uint64_t)blockIdx.x * 4 + wv) * 64; base < n; base += (uint64_t)gridDim.x * 256) {
@@ -955,7 +959,7 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
             RayT sray;
             ray_setup(sray, P, -1.0f * om);
             float tm = __uint_as_float(c.y), su, sv;
-            const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk, A.lds_cap, ovf, ostride,
+            const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk2, A.lds_cap, ovf, ostride,
                                             c_nodes, c_tris, su, sv, top, nln);
             if (occ >= 0) {
                 if (A.hero) reinterpret_cast<float4*>(A.sdense)[c.w] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);

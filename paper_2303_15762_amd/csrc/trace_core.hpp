@@ -18,6 +18,8 @@ typedef __attribute__((address_space(3))) int lds_int;
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4f_t lds_v4f;
+typedef int v2i_t __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) v2i_t lds_v2i;
 
 // Copy BVH nodes 0 .. min(kLdsNodes, node count) - 1 into the block's LDS (8 float4 each) and
 // return how many; all threads of the block call it.
@@ -163,9 +165,10 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
 // triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
 // triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack (stride 64),
-// of which the first cap (<= STACK) entries are used; entry cap + i goes to
-// ovf[i * ostride + lane], ovf being the wave's slice of the overflow region, which the caller
-// sizes for the tree: at most 3 entries per inner node on the current root path.
+// of which the first cap (<= STACK / 2) entries are used, each a (child code, entry key) pair;
+// entry cap + i goes to ovf[i * ostride + lane], ovf being the wave's slice of the overflow
+// region, which the caller sizes for the tree: at most 3 entries per inner node on the current
+// root path.
 // Returns the triangle (leaf order) or -1.
 // Traversal loop structure (Aila and Laine, "Understanding the efficiency of ray traversal on
 // GPUs", HPG 2009: while-while with postponed leaves): each lane descends inner nodes until it
@@ -175,7 +178,7 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // Nodes below nln are read from top (their LDS copy), the others from the node array.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
-                                        bool any, int skip, lds_int* stk, int cap, int* ovf, size_t ostride,
+                                        bool any, int skip, lds_v2i* stk, int cap, v2i_t* ovf, size_t ostride,
                                         uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv,
                                         const lds_v4f* top, int nln) {
     constexpr int kDone = 0x7FFFFFFF;   // nothing left to visit (never a node index)
@@ -185,14 +188,31 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
     int sp = 0;
     int cur = 0;    // next inner node (>= 0) or leaf (< 0) to visit, or kDone
     int leaf = 0;   // a parked leaf (< 0), or 0
-    // the LDS entry is always read (in range) and replaced by the overflow entry when the
-    // stack is that deep, so the common pop stays an LDS read
+    // The LDS entry is always read (in range) and replaced by the overflow entry when the
+    // stack is that deep, so the common pop stays an LDS read.  A closest-hit query skips an
+    // inner node whose entry distance lies beyond the closest hit found since it was pushed:
+    // its children's boxes lie inside its (widened) box and the slab distances are monotonic
+    // in the planes, so each child's entry distance is at least the node's and the node test
+    // would reject all four.  The stored key is the entry distance's bit pattern with the slot
+    // in its two low bits, hence "beyond" is key > bits(t_best) + 3.  Leaves are always tested
+    // (a triangle's own distance can round below its box's).
+    auto read_top = [&]() -> v2i_t {
+        --sp;
+        v2i_t e = stk[min(sp, cap - 1) * 64];
+        if (sp >= cap) e = ovf[(size_t)(sp - cap) * ostride + __lane_id()];
+        return e;
+    };
     auto pop = [&]() -> int {
         if (sp == 0) return kDone;
-        --sp;
-        int v = stk[min(sp, cap - 1) * 64];
-        if (sp >= cap) v = ovf[(size_t)(sp - cap) * ostride + __lane_id()];
-        return v;
+        v2i_t e = read_top();
+        if (!any) {
+            const int ib = __float_as_int(best_t) + 3;
+            while (e.x >= 0 && e.y > ib) {   // a stale inner node: take the next entry
+                if (sp == 0) return kDone;
+                e = read_top();
+            }
+        }
+        return e.x;
     };
     // slab distances as (lo - o) / d = lo * inv - o * inv: one FMA per plane (the node boxes
     // are widened by more than the extra rounding of o * inv)
@@ -214,15 +234,16 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
             v4f_t nx, fx, ny, fy, nz, fz;
             v4i_t chv;
             if (cur < nln) {
-                // the same 16-byte rows of the node's LDS copy
-                const lds_v4f* L = top + (cur << 3);
-                nx = L[sx >> 4];
-                fx = L[(sx ^ 16) >> 4];
-                ny = L[sy >> 4];
-                fy = L[(sy ^ 16) >> 4];
-                nz = L[sz >> 4];
-                fz = L[(sz ^ 16) >> 4];
-                chv = __builtin_bit_cast(v4i_t, L[6]);
+                // the same 16-byte rows of the node's LDS copy, at the same byte offsets (the
+                // copy's base folds into the LDS reads' immediate offset)
+                const __attribute__((address_space(3))) char* L = (const __attribute__((address_space(3))) char*)top;
+                nx = *(const lds_v4f*)(L + onx);
+                fx = *(const lds_v4f*)(L + (onx ^ 16));
+                ny = *(const lds_v4f*)(L + ony);
+                fy = *(const lds_v4f*)(L + (ony ^ 16));
+                nz = *(const lds_v4f*)(L + onz);
+                fz = *(const lds_v4f*)(L + (onz ^ 16));
+                chv = __builtin_bit_cast(v4i_t, *(const lds_v4f*)(L + base + 96));
             } else {
                 nx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx, 0, 0);
                 fx = __builtin_amdgcn_raw_buffer_load_b128(nb, onx ^ 16, 0, 0);
@@ -255,9 +276,9 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 const int tf = min(min(__float_as_int(t1x), __float_as_int(t1y)), min(__float_as_int(t1z), ibest));
                 key[i] = tn <= tf ? (((uint32_t)tn & ~3u) | (uint32_t)i) : 0xFFFFFFFFu;
             }
-            auto push = [&](int v) {
-                if (sp < cap) stk[sp * 64] = v;
-                else ovf[(size_t)(sp - cap) * ostride + __lane_id()] = v;
+            auto push = [&](int v, uint32_t k) {
+                if (sp < cap) stk[sp * 64] = v2i_t{v, (int)k};
+                else ovf[(size_t)(sp - cap) * ostride + __lane_id()] = v2i_t{v, (int)k};
                 ++sp;
             };
             if (any) {
@@ -268,7 +289,7 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
 #pragma unroll
                 for (int i = 3; i >= 0; --i) {
                     if (key[i] != 0xFFFFFFFFu) {
-                        if (have) push(nxt);
+                        if (have) push(nxt, 0u);
                         nxt = chd[i];
                         have = true;
                     }
@@ -295,7 +316,7 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 // push the farther hits (farthest first), descend into the nearest
 #pragma unroll
                 for (int i = 3; i >= 1; --i) {
-                    if (key[i] != 0xFFFFFFFFu) push(chd[i]);
+                    if (key[i] != 0xFFFFFFFFu) push(chd[i], key[i]);
                 }
                 cur = key[0] != 0xFFFFFFFFu ? chd[0] : pop();
             }
