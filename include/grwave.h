@@ -115,8 +115,8 @@ enum {
  *   flags                : GR_TRACE_KEEP_PATHS keeps the per-path contributions in the
  *                          workspace (see gr_workspace_paths).  GR_TRACE_SHORT_LDS_STACK keeps
  *                          only 4 BVH traversal-stack entries per lane in LDS and the rest in
- *                          the workspace (normally 16 stay in LDS, and the workspace holds the
- *                          deeper entries of BVHs of more than 4 levels); the image is
+ *                          the workspace (normally 14 stay in LDS, and the workspace holds the
+ *                          deeper entries of BVHs of more than 3 levels); the image is
  *                          identical, the render slower.  It
  *                          exists to exercise the overflow path.  GR_TRACE_HERO traces
  *                          hero-wavelength paths (Sec. "Interactive Rendering", implementation

@@ -121,7 +121,9 @@ constexpr int kMaxStack = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack / 2; }
+// (child, key) entries per lane kept in LDS: the lane's LDS words hold kLdsStack / 2 entries,
+// of which the last two are the traversal's child-code scratch
+int lds_cap_for(const gr_trace_opts* o) { return (o->flags & GR_TRACE_SHORT_LDS_STACK) ? 4 : grw::kLdsStack / 2 - 2; }
 
 // The learned-p_w path renders in launches of at most this many paths: each launch queues at
 // most one query per path and interaction (32 B) and owns one result float per slot.  Each

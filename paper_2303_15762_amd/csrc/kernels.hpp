@@ -10,8 +10,8 @@ namespace grw {
 
 constexpr int kMaxSources = 16;
 constexpr int kMaxLambda = 64;
-// LDS words per lane of the traversal stack: kLdsStack / 2 entries of (child code, entry key);
-// deeper entries go to the overflow region.
+// LDS words per lane of the traversal stack: kLdsStack / 2 - 2 entries of (child code, entry
+// key) and 16 bytes of child-code scratch; deeper entries go to the overflow region.
 constexpr int kLdsStack = 32;
 // BVH nodes 0 .. kLdsNodes - 1 (the builder puts the top levels there, breadth-first) are
 // copied into each block's LDS by the traversal kernels: 8 KB beside the 32 KB of stacks,
@@ -108,7 +108,7 @@ struct TraceArgs {
     float* records;                  // [n_paths]
     int* ovf;                        // traversal stack overflow [ovf_n][grid * 256][2] (child, key), or null
     uint32_t ovf_n;                  // overflow entries per lane
-    int lds_cap;                     // stack entries kept in LDS (<= kLdsStack / 2: two ints each)
+    int lds_cap;                     // stack entries kept in LDS (<= kLdsStack / 2 - 2: two ints each)
     unsigned long long* counter;     // path dispenser
     unsigned long long* stats;       // [16]
 };

@@ -347,7 +347,7 @@ __device__ __forceinline__ void aniso_footprint(const AnisoRay& R, const f3& d, 
 // continuation samples one side's kernel with the probability of its window mass.
 template <int STACK, bool DEFER, bool HERO, bool ANISO = false, bool COMPOSITE = false>
 __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
-    __shared__ int lds_stack[4][STACK][64];
+    __shared__ __attribute__((aligned(16))) int lds_stack[4][STACK][64];
     // the top levels of the BVH, read by every closest-hit query
     __shared__ float4 lds_nodes[kLdsNodes * 8];
     const int nln = stage_top_nodes(A.scene, lds_nodes);
@@ -358,6 +358,8 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
     // the traversal's (child, key) pairs over the same wave-private region (the shading code
     // uses the lane's column of it as a cache between traversals)
     lds_v2i* stk2 = (lds_v2i*)&lds_stack[wv][0][0] + lane;
+    // the child-code scratch: 16 contiguous bytes per lane in the last two entries' space
+    lds_v4i* scr = (lds_v4i*)&lds_stack[wv][STACK - 4][0] + lane;
     // this wave's slice of the traversal-stack overflow (uniform; the lane adds its id)
     const size_t ostride = (size_t)gridDim.x * 256;
     v2i_t* ovf = A.ovf ? (v2i_t*)A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
@@ -494,7 +496,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
         ray_setup(ray, o, d);
         const float tmin = 1e-7f * (1.0f + maxabs3(to_f3(o)));
         float thit = FLT_MAX, bu = 0.0f, bv = 0.0f;
-        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk2, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv,
+        const int tri = traverse<STACK>(A.scene, ray, tmin, thit, false, prev, stk2, scr, A.lds_cap, ovf, ostride, c_nodes, c_tris, bu, bv,
                                         top, nln);
         if (tri < 0) {
             finish = true;
@@ -934,7 +936,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
 // the trace kernel's, so the traversal-stack overflow region fits.
 template <int STACK>
 __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
-    __shared__ int lds_stack[4][STACK][64];
+    __shared__ __attribute__((aligned(16))) int lds_stack[4][STACK][64];
     __shared__ float4 lds_nodes[kLdsNodes * 8];
     const int nln = stage_top_nodes(A.scene, lds_nodes);
     const lds_v4f* top = (const lds_v4f*)&lds_nodes[0];
@@ -942,6 +944,8 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
     const int wv = threadIdx.x >> 6;
     // the traversal's (child, key) pairs over the wave-private region
     lds_v2i* stk2 = (lds_v2i*)&lds_stack[wv][0][0] + lane;
+    // the child-code scratch: 16 contiguous bytes per lane in the last two entries' space
+    lds_v4i* scr = (lds_v4i*)&lds_stack[wv][STACK - 4][0] + lane;
     const size_t ostride = (size_t)gridDim.x * 256;
     v2i_t* ovf = A.ovf ? (v2i_t*)A.ovf + ((size_t)blockIdx.x * 256 + 64 * __builtin_amdgcn_readfirstlane(wv)) : nullptr;
     const uint64_t n = *A.shq_count;
@@ -959,7 +963,7 @@ __global__ __launch_bounds__(256, 4) void shadow_kernel(const TraceArgs A) {
             RayT sray;
             ray_setup(sray, P, -1.0f * om);
             float tm = __uint_as_float(c.y), su, sv;
-            const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk2, A.lds_cap, ovf, ostride,
+            const int occ = traverse<STACK>(A.scene, sray, tminP, tm, true, (int)c.z, stk2, scr, A.lds_cap, ovf, ostride,
                                             c_nodes, c_tris, su, sv, top, nln);
             if (occ >= 0) {
                 if (A.hero) reinterpret_cast<float4*>(A.sdense)[c.w] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);

@@ -20,6 +20,7 @@ typedef int v4i_t __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4f_t lds_v4f;
 typedef int v2i_t __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) v2i_t lds_v2i;
+typedef __attribute__((address_space(3))) v4i_t lds_v4i;
 
 // Copy BVH nodes 0 .. min(kLdsNodes, node count) - 1 into the block's LDS (8 float4 each) and
 // return how many; all threads of the block call it.
@@ -165,7 +166,9 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
 // triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
 // triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack (stride 64),
-// of which the first cap (<= STACK / 2) entries are used, each a (child code, entry key) pair;
+// of which the first cap (<= STACK / 2 - 2) entries are used, each a (child code, entry key)
+// pair; scr: 16 bytes of LDS of this lane (the last two stack entries' space) for a node's
+// child codes while its children are ordered;
 // entry cap + i goes to ovf[i * ostride + lane], ovf being the wave's slice of the overflow
 // region, which the caller sizes for the tree: at most 3 entries per inner node on the current
 // root path.
@@ -178,7 +181,7 @@ __device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
 // Nodes below nln are read from top (their LDS copy), the others from the node array.
 template <int STACK>
 __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float tmin, float& tmax,
-                                        bool any, int skip, lds_v2i* stk, int cap, v2i_t* ovf, size_t ostride,
+                                        bool any, int skip, lds_v2i* stk, lds_v4i* scr, int cap, v2i_t* ovf, size_t ostride,
                                         uint32_t& n_nodes, uint32_t& n_tris, float& hu, float& hv,
                                         const lds_v4f* top, int nln) {
     constexpr int kDone = 0x7FFFFFFF;   // nothing left to visit (never a node index)
@@ -193,8 +196,8 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
     // inner node whose entry distance lies beyond the closest hit found since it was pushed:
     // its children's boxes lie inside its (widened) box and the slab distances are monotonic
     // in the planes, so each child's entry distance is at least the node's and the node test
-    // would reject all four.  The stored key is the entry distance's bit pattern with the slot
-    // in its two low bits, hence "beyond" is key > bits(t_best) + 3.  Leaves are always tested
+    // would reject all four.  The stored key is the entry distance's bit pattern with its four
+    // low bits replaced by 4 x slot, hence "beyond" is key > bits(t_best) + 15.  Leaves are always tested
     // (a triangle's own distance can round below its box's).
     auto read_top = [&]() -> v2i_t {
         --sp;
@@ -206,7 +209,7 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
         if (sp == 0) return kDone;
         v2i_t e = read_top();
         if (!any) {
-            const int ib = __float_as_int(best_t) + 3;
+            const int ib = __float_as_int(best_t) + 15;
             while (e.x >= 0 && e.y > ib) {   // a stale inner node: take the next entry
                 if (sp == 0) return kDone;
                 e = read_top();
@@ -257,8 +260,9 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
             const float lxa[4] = {nx.x, nx.y, nx.z, nx.w}, hxa[4] = {fx.x, fx.y, fx.z, fx.w};
             const float lya[4] = {ny.x, ny.y, ny.z, ny.w}, hya[4] = {fy.x, fy.y, fy.z, fy.w};
             const float lza[4] = {nz.x, nz.y, nz.z, nz.w}, hza[4] = {fz.x, fz.y, fz.z, fz.w};
-            // key = entry distance with the slot in its two low bits (distances are positive, so
-            // their bit patterns order like the values); a miss keys as 0xFFFFFFFF.  Empty slots
+            // key = entry distance with 4 x slot in its four low bits (distances are positive, so
+            // their bit patterns order like the values; distances within 16 ulps order by slot);
+            // a miss keys as 0xFFFFFFFF.  Empty slots
             // hold boxes at +inf and always miss.  The interval ends are taken as signed integers:
             // the entry is at least tmin > 0, and positive floats order like their bit patterns
             // while any negative float is a negative integer, so the hit decision and the entry
@@ -274,7 +278,7 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 const float t0z = fmaf(lza[i], iz, -oiz), t1z = fmaf(hza[i], iz, -oiz);
                 const int tn = max(max(__float_as_int(t0x), __float_as_int(t0y)), max(__float_as_int(t0z), itmin));
                 const int tf = min(min(__float_as_int(t1x), __float_as_int(t1y)), min(__float_as_int(t1z), ibest));
-                key[i] = tn <= tf ? (((uint32_t)tn & ~3u) | (uint32_t)i) : 0xFFFFFFFFu;
+                key[i] = tn <= tf ? (((uint32_t)tn & ~15u) | (uint32_t)(4 * i)) : 0xFFFFFFFFu;
             }
             auto push = [&](int v, uint32_t k) {
                 if (sp < cap) stk[sp * 64] = v2i_t{v, (int)k};
@@ -296,29 +300,32 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 }
                 cur = have ? nxt : pop();
             } else {
-                // ascending sorting network on the keys, the child codes carried along
-#define GRW_CSWAP(i, j)                                 \
+                // ascending sorting network on the keys alone; the child codes wait in the
+                // lane's scratch and each is read back at the byte offset its key's slot bits
+                // give (4 x slot)
+                *scr = chv;
+#define GRW_KSWAP(i, j)                                 \
         {                                                   \
-            const bool sw_ = key[j] < key[i];               \
-            const uint32_t lo_ = sw_ ? key[j] : key[i];     \
-            key[j] = sw_ ? key[i] : key[j];                 \
+            const uint32_t lo_ = min(key[i], key[j]);       \
+            key[j] = max(key[i], key[j]);                   \
             key[i] = lo_;                                   \
-            const int cl_ = sw_ ? chd[j] : chd[i];          \
-            chd[j] = sw_ ? chd[i] : chd[j];                 \
-            chd[i] = cl_;                                   \
         }
-                GRW_CSWAP(0, 1)
-                GRW_CSWAP(2, 3)
-                GRW_CSWAP(0, 2)
-                GRW_CSWAP(1, 3)
-                GRW_CSWAP(1, 2)
-#undef GRW_CSWAP
+                GRW_KSWAP(0, 1)
+                GRW_KSWAP(2, 3)
+                GRW_KSWAP(0, 2)
+                GRW_KSWAP(1, 3)
+                GRW_KSWAP(1, 2)
+#undef GRW_KSWAP
+                const uint32_t sbase = (uint32_t)(uintptr_t)scr;
+                auto child = [&](uint32_t k) -> int {
+                    return *(const __attribute__((address_space(3))) int*)(uintptr_t)((k & 12u) | sbase);
+                };
                 // push the farther hits (farthest first), descend into the nearest
 #pragma unroll
                 for (int i = 3; i >= 1; --i) {
-                    if (key[i] != 0xFFFFFFFFu) push(chd[i], key[i]);
+                    if (key[i] != 0xFFFFFFFFu) push(child(key[i]), key[i]);
                 }
-                cur = key[0] != 0xFFFFFFFFu ? chd[0] : pop();
+                cur = key[0] != 0xFFFFFFFFu ? child(key[0]) : pop();
             }
             if (cur < 0 && leaf == 0) {   // park the leaf and keep descending
                 leaf = cur;

@@ -178,7 +178,7 @@ def test_traversal_stack_overflow_path(R):
     o = dict(spp_count=wl.spp, spp_norm=wl.spp, max_depth=wl.max_depth, seed=wl.seed)
     a, sa = R.trace(wl.lambdas_um, R.opts(**o))
     b, sb = R.trace(wl.lambdas_um, R.opts(short_lds_stack=True, **o))
-    print("LDS stack 16:", sa, "LDS stack 4:", sb)
+    print("LDS stack 14:", sa, "LDS stack 4:", sb)
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
     for key in ("paths", "segments", "shadow_rays"):
         assert sa[key] == sb[key]
