@@ -391,6 +391,8 @@ int gr_set_sources(gr_ctx* c, const gr_source* s, int32_t n) {
     return GR_OK;
 }
 
+}  // extern "C"
+
 namespace {
 // header | path records | traversal-stack overflow of the scene's BVH (per persistent lane) |
 // learned-p_w queue and per-(path, interaction) results of one launch
@@ -421,6 +423,8 @@ WsLayout ws_layout(const gr_ctx* c, const gr_trace_opts* o, int32_t nl) {
     return L;
 }
 }  // namespace
+
+extern "C" {
 
 int gr_workspace_size(const gr_ctx* c, const gr_trace_opts* o, int32_t nl, size_t* bytes) {
     if (!c || !o || !bytes) return GR_E_INVALID;
