@@ -47,6 +47,18 @@ int main() {
             if (c == kEmptyChild) continue;
             if (c >= 0) {
                 if (c <= n || c >= nn) { std::printf("FAIL child index %d at node %ld\n", c, n); return 1; }
+                // nested boxes: every box of the child node lies inside the slot's box (the
+                // traversal skips a popped node whose slot box starts beyond the closest hit,
+                // which is exact only if no box below starts nearer)
+                const BVH4Node& C = B.nodes[c];
+                for (int k = 0; k < 4; ++k) {
+                    if (C.child[k] == kEmptyChild) continue;
+                    if (C.lox[k] < N.lox[i] || C.hix[k] > N.hix[i] || C.loy[k] < N.loy[i] ||
+                        C.hiy[k] > N.hiy[i] || C.loz[k] < N.loz[i] || C.hiz[k] > N.hiz[i]) {
+                        std::printf("FAIL child box outside its slot box at node %ld\n", n);
+                        return 1;
+                    }
+                }
             } else {
                 int first = c & 0x0FFFFFFF, cnt = ((c >> 28) & 7) + 1;
                 if (first + cnt > nt) { std::printf("FAIL leaf range\n"); return 1; }
