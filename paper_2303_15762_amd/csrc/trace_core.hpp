@@ -320,12 +320,18 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
                 auto child = [&](uint32_t k) -> int {
                     return *(const __attribute__((address_space(3))) int*)(uintptr_t)((k & 12u) | sbase);
                 };
-                // push the farther hits (farthest first), descend into the nearest
+                // descend into the nearest hit and push the farther ones (farthest first); the
+                // nearest child's code is read first, since the next node fetch waits on it
+                // (with no hit there is nothing to push: the keys are sorted)
+                if (key[0] != 0xFFFFFFFFu) {
+                    cur = child(key[0]);
 #pragma unroll
-                for (int i = 3; i >= 1; --i) {
-                    if (key[i] != 0xFFFFFFFFu) push(child(key[i]), key[i]);
+                    for (int i = 3; i >= 1; --i) {
+                        if (key[i] != 0xFFFFFFFFu) push(child(key[i]), key[i]);
+                    }
+                } else {
+                    cur = pop();
                 }
-                cur = key[0] != 0xFFFFFFFFu ? child(key[0]) : pop();
             }
             if (cur < 0 && leaf == 0) {   // park the leaf and keep descending
                 leaf = cur;
