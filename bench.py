@@ -339,11 +339,11 @@ def composite_leg(R, wl, ms_plain, img_plain, steps, threads, no_cpu, reach_m=2e
 
 # Coherent measurement: vector operations of one (sample, slit node) evaluation in the FP64
 # mode, the way the kernel writes them: distance (1 FMA + a square root of ~6), phase (1),
-# amplitude (4 multiplies, a division of ~8, a square root of ~6), sincos with its range
-# reduction (~40), the large-argument correction (a division of ~8), complex product and
+# amplitude (a reciprocal of the distance, ~8, 3 multiplies, a square root of ~6), sincos with
+# its range reduction (~40), the large-argument correction (1 multiply), complex product and
 # accumulation (8).  FP64 vector operations issue at the FP32 rate on this chip (78.6 TFLOP/s
 # counts an FMA as two).
-COHERENT_NODE_OPS = 85
+COHERENT_NODE_OPS = 74
 
 
 def coherent_leg(R, steps):

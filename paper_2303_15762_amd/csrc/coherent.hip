@@ -91,6 +91,14 @@ __global__ __launch_bounds__(256) void coherent_kernel(const CohArgs A, float* _
     const int64_t pix = (int64_t)blockIdx.x * 4 + wv;
     const int64_t npix = (int64_t)A.W * A.H;
     double acc = 0.0;
+    // the slit kernel's constant factors (k z / 2) sqrt(2 / (pi k)) and 3 / (8 k), once per
+    // thread (a thread draws few samples: the points case does not pay for them)
+    double c_amp = 0.0, c_ci = 0.0;
+    if (A.kind == 1) {
+        c_amp = 0.5 * A.k * A.z * sqrt(2.0 / (M_PI * A.k));
+        c_ci = 3.0 / (8.0 * A.k);
+    }
+    const float c_ampf = (float)c_amp, c_cif = (float)c_ci;
     if (pix < npix) {
         const int x = (int)(pix % A.W), y = (int)(pix / A.W);
         for (int64_t s = lane; s < A.spp; s += 64) {
@@ -107,23 +115,28 @@ __global__ __launch_bounds__(256) void coherent_kernel(const CohArgs A, float* _
                 sincospi(2.0 * u3, &sn, &cs);
                 const double X = (x + u0 - 0.5 * A.W) * A.pitch + A.sigma * rr * cs;
                 const double Y = (y + u1 - 0.5 * A.H) * A.pitch + A.sigma * rr * sn;
+                // one double division per node: the distance's reciprocal
+                const double z2y2 = A.z * A.z + Y * Y, z2 = A.z * A.z;
                 for (int e = 0; e < A.n; ++e) {
                     const double dx = X - A.xs[e];
                     if (A.kind == 0) {
-                        const double L = sqrt(A.z * A.z + dx * dx + Y * Y);
+                        const double L = sqrt(z2y2 + dx * dx);
+                        const double rL = 1.0 / L;
                         double ps, pc;
                         sincos(A.k * L, &ps, &pc);
-                        re += pc / L;
-                        im += ps / L;
+                        re += pc * rL;
+                        im += ps * rL;
                     } else {
                         // (i k z / 2) H1(k rho) / rho with the large-argument expansion of
-                        // H1: sqrt(2 / (pi x)) exp(i (x - 3 pi / 4)) (1 + 3 i / (8 x))
-                        const double rho = sqrt(A.z * A.z + dx * dx);
+                        // H1: sqrt(2 / (pi x)) exp(i (x - 3 pi / 4)) (1 + 3 i / (8 x)),
+                        // x = k rho: amplitude (k z / 2) sqrt(2 / (pi k)) rho^-3/2
+                        const double rho = sqrt(z2 + dx * dx);
+                        const double rr = 1.0 / rho;
                         const double xk = A.k * rho;
-                        const double amp = A.ws[e] * 0.5 * A.k * A.z / rho * sqrt(2.0 / (M_PI * xk));
+                        const double amp = A.ws[e] * c_amp * rr * sqrt(rr);
                         double ps, pc;
                         sincos(xk - 0.75 * M_PI, &ps, &pc);
-                        const double cr = 1.0, ci = 3.0 / (8.0 * xk);
+                        const double cr = 1.0, ci = c_ci * rr;
                         // i * (pc + i ps) * (cr + i ci)
                         const double ar = pc * cr - ps * ci, ai = pc * ci + ps * cr;
                         re += -amp * ai;
@@ -143,17 +156,19 @@ __global__ __launch_bounds__(256) void coherent_kernel(const CohArgs A, float* _
                         const float dx = X - (float)A.xs[e];
                         if (A.kind == 0) {
                             const float L = sqrtf(zf * zf + dx * dx + Y * Y);
+                            const float rL = 1.0f / L;
                             float ps, pc;
                             sincosf(kf * L, &ps, &pc);
-                            fre += pc / L;
-                            fim += ps / L;
+                            fre += pc * rL;
+                            fim += ps * rL;
                         } else {
                             const float rho = sqrtf(zf * zf + dx * dx);
+                            const float rr = 1.0f / rho;
                             const float xk = kf * rho;
-                            const float amp = (float)A.ws[e] * 0.5f * kf * zf / rho * sqrtf(2.0f / (kPiF * xk));
+                            const float amp = (float)A.ws[e] * c_ampf * rr * sqrtf(rr);
                             float ps, pc;
                             sincosf(xk - 0.75f * kPiF, &ps, &pc);
-                            const float ci = 3.0f / (8.0f * xk);
+                            const float ci = c_cif * rr;
                             fre += -amp * (pc * ci + ps);
                             fim += amp * (pc - ps * ci);
                         }
@@ -182,17 +197,17 @@ __global__ __launch_bounds__(256) void coherent_kernel(const CohArgs A, float* _
                         const df red = df_add(ph, df_mul(df{-nn, 0.0f}, twopi));
                         const float phi = red.hi + red.lo;
                         const float Lf = L.hi;
+                        const float rL = 1.0f / Lf;
                         if (A.kind == 0) {
                             float ps, pc;
                             sincosf(phi, &ps, &pc);
-                            fre += pc / Lf;
-                            fim += ps / Lf;
+                            fre += pc * rL;
+                            fim += ps * rL;
                         } else {
-                            const float xk = kf * Lf;
-                            const float amp = (float)A.ws[e] * 0.5f * kf * zf / Lf * sqrtf(2.0f / (kPiF * xk));
+                            const float amp = (float)A.ws[e] * c_ampf * rL * sqrtf(rL);
                             float ps, pc;
                             sincosf(phi - 0.75f * kPiF, &ps, &pc);
-                            const float ci = 3.0f / (8.0f * xk);
+                            const float ci = c_cif * rL;
                             fre += -amp * (pc * ci + ps);
                             fim += amp * (pc - ps * ci);
                         }
