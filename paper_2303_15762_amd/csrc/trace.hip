@@ -989,8 +989,19 @@ __global__ __launch_bounds__(256) void shadow_merge_kernel(const float* __restri
     bool bad = false;
     if (i < n) {
         const int m = nd[i];
+        const float* vp = val + i * depth;
         float s = 0.0f;
-        for (int d = 0; d < m; ++d) s += val[i * depth + d];
+        if (depth <= 8) {
+            // the stored slots' loads issue together; the sum keeps depth order
+            float v8[8];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) v8[d] = d < m ? vp[d] : 0.0f;
+#pragma unroll
+            for (int d = 0; d < 8; ++d)
+                if (d < m) s += v8[d];
+        } else {
+            for (int d = 0; d < m; ++d) s += vp[d];
+        }
         float v = s * inv_spp_norm;
         if (!isfinite(v)) {
             bad = true;
@@ -1047,6 +1058,8 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ r
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= per) return;
     float acc = 0.0f;
+    // eight samples' loads in flight at a time; the sum keeps sample order
+#pragma unroll 8
     for (int64_t s = 0; s < S; ++s) acc += rec[(size_t)s * per + t];
     const uint32_t w = t % nl;
     const uint32_t pix = t / nl;
