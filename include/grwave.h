@@ -283,8 +283,9 @@ int gr_trace(gr_ctx* ctx, const float* lambda_um, int32_t n_lambda, const gr_tra
  * synchronising; no statistics.
  *   image : device float [n_lambda][height][width], caller-owned; contributions are ADDED.
  * Errors: as gr_trace; GR_E_WORKSPACE when gr_workspace_size for these options exceeds
- * 64 MiB (e.g. a 41 x 29 sensor with 8 wavelengths, 16 samples and depth 4 needs about
- * 33 MB; full-size frames need gr_trace).  Every call on one GPU shares that GPU's array,
+ * 64 MiB (e.g. a 41 x 29 sensor with 8 wavelengths, 16 samples and depth 4 over a
+ * 65,536-triangle terrain needs about 62 MB, half of it the traversal stack's overflow region
+ * for every persistent lane; full-size frames need gr_trace).  Every call on one GPU shares that GPU's array,
  * which keeps the last call's contents: calls that overlap on one GPU (two streams, two
  * contexts, two threads) race and must be serialised by the caller.  The per-path records
  * of GR_TRACE_KEEP_PATHS stay in the array and are not accessible. */
