@@ -553,10 +553,13 @@ int trace_impl(gr_ctx* c, const float* lambda, int32_t nl, const gr_trace_opts* 
                 d.bu[j] = q.eu[j] / lu;
                 d.bv[j] = q.ev[j] / lv;
             }
-            d.lu = lu;
-            d.lv = lv;
+            d.ilu = 1.0f / lu;
+            d.ilv = 1.0f / lv;
+        } else {
+            d.ilu = d.ilv = 0.0f;
         }
         d.rc_um = q.coherence_radius_um;
+        d.irc_um = q.kind == GR_SRC_GSM_AREA ? 1.0f / q.coherence_radius_um : 0.0f;
         d.power = q.power;
     }
     a.nl = nl;

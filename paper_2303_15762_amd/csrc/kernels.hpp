@@ -41,8 +41,9 @@ struct SourceDev {
     float dir[3];     // travel direction / emission axis (unit)
     float pos[3];
     float bu[3], bv[3];   // unit in-plane axes of the emitter
-    float lu, lv;         // half extents (m)
-    float rc_um, power;
+    float ilu, ilv;       // reciprocal half extents (1/m)
+    float rc_um, irc_um;  // coherence radius (um) and its reciprocal
+    float power;
 };
 
 // Trained domain of the learned p_w (the trace kernel encodes queries; a batched

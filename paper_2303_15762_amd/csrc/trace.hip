@@ -624,17 +624,20 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                     } else {
                         float z1, z2;
                         box_muller(unif(rn.y), unif(rn.z), z1, z2);
-                        const float du = z1 / L.rc_um, dv = z2 / L.rc_um;
-                        const float tt = (du * du + dv * dv) / (k * k);
+                        // one division: 1 / k (the emitter's reciprocal radius and extents
+                        // come with it)
+                        const float ik = 1.0f / k;
+                        const float du = z1 * L.irc_um, dv = z2 * L.irc_um;
+                        const float tt = (du * du + dv * dv) * (ik * ik);
                         tt_s = tt;
                         if (tt < 1.0f) {
                             const f3 ax = ld3(L.dir), eu = ld3(L.bu), ev = ld3(L.bv);
-                            om = (du / k) * eu + (dv / k) * ev + sqrtf(1.0f - tt) * ax;
+                            om = (du * ik) * eu + (dv * ik) * ev + sqrtf(1.0f - tt) * ax;
                             const f3 pp = diff_f3(P, ld3(L.pos));   // P - emitter centre
                             const float te = dot3(pp, ax) / dot3(om, ax);
                             if (te > tminP) {
                                 const f3 qp = pp - te * om;           // Q - emitter centre
-                                const float a = dot3(qp, eu) / L.lu, b = dot3(qp, ev) / L.lv;
+                                const float a = dot3(qp, eu) * L.ilu, b = dot3(qp, ev) * L.ilv;
                                 if (fabsf(a) <= 1.0f && fabsf(b) <= 1.0f) {
                                     ok = true;
                                     tmax_s = te;
