@@ -149,19 +149,15 @@ __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, f
     const float det = U + V + W;
     if (det == 0.0f) return false;
     const float T = U * (r.Sz * Az0) + V * (r.Sz * Bz0) + W * (r.Sz * Cz0);
-    const float rcp = 1.0f / det;
+    // hardware reciprocal (1 ulp): the hit found is recomputed in double (refine_hit), and t
+    // only orders this ray's candidates
+    const float rcp = __builtin_amdgcn_rcpf(det);
     t = T * rcp;
     bu = V * rcp;
     bv = W * rcp;
     return true;
 }
 
-// Child code of the slot held in a sorted key's two low bits.
-__device__ __forceinline__ int child_of(int4 ch, uint32_t key) {
-    const int a = (key & 1u) ? ch.y : ch.x;
-    const int b = (key & 1u) ? ch.w : ch.z;
-    return (key & 2u) ? b : a;
-}
 
 // BVH4 traversal.  closest: smallest t in (tmin, tmax), equal t resolved to the lower original
 // triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
