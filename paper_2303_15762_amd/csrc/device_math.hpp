@@ -82,7 +82,7 @@ __device__ __forceinline__ void box_muller(float u1, float u2, float& z1, float&
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ float gauss2(float x, float y, float a, float b, float c) {
     const float det = a * b - c * c;
-    const float q = (b * x * x - 2.0f * c * x * y + a * y * y) / det;
+    const float q = (b * x * x - 2.0f * c * x * y + a * y * y) * __builtin_amdgcn_rcpf(det);
     return __expf(-0.5f * q) * (1.0f / kTwoPiF) * rsqrtf(det);
 }
 
@@ -198,10 +198,12 @@ enum { MAT_SMOOTH = 0, MAT_ROUGH = 1, MAT_GRATING = 2 };
 //   rough  : sum_m Poisson(m; q_z^2 s^2) N(kappa; 0, Sk + 2m/l^2 I)   (ensemble average)
 // with Sk = S_fp^-1 / 4, S_fp the footprint covariance, q_z = k (cos i + cos o).
 // ------------------------------------------------------------------------------------------
+// (Its reciprocals are the hardware's, 1 ulp: they scale the value, and no decision of the path
+// depends on them.)
 __device__ inline float pw_plain(int kind, float h, float L, float refl, float k, float kix,
                                  float kiy, float kox, float koy, float sxx, float syy, float sxy,
                                  float gx, float gy) {
-    const float ik2 = 1.0f / (k * k);
+    const float ik2 = __builtin_amdgcn_rcpf(k * k);
     const float ni = (kix * kix + kiy * kiy) * ik2;
     const float no = (kox * kox + koy * koy) * ik2;
     if (ni >= 1.0f || no >= 1.0f) return 0.0f;
@@ -211,7 +213,7 @@ __device__ inline float pw_plain(int kind, float h, float L, float refl, float k
     // a window thinner than float resolves (its determinant rounds to zero or below: extreme
     // anisotropic footprints after grazing interactions) measures nothing
     if (!(det > 0.0f)) return 0.0f;
-    const float idet = 0.25f / det;
+    const float idet = 0.25f * __builtin_amdgcn_rcpf(det);
     const float a = syy * idet, b = sxx * idet, c = -sxy * idet;
     if (kind == MAT_SMOOTH) return refl * gauss2(kx, ky, a, b, c);
     if (kind == MAT_GRATING) {
@@ -240,7 +242,7 @@ __device__ inline float pw_plain(int kind, float h, float L, float refl, float k
         mlo = max(0, (int)g - 2048);
         mhi = mlo + 4095;
     }
-    const float add = 2.0f / (L * L);
+    const float add = 2.0f * __builtin_amdgcn_rcpf(L * L);
     const float logg = logf(g);
     const float c2 = c * c;
     // Poisson weights by the recurrence P(m + 1) = P(m) g / (m + 1) from the log-space first

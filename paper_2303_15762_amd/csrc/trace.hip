@@ -520,10 +520,13 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
             } else if constexpr (ANISO) {
                 aniso_free(ar, thit * 1e6f / k);
             } else {
-                const float zb = thit * 1e6f / k;
+                // the free-space law with hardware reciprocals (1 ulp): beta and rho only scale
+                // footprints and values
+                const float zb = thit * 1e6f * __builtin_amdgcn_rcpf(k);
                 const float orr = 1.0f + rho * rho;
-                const float rho_n = rho + zb * orr / beta2;
-                beta2 = beta2 + zb * (2.0f * rho + zb * orr / beta2);
+                const float q = zb * orr * __builtin_amdgcn_rcpf(beta2);
+                const float rho_n = rho + q;
+                beta2 = beta2 + zb * (2.0f * rho + q);
                 rho = rho_n;
             }
             const d3 P = d3{o.x + t64 * dd.x, o.y + t64 * dd.y, o.z + t64 * dd.z};
@@ -587,7 +590,7 @@ __global__ __launch_bounds__(256, 4) void trace_kernel(const TraceArgs A) {
                 if constexpr (HERO) b2w = pick4(mb2, hs);
                 const float sr2 = 0.5f * b2w;
                 const float dx = dot3(d, xa), dy = dot3(d, ya);
-                const float ic2 = 1.0f / (ci * ci);
+                const float ic2 = __builtin_amdgcn_rcpf(ci * ci);   // scales the footprint only
                 float sxx = 0.0f, syy = 0.0f, sxy = 0.0f;
                 if constexpr (ANISO) {
                     aniso_footprint(ar, d, ns, xa, ya, sxx, syy, sxy);
