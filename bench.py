@@ -53,8 +53,8 @@ SHADOW_QUEUE_BYTES = 2 * 48 + 2 * 4   # a queued shadow ray written and read, it
 # merge kernels), from rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by a plain copy of known
 # size; valid only for the kernel sources it was measured on (sha256 prefix of the files
 # below).
-TRAFFIC_BYTES = {"mid": 2_897_117 * 1024, "large": 113_168_722 * 1024}
-TRAFFIC_KERNEL_HASH = "93a4a161ac5c3544"
+TRAFFIC_BYTES = {"mid": 2_897_092 * 1024, "large": 113_166_855 * 1024}
+TRAFFIC_KERNEL_HASH = "f380417f462446ac"
 KERNEL_SOURCES = ["paper_2303_15762_amd/csrc/trace.hip", "paper_2303_15762_amd/csrc/trace_core.hpp",
                   "paper_2303_15762_amd/csrc/device_math.hpp",
                   "paper_2303_15762_amd/csrc/kernels.hpp", "paper_2303_15762_amd/csrc/composite.hpp",

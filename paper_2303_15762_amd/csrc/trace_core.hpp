@@ -163,11 +163,10 @@ __device__ __forceinline__ bool tri_isect(const RayT& r, float4 a4, float4 b4, f
 // triangle index; any: stop at the first t in (tmin, tmax).  skip: original index of the
 // triangle the ray leaves (never hit again), or -1.  stk: this lane's LDS stack (stride 64),
 // of which the first cap (<= STACK / 2 - 2) entries are used, each a (child code, entry key)
-// pair; scr: 16 bytes of LDS of this lane (the last two stack entries' space) for a node's
-// child codes while its children are ordered;
-// entry cap + i goes to ovf[i * ostride + lane], ovf being the wave's slice of the overflow
-// region, which the caller sizes for the tree: at most 3 entries per inner node on the current
-// root path.
+// pair; entry cap + i goes to ovf[i * ostride + lane], ovf being the wave's slice of the
+// overflow region, which the caller sizes for the tree: at most 3 entries per inner node on the
+// current root path.  scr: 16 bytes of LDS of this lane (the space of the stack's last two
+// entries) that hold a node's child codes while its children are ordered.
 // Returns the triangle (leaf order) or -1.
 // Traversal loop structure (Aila and Laine, "Understanding the efficiency of ray traversal on
 // GPUs", HPG 2009: while-while with postponed leaves): each lane descends inner nodes until it
@@ -193,8 +192,8 @@ __device__ __forceinline__ int traverse(const SceneDev& S, const RayT& r, float 
     // its children's boxes lie inside its (widened) box and the slab distances are monotonic
     // in the planes, so each child's entry distance is at least the node's and the node test
     // would reject all four.  The stored key is the entry distance's bit pattern with its four
-    // low bits replaced by 4 x slot, hence "beyond" is key > bits(t_best) + 15.  Leaves are always tested
-    // (a triangle's own distance can round below its box's).
+    // low bits replaced by 4 x slot, hence "beyond" is key > bits(t_best) + 15.  Leaves are
+    // always tested (a triangle's own distance can round below its box's).
     auto read_top = [&]() -> v2i_t {
         --sp;
         v2i_t e = stk[min(sp, cap - 1) * 64];
